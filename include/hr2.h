@@ -1,0 +1,320 @@
+/*
+ * hr2.h — C ABI of libhr2, the MI355X (gfx950) emission-spectrum forward model
+ * of Helios-r2 (Kitzmann et al. 2020, arXiv:1910.01070).
+ *
+ * The forward model maps one atmospheric column (one parameter set of the
+ * nested sampler) to the theoretical observation D_m(M, Theta) at the data
+ * bins (Sect. 3.1, the quantity entering Eq. 19).  It runs in three stages,
+ * each a HIP kernel on the device (Sect. 2.8 lists them as the GPU part):
+ *
+ *   1. opacity      chi_l(nu) = sum_s n_s,l sigma_s(nu; T_l, p_l)  + CIA
+ *                   (Sect. 2.3: cross-sections tabulated in (T, p, nu),
+ *                   interpolated to each level; H2-H2 and H2-He CIA)
+ *   2. emission RT  short characteristics with a linear source, alpha = 0
+ *                   (Eq. 4-7), source S = B_nu(T) (Eq. 2), outgoing flux by
+ *                   Gauss quadrature over mu in (0, 1] (Eq. 8)
+ *   3. observation  scaling F = F+ f (R/d)^2 (Eq. 9), Gaussian instrument
+ *                   profile truncated at 5 sigma (Eq. 17), binning to the
+ *                   observational bins (Sect. 2.8)
+ *
+ * Readings of points the paper leaves open (all fixed here and in the
+ * oracle alike):
+ *   - levels are indexed bottom (0, highest p) to top (L-1); layer l joins
+ *     levels l and l+1; the recurrence runs upward, the deeper level is the
+ *     upwind point, Delta = dtau_l / mu >= 0 (Eq. 4, 7);
+ *   - Eq. 4's attenuation is exp(-Delta) (dtau over mu);
+ *   - gamma = (1 - exp(-Delta))/Delta - exp(-Delta) (the linear-source
+ *     upwind coefficient; the printed sign of Eq. 6 makes beta + gamma exceed
+ *     1 - exp(-Delta));
+ *   - lower boundary I+(bottom, mu) = B_nu(T_0) (semi-infinite atmosphere);
+ *   - n_mu-point Gauss-Legendre nodes on mu in [0, 1] (Eq. 8);
+ *   - dtau_l = (chi_l + chi_{l+1})/2 * dz_l with hydrostatic, ideal-gas
+ *     dz_l = k_B Tbar_l / (mubar m_u g) * ln(p_l / p_{l+1}),
+ *     Tbar_l = (T_l + T_{l+1})/2;
+ *   - cross-sections: bilinear in (T, log10 p) on log sigma, clamped to the
+ *     table, lower node i = largest index with axis[i] <= value (capped at
+ *     N-2), weight w = (value - axis[i]) / (axis[i+1] - axis[i]);
+ *   - CIA: n_a n_b k(T, nu), linear in T on log k, same T axis, clamped;
+ *   - H2 and He fill the rest of the gas, x_He = r x_H2 (r = he_h2_ratio);
+ *   - Planck in wavenumber form, 2 h c^2 nu^3 / expm1(h c nu / (k_B T)),
+ *     with the unclamped level temperature;
+ *   - instrument profile: Gaussian of FWHM nu/R evaluated at the output
+ *     point, points with |k| * dnu_eff <= 5 sigma kept, weights renormalised
+ *     over the points of the window;
+ *   - bins: trapezoid mean of the convolved spectrum between edges snapped
+ *     to the nearest window point (ties away from the start), adjacent bins
+ *     share the edge point.
+ *
+ * Units: cgs, wavenumber in cm^-1, pressure in bar, temperature in K.
+ * chi in cm^-1; F+ in erg s^-1 cm^-2 (cm^-1)^-1; bins = f (R/d)^2 times the
+ * bin mean of the convolved F+.
+ *
+ * Precision: device arrays of stage and batch calls hold `hr2_real`
+ * elements: double when the tables were created with HR2_TABLE_F64, float
+ * otherwise.  With F32/F16/BF16 storage the arithmetic is FP32; with F64 it
+ * is FP64.
+ *
+ * Ownership: the caller owns every array it passes.  *_create copies what it
+ * needs; host arrays may be freed on return.  The library owns handles,
+ * resident tables, observation layouts and its scratch.  Stage and batch
+ * calls are asynchronous on `stream` (a hipStream_t passed as void*, NULL =
+ * the null stream); device buffers must stay alive until the stream has
+ * completed them.  Host arrays passed to them may be reused on return.
+ *
+ * Errors: every call returns hr2_status; nothing is thrown across the ABI.
+ * Host-side validation happens before anything is enqueued, so an
+ * HR2_E_INVALID_ARG / HR2_E_OUT_OF_RANGE return leaves every output
+ * untouched.  A failed HIP call returns HR2_E_DEVICE.  hr2_last_error()
+ * gives a thread-local text of the last failure on the calling thread.
+ *
+ * Threading: a context (and the tables / observation layouts made from it)
+ * is used by one thread at a time; hr2_serve_submit and hr2_serve_poll are
+ * thread-safe.
+ */
+#ifndef HR2_H
+#define HR2_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  HR2_OK = 0,
+  HR2_NOT_READY = 1,        /* hr2_serve_poll only: request still pending or running */
+  HR2_E_INVALID_ARG = -1,   /* NULL pointer, NaN/Inf, non-monotone axis, bad count     */
+  HR2_E_OUT_OF_RANGE = -2,  /* window outside the table, n_mu outside [1, 8], too big */
+  HR2_E_NO_MEMORY = -3,     /* device or host allocation failed; request > budget     */
+  HR2_E_DEVICE = -4,        /* a HIP call failed                                       */
+  HR2_E_NOT_FOUND = -5,     /* unknown or already consumed ticket                      */
+  HR2_E_UNSUPPORTED = -6,   /* valid request this build does not implement            */
+  HR2_E_CANCELLED = -7      /* request cancelled by hr2_serve_destroy                  */
+} hr2_status;
+
+typedef enum {
+  HR2_TABLE_F32 = 0,   /* log2-sigma rows minus a per-row offset, float    */
+  HR2_TABLE_F16 = 1,   /* same, IEEE binary16 (one RNE rounding from FP64) */
+  HR2_TABLE_BF16 = 2,  /* same, bfloat16 (RNE to float, then RNE to bf16)  */
+  HR2_TABLE_F64 = 3    /* log2-sigma, no offset, double; FP64 arithmetic   */
+} hr2_table_dtype;
+
+enum {
+  HR2_MAX_SPECIES = 12,
+  HR2_MAX_CIA = 2,
+  HR2_MAX_LEVELS = 1024,
+  HR2_MAX_MU = 8
+};
+
+typedef struct hr2_ctx hr2_ctx;
+typedef struct hr2_tables hr2_tables;
+typedef struct hr2_obs hr2_obs;
+typedef struct hr2_server hr2_server;
+
+/* Create a context on HIP device `hip_device`.  Allocates the angular
+ * quadrature constants and grow-only scratch.  Errors: HR2_E_INVALID_ARG
+ * (out == NULL), HR2_E_DEVICE (no such device). */
+hr2_status hr2_ctx_create(int hip_device, hr2_ctx **out);
+/* Waits for the context's work, frees its scratch.  NULL is a no-op. */
+void hr2_ctx_destroy(hr2_ctx *ctx);
+/* Thread-local text of the last failure on this thread ("" if none). */
+const char *hr2_last_error(void);
+
+/* Launch-shape options (performance only; results do not depend on them
+ * beyond FP32 rounding of the chunk combination, see HR2_OPT_CHUNKS). */
+typedef enum {
+  HR2_OPT_CHUNKS = 0,      /* layer chunks per wavenumber tile: 0 = auto, 1, 2, 4 */
+  HR2_OPT_NU_PER_LANE = 1  /* wavenumbers per lane: 0 = auto, 1, 2               */
+} hr2_option;
+hr2_status hr2_ctx_set_option(hr2_ctx *ctx, hr2_option opt, int value);
+
+/* Cross-section and CIA tables (Sect. 2.3).  All arrays are host FP64.
+ *   T_K[n_T]            strictly increasing, > 0 (non-uniform allowed), n_T >= 2
+ *   log10_p_bar[n_p]    strictly increasing, n_p >= 2
+ *   nu_k = nu0_cm + k * dnu_cm, k < n_nu (cm^-1), dnu_cm > 0, nu0_cm > 0
+ *   log10_sigma         [n_species][n_T][n_p][n_nu], sigma in cm^2/molecule
+ *   molar_mass[n_species]   g/mol (enters the mean molecular weight)
+ *   n_cia               0 or 2 (pair 0 = H2-H2, pair 1 = H2-He)
+ *   log10_k_cia         [n_cia][n_T][n_nu], k in cm^5/molecule^2, same T axis
+ *   he_h2_ratio         x_He / x_H2 of the filler gas, > 0
+ *   dtype               storage in HBM.  For F32/F16/BF16 each row
+ *                       (species, T, p) (and each CIA row) is stored as
+ *                       y = log10_sigma * log2(10) - off_row in the dtype,
+ *                       off_row = (min + max)/2 of that row's
+ *                       log10_sigma * log2(10) values (FP64); F64 keeps
+ *                       log10_sigma * log2(10) with no offset.  CIA rows are
+ *                       float (double for F64) in every case.
+ * Copies everything to the device; host arrays may be freed on return.
+ * Errors: HR2_E_INVALID_ARG (NULL, NaN/Inf, non-monotone axis, counts out of
+ * [1, HR2_MAX_SPECIES], n_cia not 0/2), HR2_E_NO_MEMORY, HR2_E_DEVICE. */
+typedef struct {
+  int n_species, n_T, n_p;
+  const double *T_K;
+  const double *log10_p_bar;
+  double nu0_cm, dnu_cm;
+  int64_t n_nu;
+  const double *log10_sigma;
+  const double *molar_mass;
+  int n_cia;
+  const double *log10_k_cia;
+  double he_h2_ratio;
+  hr2_table_dtype dtype;
+} hr2_tables_desc;
+
+hr2_status hr2_tables_create(hr2_ctx *ctx, const hr2_tables_desc *desc, hr2_tables **out);
+void hr2_tables_destroy(hr2_tables *tables);
+
+/* One atmospheric column = one parameter set (Table 1 parameters after the
+ * temperature profile (Sect. 2.5) and free chemistry (Sect. 5.2) have been
+ * evaluated).
+ *   n_levels   2 <= L <= HR2_MAX_LEVELS; layers = L - 1
+ *   p_bar[L]   strictly decreasing, > 0 (level 0 = bottom)
+ *   T_K[L]     > 0; table lookups clamp to the T axis, Planck uses T as given
+ *   x[n_species]  isoprofile mixing ratios, >= 0, sum < 1 (Sect. 5.2)
+ *   log_g_cgs  log10 of surface gravity in cm s^-2
+ *   scale      f (R/d)^2 (Eq. 9), finite */
+typedef struct {
+  int n_levels;
+  const double *p_bar;
+  const double *T_K;
+  const double *x;
+  double log_g_cgs;
+  double scale;
+} hr2_column;
+
+/* Wavenumber window: table points nu_begin + j * nu_stride, j < nu_count.
+ * Requires nu_begin >= 0, nu_count >= 1, nu_stride >= 1 and
+ * nu_begin + (nu_count - 1) * nu_stride < n_nu (else HR2_E_OUT_OF_RANGE). */
+typedef struct {
+  int64_t nu_begin, nu_count, nu_stride;
+} hr2_window;
+
+/* Stage 1 alone (Sect. 2.3 / 2.8): absorption coefficient at every level.
+ * chi_dev: device hr2_real[L][nu_count], cm^-1.  Enqueued on stream. */
+hr2_status hr2_opacity(hr2_ctx *ctx, const hr2_tables *tables, const hr2_column *col,
+                       hr2_window window, void *chi_dev, void *stream);
+
+/* Stage 2 alone (Eq. 2, 4-8): outgoing top-of-atmosphere flux F+ from a
+ * given absorption coefficient.  chi_dev: device hr2_real[L][nu_count]
+ * (e.g. from hr2_opacity); fplus_dev: device hr2_real[nu_count];
+ * 1 <= n_mu <= HR2_MAX_MU.  The column supplies T (Planck), p, x, log g
+ * (layer thicknesses).  Enqueued on stream. */
+hr2_status hr2_rt_emission(hr2_ctx *ctx, const hr2_tables *tables, const hr2_column *col,
+                           hr2_window window, const void *chi_dev, int n_mu,
+                           void *fplus_dev, void *stream);
+
+/* Observation layout (Eq. 17 and the binning of Sect. 2.8): resolving power
+ * R > 0 (sigma(nu) = nu / (R 2 sqrt(2 ln 2))), n_bins >= 1 bins with
+ * increasing edges bin_edges_cm[n_bins + 1], each snapped to the nearest
+ * window point; snapped edges must be strictly increasing.  The convolution
+ * and binning are linear, so the layout is held as one banded weight row per
+ * bin (the composite of trapezoid weights and renormalised Gaussians), built
+ * on the device.  Blocks until built.  Errors: HR2_E_INVALID_ARG,
+ * HR2_E_OUT_OF_RANGE (window, or a snapped edge outside it), HR2_E_NO_MEMORY. */
+hr2_status hr2_obs_create(hr2_ctx *ctx, const hr2_tables *tables, hr2_window window,
+                          double resolving_power, int n_bins, const double *bin_edges_cm,
+                          hr2_obs **out);
+void hr2_obs_destroy(hr2_obs *obs);
+/* Number of bins of a layout (0 for NULL). */
+int hr2_obs_n_bins(const hr2_obs *obs);
+
+/* Stage 3 alone (Eq. 9, 17, binning): bins_dev[n_bins] = scale * binned,
+ * convolved fplus_dev[nu_count].  Device hr2_real arrays; enqueued. */
+hr2_status hr2_convolve_bin(hr2_ctx *ctx, const hr2_obs *obs, const void *fplus_dev,
+                            double scale, void *bins_dev, void *stream);
+
+/* The whole forward model for n_sets columns that share n_levels (host
+ * columns, validated on the host, staged to the device).  bins_dev: device
+ * hr2_real[n_sets][n_bins].  fplus_dev: NULL, or device
+ * hr2_real[n_sets][nu_count] that receives the unscaled F+ of each set.
+ * Each set's result does not depend on the other sets of the call. */
+hr2_status hr2_forward_batch(hr2_ctx *ctx, const hr2_tables *tables, const hr2_obs *obs,
+                             int n_sets, const hr2_column *cols, int n_mu,
+                             void *bins_dev, void *fplus_dev, void *stream);
+
+/* Same, with the columns already resident in device memory (FP64):
+ *   p_dev[n_sets][n_levels], T_dev[n_sets][n_levels],
+ *   x_dev[n_sets][n_species], log_g_dev[n_sets], scale_dev[n_sets].
+ * Nothing is validated on the host (that would need a device read); the
+ * level kernel checks every set and writes its status to set_status_dev
+ * (device int[n_sets], may be NULL): 0 = valid, HR2_E_INVALID_ARG otherwise.
+ * An invalid set's bins and F+ are NaN; other sets are unaffected. */
+hr2_status hr2_forward_batch_dev(hr2_ctx *ctx, const hr2_tables *tables, const hr2_obs *obs,
+                                 int n_sets, int n_levels, const double *p_dev,
+                                 const double *T_dev, const double *x_dev,
+                                 const double *log_g_dev, const double *scale_dev, int n_mu,
+                                 void *bins_dev, void *fplus_dev, int *set_status_dev,
+                                 void *stream);
+
+/* ---- serving: continuous batching of uneven forward-model requests ----
+ * A scheduler thread owns one stream.  Requests (each n_sets columns sharing
+ * n_levels, its own window, resolving power and bins) are admitted while
+ * their device footprint fits the budget and a slot is free; every step
+ * launches the opacity+RT work of all admitted, not yet launched requests as
+ * one launch, then their convolution/binning, then copies bins to pinned
+ * host memory.  Requests arriving meanwhile join the next step.  Per-set
+ * arithmetic does not depend on the other requests in a step, so a result is
+ * bit-identical alone and in the mix. */
+typedef struct {
+  hr2_window window;
+  double resolving_power;
+  int n_bins;
+  const double *bin_edges_cm;   /* [n_bins + 1] */
+  int n_sets;
+  const hr2_column *cols;       /* [n_sets], all with the same n_levels */
+  int n_mu;
+} hr2_request;
+
+typedef enum {
+  HR2_REQ_PENDING = 0, HR2_REQ_RUNNING = 1, HR2_REQ_DONE = 2,
+  HR2_REQ_ERROR = 3, HR2_REQ_CANCELLED = 4
+} hr2_request_state;
+
+typedef struct {
+  int state;                 /* hr2_request_state */
+  double t_submit, t_admit, t_done;   /* seconds, CLOCK_MONOTONIC */
+  hr2_status error;          /* why a request ended in ERROR / CANCELLED */
+  int n_bins, n_sets;
+} hr2_request_info;
+
+/* hbm_budget_bytes: cap on the device bytes held by admitted requests
+ * (level records, F+, layouts, bins); max_slots: cap on admitted requests.
+ * Errors: HR2_E_INVALID_ARG, HR2_E_DEVICE. */
+hr2_status hr2_serve_create(hr2_ctx *ctx, const hr2_tables *tables, size_t hbm_budget_bytes,
+                            int max_slots, hr2_server **out);
+/* Non-blocking.  Validates and deep-copies the request, returns a ticket.
+ * Errors: HR2_E_INVALID_ARG / HR2_E_OUT_OF_RANGE (validation),
+ * HR2_E_NO_MEMORY (the request alone exceeds the budget). */
+hr2_status hr2_serve_submit(hr2_server *srv, const hr2_request *req, uint64_t *ticket);
+/* HR2_NOT_READY while pending/running.  When done, copies n_sets * n_bins
+ * results (float; double for F64 tables) to bins_host if capacity allows
+ * (else HR2_E_INVALID_ARG, ticket kept), releases the ticket and returns
+ * HR2_OK.  A request that failed returns its error and is released.
+ * info may be NULL.  Unknown / released ticket: HR2_E_NOT_FOUND. */
+hr2_status hr2_serve_poll(hr2_server *srv, uint64_t ticket, void *bins_host,
+                          size_t capacity_elems, hr2_request_info *info);
+/* Blocks until ticket completes (or timeout_s elapses: HR2_NOT_READY), then
+ * behaves as hr2_serve_poll. */
+hr2_status hr2_serve_wait(hr2_server *srv, uint64_t ticket, double timeout_s, void *bins_host,
+                          size_t capacity_elems, hr2_request_info *info);
+/* Cancels pending requests (state CANCELLED), waits for launched ones,
+ * joins the scheduler and frees everything. */
+void hr2_serve_destroy(hr2_server *srv);
+
+/* Test hook: the next scheduler step is treated as a failed launch, which
+ * marks exactly that step's requests ERROR (HR2_E_DEVICE); later steps run
+ * normally.  Nothing is enqueued for the failed step. */
+hr2_status hr2_serve_debug_fail_next_step(hr2_server *srv);
+
+/* Counters of a server: steps launched, requests done, peak admitted bytes. */
+typedef struct {
+  uint64_t steps, requests_done, requests_failed, max_inflight;
+  size_t peak_bytes;
+} hr2_serve_stats;
+hr2_status hr2_serve_get_stats(hr2_server *srv, hr2_serve_stats *out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HR2_H */
