@@ -1,0 +1,222 @@
+"""Benchmark of the Helios-r2 emission forward model on one MI355X.
+
+One step = one pass of the whole forward model over one batch of synthetic
+columns already resident in HBM: level records, the fused opacity + RT
+column kernel, the convolve/bin kernel (hr2_forward_batch_dev).
+
+Default workload: a single realistic forward model at FP32 (8 absorbers +
+H2-H2/H2-He CIA, 27 T x 19 log p table, 150,000 wavenumbers at 0.1 cm^-1,
+100 layers, 3 angles, R = 300, 400 bins).  Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "forward spectra/s and layer·ν points/s + p50/p99 latency vs plain FP32 at ≤1e-3"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def axis_cell(axis, v):
+    """Table cell of the forward model's lookup rule (lower node = largest
+    index with axis[i] <= v, clamped, capped at n-2) and the upper weight."""
+    v = np.clip(v, axis[0], axis[-1])
+    i = np.searchsorted(axis, v, side="right") - 1
+    i = np.minimum(i, len(axis) - 2)
+    w = (v - axis[i]) / (axis[i + 1] - axis[i])
+    return i, w
+
+
+def algorithmic_bytes(tab, cols, elem_bytes, n_nu, n_bins):
+    """Bytes the column kernel must move: every distinct table row (T node,
+    p node) with nonzero weight in any level of any set, per species, at
+    elem_bytes per entry, plus the distinct CIA rows (FP32) and the F+ write."""
+    rows, cia_rows = set(), set()
+    for c in cols:
+        iT, wT = axis_cell(tab.T_K, c.T_K)
+        ip, wp = axis_cell(tab.log10_p_bar, np.log10(c.p_bar))
+        for a in (0, 1):
+            for b in (0, 1):
+                w = (wT if a else 1 - wT) * (wp if b else 1 - wp)
+                for k in np.nonzero(w)[0]:
+                    rows.add((int(iT[k] + a), int(ip[k] + b)))
+            wt = wT if a else 1 - wT
+            for k in np.nonzero(wt)[0]:
+                cia_rows.add(int(iT[k] + a))
+    S = tab.n_species
+    table = S * len(rows) * n_nu * elem_bytes
+    cia = tab.n_cia * len(cia_rows) * n_nu * 4
+    out = len(cols) * n_nu * 4
+    return table + cia + out, len(rows), len(cia_rows)
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    with open(os.path.join(ROOT, "paper_1910_01070_amd", "csrc", "kernels.hip"), "rb") as f:
+        h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profile(kernel_hash):
+    """HBM bytes per launch of the column kernel from committed rocprofv3
+    counter runs, if they were taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", "column_kernel_c2_f32_counters.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        d = json.load(f)
+    if d.get("kernel_source_sha256_16") != kernel_hash:
+        return None
+    return d.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(tab, col, spec, n_mu, budget_s=20.0):
+    """The FP64 oracle on the host cores: whole spectra of the same workload,
+    repeated until about budget_s seconds have passed (at least one)."""
+    import oracle
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    n = 0
+    t0 = time.perf_counter()
+    while True:
+        oracle.forward(tab, col, spec.window, spec.resolving_power, spec.edges_cm, n_mu)
+        n += 1
+        el = time.perf_counter() - t0
+        if el >= budget_s or el / n * (n + 1) > 1.5 * budget_s:
+            break
+    return {"value": n / el, "unit": "spectra/s", "cores": threads, "kind": "oracle",
+            "sample": f"{n} whole spectra of the same workload (all stages, FP64), {el:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--dtype", default="f32", choices=["f32", "f16", "bf16"])
+    ap.add_argument("--batch", type=int, default=1)
+    ap.add_argument("--n-nu", type=int, default=150_000)
+    ap.add_argument("--chunks", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-budget-s", type=float, default=20.0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
+        sys.exit(2)
+
+    import torch
+    import workloads as wl
+    from paper_1910_01070_amd import hr2
+
+    assert torch.cuda.is_available(), "bench needs a HIP device"
+    log("generating tables")
+    t0 = time.perf_counter()
+    tab = wl.c2_table(n_nu=args.n_nu)
+    log(f"  {time.perf_counter() - t0:.1f} s")
+    spec = wl.c2_obs(tab)
+    cols = [wl.c2_column()] if args.batch == 1 else wl.c4_columns(args.batch)
+    B, L = len(cols), cols[0].n_levels
+    n_mu = 3
+
+    ctx = hr2.Context(0)
+    ctx.set_option(hr2.OPT_CHUNKS, args.chunks)
+    T = hr2.Tables(ctx, tab, args.dtype)
+    obs = hr2.Obs(ctx, T, spec.window, spec.resolving_power, spec.edges_cm)
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+    p = dev(np.stack([c.p_bar for c in cols]))
+    Tk = dev(np.stack([c.T_K for c in cols]))
+    x = dev(np.stack([c.x for c in cols]))
+    lg = dev([c.log_g for c in cols])
+    sc = dev([c.scale for c in cols])
+    bins = torch.empty(B * obs.n_bins, dtype=torch.float32, device="cuda")
+    fplus = torch.empty(B * spec.window.count, dtype=torch.float32, device="cuda")
+    stream = torch.cuda.current_stream()
+
+    def step():
+        hr2.forward_batch_dev(ctx, T, obs, p, Tk, x, lg, sc, n_mu, bins, fplus, None, stream)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+
+    # timed region: K steps, per-step events for latency, kernel events inside
+    ctx.set_option(hr2.OPT_TIMING, 1)
+    ctx.collect_timing()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev[0].record(stream)
+    for k in range(args.steps):
+        step()
+        ev[k + 1].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ctx.set_option(hr2.OPT_TIMING, 0)
+    (ms_lev, ms_col, ms_conv), n_timed = ctx.collect_timing()
+    lat = np.array([ev[k].elapsed_time(ev[k + 1]) for k in range(args.steps)])
+
+    spectra_s = B * args.steps / wall
+    layer_nu = (L - 1) * spec.window.count
+    elem = {"f32": 4, "f16": 2, "bf16": 2}[args.dtype]
+    alg_bytes, U, U_cia = algorithmic_bytes(tab, cols, elem, spec.window.count, obs.n_bins)
+    col_ms = ms_col / max(n_timed, 1)
+    achieved = alg_bytes / (col_ms * 1e-3) / 1e9
+    khash = kernel_source_hash()
+    traffic = traffic_from_profile(khash)
+
+    res = {
+        "metric": METRIC,
+        "value": spectra_s,
+        "unit": "spectra/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if args.dtype == "f32" else f"f32 ({args.dtype} tables)",
+        "data": "synthetic",
+        "config": {
+            "workload": ("single realistic forward model: 8 absorbers + H2-H2/H2-He CIA, "
+                         "27 T x 19 log p table, 150k wavenumbers at 0.1 cm^-1, 100 layers, "
+                         "6-knot T(p), 3 angles, R=300, 400 bins" if args.n_nu == 150_000 and B == 1
+                         else f"C2-like batch of {B}, {args.n_nu} wavenumbers"),
+            "sets_per_step": B, "layers": L - 1, "wavenumbers": spec.window.count,
+            "species": tab.n_species, "cia_pairs": tab.n_cia, "n_mu": n_mu,
+            "resolving_power": spec.resolving_power, "bins": obs.n_bins,
+            "table_storage": args.dtype, "chunks": args.chunks,
+        },
+        "layer_nu_points_per_s": spectra_s * layer_nu,
+        "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
+                       "kind": "per step, HIP events on the launch stream"},
+        "kernel_ms": {"levels": ms_lev / max(n_timed, 1), "column": col_ms,
+                      "convolve_bin": ms_conv / max(n_timed, 1), "calls": n_timed},
+        "roofline": {
+            "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+            "kernel": "k_column (fused opacity + short characteristics)",
+            "algorithmic_bytes_per_launch": alg_bytes, "distinct_rows_per_species": U,
+            "distinct_cia_rows": U_cia, "kernel_source": khash,
+        },
+    }
+    if not args.no_cpu_baseline:
+        log("timing the oracle on the host")
+        res["cpu_baseline"] = cpu_baseline(tab, cols[0], spec, n_mu, args.cpu_budget_s)
+    print(json.dumps(res))
+
+
+if __name__ == "__main__":
+    main()

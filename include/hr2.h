@@ -125,9 +125,18 @@ const char *hr2_last_error(void);
  * beyond FP32 rounding of the chunk combination, see HR2_OPT_CHUNKS). */
 typedef enum {
   HR2_OPT_CHUNKS = 0,      /* layer chunks per wavenumber tile: 0 = auto, 1, 2, 4 */
-  HR2_OPT_NU_PER_LANE = 1  /* wavenumbers per lane: 0 = auto, 1, 2               */
+  HR2_OPT_NU_PER_LANE = 1, /* wavenumbers per lane: 0 = auto, 1 (only 1 is built) */
+  HR2_OPT_TIMING = 2       /* 1: bracket each forward-batch kernel with HIP events */
 } hr2_option;
 hr2_status hr2_ctx_set_option(hr2_ctx *ctx, hr2_option opt, int value);
+
+/* Kernel timing of the forward-batch calls made while HR2_OPT_TIMING was on
+ * (measured with HIP events on the caller's stream, bracketing each launch):
+ * waits for those calls, writes the summed milliseconds of the level kernel,
+ * the opacity+RT column kernel and the convolve/bin kernel to ms[0..2] and
+ * the number of calls to *n_calls, then resets.  At most 65536 calls are
+ * recorded between collections (later ones are not timed). */
+hr2_status hr2_ctx_collect_timing(hr2_ctx *ctx, double ms[3], int64_t *n_calls);
 
 /* Cross-section and CIA tables (Sect. 2.3).  All arrays are host FP64.
  *   T_K[n_T]            strictly increasing, > 0 (non-uniform allowed), n_T >= 2

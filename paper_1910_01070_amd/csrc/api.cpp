@@ -1,0 +1,909 @@
+// api.cpp — host side of libhr2: contexts, resident tables, observation
+// layouts, validation, staging and the launch sequence of the forward model
+// (level records -> fused opacity/RT column kernel -> convolve/bin kernel).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "hr2_context.h"
+#include "hr2_internal.h"
+
+using namespace hr2;
+
+// ------------------------------------------------------------------ errors
+namespace hr2 {
+thread_local std::string g_last_error;
+
+hr2_status set_error(hr2_status st, const std::string &msg) {
+  g_last_error = msg;
+  return st;
+}
+
+hr2_status hip_error(hipError_t e, const char *what) {
+  return set_error(HR2_E_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+}  // namespace hr2
+
+#define HIP_TRY(expr)                                    \
+  do {                                                   \
+    hipError_t e_ = (expr);                              \
+    if (e_ != hipSuccess) return hip_error(e_, #expr);   \
+  } while (0)
+
+extern "C" const char *hr2_last_error(void) { return g_last_error.c_str(); }
+
+// ------------------------------------------------------------ device buffers
+namespace hr2 {
+
+hr2_status DevBuf::ensure(size_t bytes) {
+  if (bytes <= cap) return HR2_OK;
+  if (ptr != nullptr) {
+    // the old buffer may still be read by enqueued work of this context
+    HIP_TRY(hipDeviceSynchronize());
+    HIP_TRY(hipFree(ptr));
+    ptr = nullptr;
+    cap = 0;
+  }
+  size_t want = std::max<size_t>(bytes, 4096);
+  want = (want + 255) & ~size_t(255);
+  if (hipMalloc(&ptr, want) != hipSuccess) {
+    ptr = nullptr;
+    (void)hipGetLastError();
+    return set_error(HR2_E_NO_MEMORY, "device allocation of " + std::to_string(want) + " bytes failed");
+  }
+  cap = want;
+  return HR2_OK;
+}
+
+void DevBuf::release() {
+  if (ptr) (void)hipFree(ptr);
+  ptr = nullptr;
+  cap = 0;
+}
+
+// Gauss-Legendre nodes on [0, 1] (Eq. 8): roots of P_n by Newton's method.
+static void gauss_legendre_01(int n, double *mu, double *w) {
+  const double pi = 3.14159265358979323846;
+  for (int i = 0; i < n; ++i) {
+    double z = std::cos(pi * (i + 0.75) / (n + 0.5));
+    double dpn = 1.0;
+    for (int it = 0; it < 200; ++it) {
+      double pa = 1.0, pb = 0.0;
+      for (int k = 1; k <= n; ++k) {
+        const double pc = pb;
+        pb = pa;
+        pa = ((2.0 * k - 1.0) * z * pb - (k - 1.0) * pc) / k;
+      }
+      dpn = n * (z * pa - pb) / (z * z - 1.0);
+      const double step = pa / dpn;
+      z -= step;
+      if (std::fabs(step) <= 1e-16) {
+        double qa = 1.0, qb = 0.0;
+        for (int k = 1; k <= n; ++k) {
+          const double qc = qb;
+          qb = qa;
+          qa = ((2.0 * k - 1.0) * z * qb - (k - 1.0) * qc) / k;
+        }
+        dpn = n * (z * qa - qb) / (z * z - 1.0);
+        break;
+      }
+    }
+    mu[n - 1 - i] = 0.5 * (1.0 + z);
+    w[n - 1 - i] = 1.0 / ((1.0 - z * z) * dpn * dpn);
+  }
+}
+
+static AngleTable make_angle_table() {
+  AngleTable t;
+  std::memset(&t, 0, sizeof(t));
+  const double pi = 3.14159265358979323846;
+  const double log2e = 1.4426950408889634074;
+  for (int n = 1; n <= kMaxMu; ++n) {
+    double mu[kMaxMu], w[kMaxMu];
+    gauss_legendre_01(n, mu, w);
+    for (int k = 0; k < n; ++k) {
+      t.mu[n - 1][k] = (float)mu[k];
+      t.inv_mu[n - 1][k] = (float)(1.0 / mu[k]);
+      t.l2e_mu[n - 1][k] = (float)(log2e / mu[k]);
+      t.cw[n - 1][k] = (float)(2.0 * pi * w[k] * mu[k]);
+      t.mu_d[n - 1][k] = mu[k];
+      t.inv_mu_d[n - 1][k] = 1.0 / mu[k];
+      t.cw_d[n - 1][k] = 2.0 * pi * w[k] * mu[k];
+    }
+  }
+  return t;
+}
+
+// Make `stream` wait for the context's previous use of its scratch, so
+// scratch reuse is ordered even when calls alternate streams.
+hr2_status ctx_begin(hr2_ctx *ctx, hipStream_t stream) {
+  HIP_TRY(hipSetDevice(ctx->device));
+  if (ctx->scratch_used) HIP_TRY(hipStreamWaitEvent(stream, ctx->scratch_event, 0));
+  return HR2_OK;
+}
+
+hr2_status ctx_end(hr2_ctx *ctx, hipStream_t stream) {
+  HIP_TRY(hipEventRecord(ctx->scratch_event, stream));
+  ctx->scratch_used = true;
+  return HR2_OK;
+}
+
+// Copy `bytes` host bytes to device scratch `dst` through pinned staging.
+hr2_status stage_upload(hr2_ctx *ctx, DevBuf &dst, const void *src, size_t bytes,
+                        hipStream_t stream) {
+  if (bytes == 0) return HR2_OK;
+  hr2_status st = dst.ensure(bytes);
+  if (st != HR2_OK) return st;
+  if (ctx->pinned_pending) {
+    HIP_TRY(hipEventSynchronize(ctx->pinned_event));
+    ctx->pinned_pending = false;
+  }
+  if (ctx->pinned_cap < bytes) {
+    if (ctx->pinned) HIP_TRY(hipHostFree(ctx->pinned));
+    ctx->pinned = nullptr;
+    size_t want = std::max<size_t>(bytes, 1 << 16);
+    HIP_TRY(hipHostMalloc(&ctx->pinned, want, hipHostMallocDefault));
+    ctx->pinned_cap = want;
+  }
+  std::memcpy(ctx->pinned, src, bytes);
+  HIP_TRY(hipMemcpyAsync(dst.ptr, ctx->pinned, bytes, hipMemcpyHostToDevice, stream));
+  HIP_TRY(hipEventRecord(ctx->pinned_event, stream));
+  ctx->pinned_pending = true;
+  return HR2_OK;
+}
+
+// Upload descriptors unless the device copy already holds the same bytes.
+hr2_status upload_cached(hr2_ctx *ctx, DevBuf &dst, std::vector<unsigned char> &shadow,
+                         const void *src, size_t bytes, hipStream_t stream) {
+  if (shadow.size() == bytes && dst.ptr != nullptr && std::memcmp(shadow.data(), src, bytes) == 0)
+    return HR2_OK;
+  hr2_status st = stage_upload(ctx, dst, src, bytes, stream);
+  if (st != HR2_OK) {
+    shadow.clear();
+    return st;
+  }
+  shadow.assign((const unsigned char *)src, (const unsigned char *)src + bytes);
+  return HR2_OK;
+}
+
+}  // namespace hr2
+
+// ----------------------------------------------------------------- context
+extern "C" hr2_status hr2_ctx_create(int hip_device, hr2_ctx **out) {
+  if (out == nullptr) return set_error(HR2_E_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  int n_dev = 0;
+  if (hipGetDeviceCount(&n_dev) != hipSuccess || hip_device < 0 || hip_device >= n_dev) {
+    (void)hipGetLastError();
+    return set_error(HR2_E_DEVICE, "no HIP device " + std::to_string(hip_device));
+  }
+  HIP_TRY(hipSetDevice(hip_device));
+  auto *ctx = new hr2_ctx();
+  ctx->device = hip_device;
+  hipError_t e = hipStreamCreateWithFlags(&ctx->internal, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&ctx->scratch_event, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&ctx->pinned_event, hipEventDisableTiming);
+  if (e == hipSuccess) e = upload_angle_table(make_angle_table());
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  if (e != hipSuccess) {
+    hr2_ctx_destroy(ctx);
+    return hip_error(e, "context setup");
+  }
+  *out = ctx;
+  return HR2_OK;
+}
+
+extern "C" void hr2_ctx_destroy(hr2_ctx *ctx) {
+  if (ctx == nullptr) return;
+  (void)hipSetDevice(ctx->device);
+  (void)hipDeviceSynchronize();
+  ctx->recs.release();
+  ctx->fplus.release();
+  ctx->cols.release();
+  ctx->segs.release();
+  ctx->convsegs.release();
+  if (ctx->pinned) (void)hipHostFree(ctx->pinned);
+  for (hipEvent_t ev : ctx->tev) (void)hipEventDestroy(ev);
+  if (ctx->scratch_event) (void)hipEventDestroy(ctx->scratch_event);
+  if (ctx->pinned_event) (void)hipEventDestroy(ctx->pinned_event);
+  if (ctx->internal) (void)hipStreamDestroy(ctx->internal);
+  delete ctx;
+}
+
+extern "C" hr2_status hr2_ctx_set_option(hr2_ctx *ctx, hr2_option opt, int value) {
+  if (ctx == nullptr) return set_error(HR2_E_INVALID_ARG, "ctx is NULL");
+  switch (opt) {
+    case HR2_OPT_CHUNKS:
+      if (value != 0 && value != 1 && value != 2 && value != 4)
+        return set_error(HR2_E_INVALID_ARG, "chunks must be 0, 1, 2 or 4");
+      ctx->opt_chunks = value;
+      return HR2_OK;
+    case HR2_OPT_NU_PER_LANE:
+      if (value != 0 && value != 1)
+        return set_error(HR2_E_UNSUPPORTED, "only one wavenumber per lane is built");
+      return HR2_OK;
+    case HR2_OPT_TIMING:
+      ctx->timing = value != 0;
+      return HR2_OK;
+  }
+  return set_error(HR2_E_INVALID_ARG, "unknown option");
+}
+
+// ------------------------------------------------------------------ tables
+namespace {
+
+constexpr double kLog2of10 = 3.32192809488736234787031942948939017586;
+
+bool finite_increasing(const double *a, int n) {
+  for (int i = 0; i < n; ++i) {
+    if (!std::isfinite(a[i])) return false;
+    if (i > 0 && !(a[i] > a[i - 1])) return false;
+  }
+  return true;
+}
+
+inline uint16_t to_bf16(double y) {
+  const float f = (float)y;   // first rounding: RNE to float
+  uint32_t u;
+  std::memcpy(&u, &f, 4);
+  u += 0x7FFFu + ((u >> 16) & 1u);   // second rounding: RNE to bfloat16
+  return (uint16_t)(u >> 16);
+}
+
+// Convert rows of log10 values to stored log2 values minus the row offset
+// (midpoint of the row's log2 range); returns false on a non-finite input.
+template <typename TT>
+bool convert_rows(const double *src, int64_t n_rows, int64_t n_nu, int64_t pitch, bool offset,
+                  TT *dst, double *off) {
+  bool ok = true;
+  const int n_thr = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+  std::vector<std::thread> pool;
+  std::vector<char> row_ok(n_thr, 1);
+  for (int t = 0; t < n_thr; ++t) {
+    pool.emplace_back([=, &row_ok]() {
+      for (int64_t r = t; r < n_rows; r += n_thr) {
+        const double *a = src + r * n_nu;
+        double lo = INFINITY, hi = -INFINITY;
+        for (int64_t k = 0; k < n_nu; ++k) {
+          const double y = a[k] * kLog2of10;
+          if (!std::isfinite(y)) row_ok[t] = 0;
+          lo = std::min(lo, y);
+          hi = std::max(hi, y);
+        }
+        const double o = offset ? 0.5 * (lo + hi) : 0.0;
+        off[r] = o;
+        TT *d = dst + r * pitch;
+        for (int64_t k = 0; k < n_nu; ++k) {
+          const double y = a[k] * kLog2of10 - o;
+          if constexpr (std::is_same<TT, uint16_t>::value)
+            d[k] = to_bf16(y);
+          else
+            d[k] = (TT)y;
+        }
+        for (int64_t k = n_nu; k < pitch; ++k) d[k] = (TT)0;
+      }
+    });
+  }
+  for (auto &th : pool) th.join();
+  for (char c : row_ok) ok = ok && c;
+  return ok;
+}
+
+template <typename TT>
+hr2_status upload_table(const double *src, int64_t n_rows, int64_t n_nu, int64_t pitch,
+                        bool offset, void **dptr, double *off, size_t *bytes_out) {
+  const size_t bytes = (size_t)n_rows * pitch * sizeof(TT);
+  if (hipMalloc(dptr, bytes) != hipSuccess) {
+    *dptr = nullptr;
+    (void)hipGetLastError();
+    return set_error(HR2_E_NO_MEMORY, "table allocation failed");
+  }
+  *bytes_out += bytes;
+  // convert and copy in blocks of rows to bound host memory
+  const int64_t rows_per_block = std::max<int64_t>(1, (int64_t)((256u << 20) / (pitch * sizeof(TT))));
+  std::vector<TT> buf;
+  for (int64_t r0 = 0; r0 < n_rows; r0 += rows_per_block) {
+    const int64_t nr = std::min(rows_per_block, n_rows - r0);
+    buf.resize((size_t)nr * pitch);
+    if (!convert_rows<TT>(src + r0 * n_nu, nr, n_nu, pitch, offset, buf.data(), off + r0))
+      return set_error(HR2_E_INVALID_ARG, "table holds a non-finite value");
+    HIP_TRY(hipMemcpy((TT *)*dptr + r0 * pitch, buf.data(), (size_t)nr * pitch * sizeof(TT),
+                      hipMemcpyHostToDevice));
+  }
+  return HR2_OK;
+}
+
+}  // namespace
+
+extern "C" hr2_status hr2_tables_create(hr2_ctx *ctx, const hr2_tables_desc *d, hr2_tables **out) {
+  if (ctx == nullptr || d == nullptr || out == nullptr)
+    return set_error(HR2_E_INVALID_ARG, "NULL argument");
+  *out = nullptr;
+  if (d->n_species < 1 || d->n_species > HR2_MAX_SPECIES)
+    return set_error(HR2_E_INVALID_ARG, "n_species must be in [1, 12]");
+  if (d->n_T < 2 || d->n_p < 2 || d->n_T > 4096 || d->n_p > 4096)
+    return set_error(HR2_E_INVALID_ARG, "n_T and n_p must be in [2, 4096]");
+  if (d->n_nu < 1 || d->n_nu > (int64_t(1) << 31) - 4096)
+    return set_error(HR2_E_INVALID_ARG, "n_nu out of range");
+  if (!d->T_K || !d->log10_p_bar || !d->log10_sigma || !d->molar_mass)
+    return set_error(HR2_E_INVALID_ARG, "NULL table array");
+  if (d->n_cia != 0 && d->n_cia != 2) return set_error(HR2_E_INVALID_ARG, "n_cia must be 0 or 2");
+  if (d->n_cia == 2 && !d->log10_k_cia) return set_error(HR2_E_INVALID_ARG, "NULL CIA table");
+  if (!finite_increasing(d->T_K, d->n_T) || !(d->T_K[0] > 0))
+    return set_error(HR2_E_INVALID_ARG, "T axis must be positive and strictly increasing");
+  if (!finite_increasing(d->log10_p_bar, d->n_p))
+    return set_error(HR2_E_INVALID_ARG, "log10 p axis must be strictly increasing");
+  if (!(d->nu0_cm > 0) || !(d->dnu_cm > 0) || !std::isfinite(d->nu0_cm) || !std::isfinite(d->dnu_cm))
+    return set_error(HR2_E_INVALID_ARG, "nu0 and dnu must be positive");
+  if (!(d->he_h2_ratio > 0) || !std::isfinite(d->he_h2_ratio))
+    return set_error(HR2_E_INVALID_ARG, "he_h2_ratio must be positive");
+  for (int s = 0; s < d->n_species; ++s)
+    if (!(d->molar_mass[s] > 0) || !std::isfinite(d->molar_mass[s]))
+      return set_error(HR2_E_INVALID_ARG, "molar masses must be positive");
+  if (d->dtype < HR2_TABLE_F32 || d->dtype > HR2_TABLE_F64)
+    return set_error(HR2_E_INVALID_ARG, "unknown table dtype");
+
+  HIP_TRY(hipSetDevice(ctx->device));
+  auto *t = new hr2_tables();
+  t->ctx = ctx;
+  const int S = d->n_species, nT = d->n_T, nP = d->n_p, nc = d->n_cia;
+  const int64_t n_nu = d->n_nu, pitch = (n_nu + 63) / 64 * 64;
+  t->T_axis.assign(d->T_K, d->T_K + nT);
+  t->lp_axis.assign(d->log10_p_bar, d->log10_p_bar + nP);
+  t->mass.assign(d->molar_mass, d->molar_mass + S);
+  t->off.assign((size_t)S * nT * nP, 0.0);
+  t->off_cia.assign((size_t)std::max(nc, 1) * nT, 0.0);
+  const bool f64 = d->dtype == HR2_TABLE_F64;
+  const int64_t rows = (int64_t)S * nT * nP;
+  hr2_status st;
+  switch (d->dtype) {
+    case HR2_TABLE_F64:
+      st = upload_table<double>(d->log10_sigma, rows, n_nu, pitch, false, &t->d_tab,
+                                t->off.data(), &t->bytes);
+      break;
+    case HR2_TABLE_F16:
+      st = upload_table<_Float16>(d->log10_sigma, rows, n_nu, pitch, true, &t->d_tab,
+                                  t->off.data(), &t->bytes);
+      break;
+    case HR2_TABLE_BF16:
+      st = upload_table<uint16_t>(d->log10_sigma, rows, n_nu, pitch, true, &t->d_tab,
+                                  t->off.data(), &t->bytes);
+      break;
+    default:
+      st = upload_table<float>(d->log10_sigma, rows, n_nu, pitch, true, &t->d_tab, t->off.data(),
+                               &t->bytes);
+  }
+  if (st == HR2_OK && nc > 0) {
+    if (f64)
+      st = upload_table<double>(d->log10_k_cia, (int64_t)nc * nT, n_nu, pitch, false, &t->d_cia,
+                                t->off_cia.data(), &t->bytes);
+    else
+      st = upload_table<float>(d->log10_k_cia, (int64_t)nc * nT, n_nu, pitch, true, &t->d_cia,
+                               t->off_cia.data(), &t->bytes);
+  }
+  if (st == HR2_OK) {
+    std::vector<double> meta;
+    meta.insert(meta.end(), t->T_axis.begin(), t->T_axis.end());
+    meta.insert(meta.end(), t->lp_axis.begin(), t->lp_axis.end());
+    meta.insert(meta.end(), t->off.begin(), t->off.end());
+    meta.insert(meta.end(), t->off_cia.begin(), t->off_cia.end());
+    meta.insert(meta.end(), t->mass.begin(), t->mass.end());
+    if (hipMalloc(&t->d_meta, meta.size() * sizeof(double)) != hipSuccess) {
+      t->d_meta = nullptr;
+      (void)hipGetLastError();
+      st = set_error(HR2_E_NO_MEMORY, "meta allocation failed");
+    } else {
+      hipError_t e = hipMemcpy(t->d_meta, meta.data(), meta.size() * sizeof(double),
+                               hipMemcpyHostToDevice);
+      if (e != hipSuccess) st = hip_error(e, "meta upload");
+      t->bytes += meta.size() * sizeof(double);
+    }
+  }
+  if (st != HR2_OK) {
+    hr2_tables_destroy(t);
+    return st;
+  }
+  TableView &v = t->view;
+  v.tab = t->d_tab;
+  v.cia = t->d_cia;
+  v.T_axis = t->d_meta;
+  v.lp_axis = v.T_axis + nT;
+  v.off = v.lp_axis + nP;
+  v.off_cia = v.off + (size_t)S * nT * nP;
+  v.mass = v.off_cia + (size_t)std::max(nc, 1) * nT;
+  v.S = S;
+  v.nT = nT;
+  v.nP = nP;
+  v.n_cia = nc;
+  v.n_nu = n_nu;
+  v.pitch = pitch;
+  v.nu0 = d->nu0_cm;
+  v.dnu = d->dnu_cm;
+  v.he_ratio = d->he_h2_ratio;
+  v.dtype = d->dtype;
+  *out = t;
+  return HR2_OK;
+}
+
+extern "C" void hr2_tables_destroy(hr2_tables *t) {
+  if (t == nullptr) return;
+  (void)hipSetDevice(t->ctx->device);
+  (void)hipDeviceSynchronize();
+  if (t->d_tab) (void)hipFree(t->d_tab);
+  if (t->d_cia) (void)hipFree(t->d_cia);
+  if (t->d_meta) (void)hipFree(t->d_meta);
+  delete t;
+}
+
+// ------------------------------------------------------------- validation
+namespace hr2 {
+
+hr2_status check_window(const hr2_tables *t, const hr2_window &w) {
+  if (w.nu_count < 1 || w.nu_stride < 1 || w.nu_begin < 0)
+    return set_error(HR2_E_OUT_OF_RANGE, "window needs begin >= 0, count >= 1, stride >= 1");
+  if (w.nu_begin + (w.nu_count - 1) * w.nu_stride >= t->view.n_nu)
+    return set_error(HR2_E_OUT_OF_RANGE, "window leaves the table");
+  return HR2_OK;
+}
+
+hr2_status check_column(const hr2_tables *t, const hr2_column &c, int want_levels) {
+  if (c.n_levels < 2 || c.n_levels > HR2_MAX_LEVELS)
+    return set_error(HR2_E_INVALID_ARG, "n_levels must be in [2, 1024]");
+  if (want_levels > 0 && c.n_levels != want_levels)
+    return set_error(HR2_E_INVALID_ARG, "all columns of a batch must share n_levels");
+  if (!c.p_bar || !c.T_K || !c.x) return set_error(HR2_E_INVALID_ARG, "NULL column array");
+  for (int l = 0; l < c.n_levels; ++l) {
+    if (!(c.p_bar[l] > 0) || !std::isfinite(c.p_bar[l]))
+      return set_error(HR2_E_INVALID_ARG, "pressures must be positive and finite");
+    if (!(c.T_K[l] > 0) || !std::isfinite(c.T_K[l]))
+      return set_error(HR2_E_INVALID_ARG, "temperatures must be positive and finite");
+    if (l > 0 && !(c.p_bar[l] < c.p_bar[l - 1]))
+      return set_error(HR2_E_INVALID_ARG, "pressures must decrease upward");
+  }
+  double xs = 0;
+  for (int s = 0; s < t->view.S; ++s) {
+    if (!(c.x[s] >= 0) || !std::isfinite(c.x[s]))
+      return set_error(HR2_E_INVALID_ARG, "mixing ratios must be >= 0 and finite");
+    xs += c.x[s];
+  }
+  if (!(xs < 1.0)) return set_error(HR2_E_INVALID_ARG, "mixing ratios must sum below 1");
+  if (!std::isfinite(c.log_g_cgs) || !std::isfinite(c.scale))
+    return set_error(HR2_E_INVALID_ARG, "log g and scale must be finite");
+  return HR2_OK;
+}
+
+hr2_status check_n_mu(int n_mu) {
+  if (n_mu < 1 || n_mu > HR2_MAX_MU) return set_error(HR2_E_OUT_OF_RANGE, "n_mu must be in [1, 8]");
+  return HR2_OK;
+}
+
+void pack_columns(const hr2_tables *t, int n_sets, const hr2_column *cols, std::vector<double> &buf) {
+  const int L = cols[0].n_levels, S = t->view.S;
+  buf.resize((size_t)n_sets * (2 * L + S + 2));
+  double *p = buf.data(), *T = p + (size_t)n_sets * L, *x = T + (size_t)n_sets * L;
+  double *lg = x + (size_t)n_sets * S, *sc = lg + n_sets;
+  for (int s = 0; s < n_sets; ++s) {
+    std::memcpy(p + (size_t)s * L, cols[s].p_bar, sizeof(double) * L);
+    std::memcpy(T + (size_t)s * L, cols[s].T_K, sizeof(double) * L);
+    std::memcpy(x + (size_t)s * S, cols[s].x, sizeof(double) * S);
+    lg[s] = cols[s].log_g_cgs;
+    sc[s] = cols[s].scale;
+  }
+}
+
+ColumnsView columns_view(const void *dev, int n_sets, int L, int S) {
+  ColumnsView v;
+  const double *p = (const double *)dev;
+  v.p = p;
+  v.T = p + (size_t)n_sets * L;
+  v.x = v.T + (size_t)n_sets * L;
+  v.logg = v.x + (size_t)n_sets * S;
+  v.scale = v.logg + n_sets;
+  v.B = n_sets;
+  v.L = L;
+  return v;
+}
+
+int auto_chunks(int64_t base_waves, int n_levels) {
+  int c = 1;
+  if (base_waves < 4096) c = 4;
+  else if (base_waves < 8192) c = 2;
+  while (c > 1 && c > n_levels - 1) c >>= 1;
+  return c;
+}
+
+}  // namespace hr2
+
+// ------------------------------------------------------------ observations
+namespace hr2 {
+
+// Host plan of an observation layout: snapped edges, 5 sigma half widths,
+// per-bin supports and offsets of the banded weight rows.
+hr2_status plan_obs(const hr2_tables *t, const hr2_window &w, double R, int n_bins,
+                    const double *edges, ObsPlan &pl) {
+  if (edges == nullptr) return set_error(HR2_E_INVALID_ARG, "NULL bin edges");
+  hr2_status st = check_window(t, w);
+  if (st != HR2_OK) return st;
+  if (!(R > 0) || !std::isfinite(R)) return set_error(HR2_E_INVALID_ARG, "R must be positive");
+  if (n_bins < 1) return set_error(HR2_E_INVALID_ARG, "n_bins must be >= 1");
+  pl.dnu = (double)w.nu_stride * t->view.dnu;
+  pl.first = t->view.nu0 + (double)w.nu_begin * t->view.dnu;
+  pl.N = w.nu_count;
+  pl.R = R;
+  pl.n_bins = n_bins;
+  pl.idx.assign(n_bins + 1, 0);
+  for (int e = 0; e <= n_bins; ++e) {
+    if (!std::isfinite(edges[e])) return set_error(HR2_E_INVALID_ARG, "bin edges must be finite");
+    const double v = std::floor((edges[e] - pl.first) / pl.dnu + 0.5);
+    if (v < 0 || v > (double)(pl.N - 1))
+      return set_error(HR2_E_OUT_OF_RANGE, "a bin edge snaps outside the window");
+    pl.idx[e] = (int64_t)v;
+    if (e > 0 && pl.idx[e] <= pl.idx[e - 1])
+      return set_error(HR2_E_INVALID_ARG, "snapped bin edges must be strictly increasing");
+  }
+  // 5 sigma half widths of the points the bins use (same FP64 test as the
+  // definition: keep k with k dnu <= 5 sigma_i).
+  pl.i0 = pl.idx[0];
+  pl.n_pts = pl.idx[n_bins] - pl.i0 + 1;
+  pl.h.assign(pl.n_pts, 0);
+  const double denom = R * 2.0 * std::sqrt(2.0 * std::log(2.0));
+  for (int64_t q = 0; q < pl.n_pts; ++q) {
+    const int64_t i = pl.i0 + q;
+    const double sig = (pl.first + (double)i * pl.dnu) / denom;
+    const double hv = std::floor(5.0 * sig / pl.dnu);
+    if (!(hv < 1e9)) return set_error(HR2_E_OUT_OF_RANGE, "instrument profile too wide");
+    int64_t hh = (int64_t)hv;
+    while ((double)(hh + 1) * pl.dnu <= 5.0 * sig) ++hh;
+    while (hh > 0 && (double)hh * pl.dnu > 5.0 * sig) --hh;
+    pl.h[q] = (int32_t)std::min<int64_t>(hh, pl.N);
+  }
+  pl.kstart.assign(n_bins, 0);
+  pl.mlo.assign(n_bins, 0);
+  pl.mlen.assign(n_bins, 0);
+  pl.nnz = 0;
+  for (int j = 0; j < n_bins; ++j) {
+    int64_t lo = INT64_MAX, hi = INT64_MIN;
+    for (int64_t i = pl.idx[j]; i <= pl.idx[j + 1]; ++i) {
+      lo = std::min(lo, std::max<int64_t>(0, i - pl.h[i - pl.i0]));
+      hi = std::max(hi, std::min<int64_t>(pl.N - 1, i + pl.h[i - pl.i0]));
+    }
+    pl.kstart[j] = pl.nnz;
+    pl.mlo[j] = (int32_t)lo;
+    pl.mlen[j] = (int32_t)(hi - lo + 1);
+    pl.nnz += hi - lo + 1;
+  }
+  return HR2_OK;
+}
+
+}  // namespace hr2
+
+extern "C" hr2_status hr2_obs_create(hr2_ctx *ctx, const hr2_tables *t, hr2_window w, double R,
+                                     int n_bins, const double *edges, hr2_obs **out) {
+  if (ctx == nullptr || t == nullptr || out == nullptr || edges == nullptr)
+    return set_error(HR2_E_INVALID_ARG, "NULL argument");
+  *out = nullptr;
+  ObsPlan pl;
+  hr2_status st = plan_obs(t, w, R, n_bins, edges, pl);
+  if (st != HR2_OK) return st;
+  HIP_TRY(hipSetDevice(ctx->device));
+  auto *o = new hr2_obs();
+  o->ctx = ctx;
+  o->tables = t;
+  o->window = w;
+  o->R = R;
+  o->n_bins = n_bins;
+  o->fp64 = t->view.dtype == HR2_TABLE_F64;
+  o->nnz = pl.nnz;
+  o->edge_idx = pl.idx;
+  const size_t rs = o->fp64 ? sizeof(double) : sizeof(float);
+  const int64_t nnz = pl.nnz, n_pts = pl.n_pts;
+  void *d_edges = nullptr, *d_h = nullptr, *d_q = nullptr, *d_z = nullptr;
+  hipError_t e = hipMalloc(&o->d_K, std::max<int64_t>(nnz, 1) * rs);
+  if (e == hipSuccess) e = hipMalloc((void **)&o->d_kstart, n_bins * sizeof(int64_t));
+  if (e == hipSuccess) e = hipMalloc((void **)&o->d_mlo, n_bins * sizeof(int32_t));
+  if (e == hipSuccess) e = hipMalloc((void **)&o->d_mlen, n_bins * sizeof(int32_t));
+  if (e == hipSuccess) e = hipMalloc(&d_edges, (n_bins + 1) * sizeof(int64_t));
+  if (e == hipSuccess) e = hipMalloc(&d_h, n_pts * sizeof(int32_t));
+  if (e == hipSuccess) e = hipMalloc(&d_q, n_pts * rs);
+  if (e == hipSuccess) e = hipMalloc(&d_z, n_pts * rs);
+  hipStream_t s = ctx->internal;
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(o->d_kstart, pl.kstart.data(), n_bins * sizeof(int64_t),
+                       hipMemcpyHostToDevice, s);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(o->d_mlo, pl.mlo.data(), n_bins * sizeof(int32_t), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(o->d_mlen, pl.mlen.data(), n_bins * sizeof(int32_t), hipMemcpyHostToDevice,
+                       s);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(d_edges, pl.idx.data(), (n_bins + 1) * sizeof(int64_t),
+                       hipMemcpyHostToDevice, s);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(d_h, pl.h.data(), n_pts * sizeof(int32_t), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess)
+    e = launch_obs_build(o->fp64, pl.N, pl.first, pl.dnu, R, n_bins, (const int64_t *)d_edges,
+                         (const int32_t *)d_h, pl.i0, n_pts, d_q, d_z, o->d_kstart, o->d_mlo,
+                         o->d_mlen, o->d_K, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (d_edges) (void)hipFree(d_edges);
+  if (d_h) (void)hipFree(d_h);
+  if (d_q) (void)hipFree(d_q);
+  if (d_z) (void)hipFree(d_z);
+  if (e != hipSuccess) {
+    hr2_obs_destroy(o);
+    return hip_error(e, "observation layout build");
+  }
+  o->bytes = std::max<int64_t>(nnz, 1) * rs + n_bins * (sizeof(int64_t) + 2 * sizeof(int32_t));
+  *out = o;
+  return HR2_OK;
+}
+
+extern "C" void hr2_obs_destroy(hr2_obs *o) {
+  if (o == nullptr) return;
+  (void)hipSetDevice(o->ctx->device);
+  (void)hipDeviceSynchronize();
+  if (o->d_K) (void)hipFree(o->d_K);
+  if (o->d_kstart) (void)hipFree(o->d_kstart);
+  if (o->d_mlo) (void)hipFree(o->d_mlo);
+  if (o->d_mlen) (void)hipFree(o->d_mlen);
+  delete o;
+}
+
+extern "C" int hr2_obs_n_bins(const hr2_obs *o) { return o ? o->n_bins : 0; }
+
+// ------------------------------------------------------------ stage calls
+namespace {
+
+size_t real_size(const hr2_tables *t) {
+  return t->view.dtype == HR2_TABLE_F64 ? sizeof(double) : sizeof(float);
+}
+size_t rec_size(const hr2_tables *t) {
+  return t->view.dtype == HR2_TABLE_F64 ? sizeof(LevelRecD) : sizeof(LevelRecF);
+}
+
+// Stage one host column and build its level records (B = 1).
+hr2_status one_column_records(hr2_ctx *ctx, const hr2_tables *t, const hr2_column *col,
+                              hipStream_t s) {
+  std::vector<double> buf;
+  pack_columns(t, 1, col, buf);
+  hr2_status st = stage_upload(ctx, ctx->cols, buf.data(), buf.size() * sizeof(double), s);
+  if (st != HR2_OK) return st;
+  st = ctx->recs.ensure((size_t)col->n_levels * rec_size(t));
+  if (st != HR2_OK) return st;
+  const ColumnsView cv = columns_view(ctx->cols.ptr, 1, col->n_levels, t->view.S);
+  HIP_TRY(launch_levels(t->view, cv, ctx->recs.ptr, nullptr, t->view.dtype == HR2_TABLE_F64, s));
+  return HR2_OK;
+}
+
+}  // namespace
+
+extern "C" hr2_status hr2_opacity(hr2_ctx *ctx, const hr2_tables *t, const hr2_column *col,
+                                  hr2_window w, void *chi, void *stream) {
+  if (!ctx || !t || !col || !chi) return set_error(HR2_E_INVALID_ARG, "NULL argument");
+  hr2_status st = check_window(t, w);
+  if (st == HR2_OK) st = check_column(t, *col, 0);
+  if (st != HR2_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  if ((st = ctx_begin(ctx, s)) != HR2_OK) return st;
+  if ((st = one_column_records(ctx, t, col, s)) != HR2_OK) return st;
+  HIP_TRY(launch_opacity_only(t->view, ctx->recs.ptr, col->n_levels, w.nu_begin, w.nu_count,
+                              w.nu_stride, chi, s));
+  return ctx_end(ctx, s);
+}
+
+extern "C" hr2_status hr2_rt_emission(hr2_ctx *ctx, const hr2_tables *t, const hr2_column *col,
+                                      hr2_window w, const void *chi, int n_mu, void *fplus,
+                                      void *stream) {
+  if (!ctx || !t || !col || !chi || !fplus) return set_error(HR2_E_INVALID_ARG, "NULL argument");
+  hr2_status st = check_window(t, w);
+  if (st == HR2_OK) st = check_column(t, *col, 0);
+  if (st == HR2_OK) st = check_n_mu(n_mu);
+  if (st != HR2_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  if ((st = ctx_begin(ctx, s)) != HR2_OK) return st;
+  if ((st = one_column_records(ctx, t, col, s)) != HR2_OK) return st;
+  const int64_t base_waves = (w.nu_count + 63) / 64;
+  const int chunks = ctx->opt_chunks ? std::min(ctx->opt_chunks, std::max(1, col->n_levels - 1))
+                                     : auto_chunks(base_waves, col->n_levels);
+  ColSeg seg{};
+  seg.wg_begin = 0;
+  seg.nu_begin = w.nu_begin;
+  seg.nu_count = w.nu_count;
+  seg.nu_stride = w.nu_stride;
+  seg.rec_offset = 0;
+  seg.out_offset = 0;
+  seg.out_stride = w.nu_count;
+  seg.chi_offset = 0;
+  seg.n_sets = 1;
+  seg.n_levels = col->n_levels;
+  seg.n_mu = n_mu;
+  seg.chunks = chunks;
+  const int per_wg = column_nu_per_wg(chunks);
+  seg.tiles_per_set = (int32_t)((w.nu_count + per_wg - 1) / per_wg);
+  if ((st = upload_cached(ctx, ctx->segs, ctx->segs_shadow, &seg, sizeof(seg), s)) != HR2_OK)
+    return st;
+  HIP_TRY(launch_column(t->view, (const ColSeg *)ctx->segs.ptr, 1, seg.tiles_per_set,
+                        ctx->recs.ptr, chi, fplus, n_mu, true, s));
+  return ctx_end(ctx, s);
+}
+
+extern "C" hr2_status hr2_convolve_bin(hr2_ctx *ctx, const hr2_obs *o, const void *fplus,
+                                       double scale, void *bins, void *stream) {
+  if (!ctx || !o || !fplus || !bins) return set_error(HR2_E_INVALID_ARG, "NULL argument");
+  if (!std::isfinite(scale)) return set_error(HR2_E_INVALID_ARG, "scale must be finite");
+  hipStream_t s = (hipStream_t)stream;
+  hr2_status st;
+  if ((st = ctx_begin(ctx, s)) != HR2_OK) return st;
+  ConvSeg cs{};
+  cs.wave_begin = 0;
+  cs.K = o->d_K;
+  cs.kstart = o->d_kstart;
+  cs.mlo = o->d_mlo;
+  cs.mlen = o->d_mlen;
+  cs.in_offset = 0;
+  cs.in_stride = o->window.nu_count;
+  cs.out_offset = 0;
+  cs.scale = nullptr;
+  cs.scale_const = scale;
+  cs.n_sets = 1;
+  cs.n_bins = o->n_bins;
+  if ((st = upload_cached(ctx, ctx->convsegs, ctx->convsegs_shadow, &cs, sizeof(cs), s)) != HR2_OK)
+    return st;
+  HIP_TRY(launch_convolve_bin(o->fp64, (const ConvSeg *)ctx->convsegs.ptr, 1, o->n_bins, fplus,
+                              bins, s));
+  return ctx_end(ctx, s);
+}
+
+// ----------------------------------------------------------- forward model
+namespace hr2 {
+
+constexpr size_t kMaxTimedCalls = 65536;
+
+// Event slot k of the current timed call (nullptr when not timing).
+static hipEvent_t timing_event(hr2_ctx *ctx, int k) {
+  if (!ctx->timing || ctx->tev_used + 4 > 4 * kMaxTimedCalls) return nullptr;
+  const size_t at = ctx->tev_used + k;
+  while (ctx->tev.size() <= at) {
+    hipEvent_t ev;
+    if (hipEventCreate(&ev) != hipSuccess) return nullptr;
+    ctx->tev.push_back(ev);
+  }
+  return ctx->tev[at];
+}
+
+hr2_status run_forward(hr2_ctx *ctx, const hr2_tables *t, const hr2_obs *o, const ColumnsView &cv,
+                       int n_mu, void *bins, void *fplus, int *status, hipStream_t s) {
+  const hr2_window &w = o->window;
+  const int B = cv.B, L = cv.L;
+  hr2_status st = ctx->recs.ensure((size_t)B * L * rec_size(t));
+  if (st != HR2_OK) return st;
+  if (fplus == nullptr) {
+    if ((st = ctx->fplus.ensure((size_t)B * w.nu_count * real_size(t))) != HR2_OK) return st;
+    fplus = ctx->fplus.ptr;
+  }
+  hipEvent_t ev[4] = {timing_event(ctx, 0), timing_event(ctx, 1), timing_event(ctx, 2),
+                      timing_event(ctx, 3)};
+  const bool timed = ev[0] && ev[1] && ev[2] && ev[3];
+  if (timed) HIP_TRY(hipEventRecord(ev[0], s));
+  HIP_TRY(launch_levels(t->view, cv, ctx->recs.ptr, status, t->view.dtype == HR2_TABLE_F64, s));
+  const int64_t base_waves = (int64_t)B * ((w.nu_count + 63) / 64);
+  const int chunks = ctx->opt_chunks ? std::min(ctx->opt_chunks, std::max(1, L - 1))
+                                     : auto_chunks(base_waves, L);
+  const int per_wg = column_nu_per_wg(chunks);
+  ColSeg seg{};
+  seg.wg_begin = 0;
+  seg.nu_begin = w.nu_begin;
+  seg.nu_count = w.nu_count;
+  seg.nu_stride = w.nu_stride;
+  seg.rec_offset = 0;
+  seg.out_offset = 0;
+  seg.out_stride = w.nu_count;
+  seg.chi_offset = 0;
+  seg.n_sets = B;
+  seg.n_levels = L;
+  seg.n_mu = n_mu;
+  seg.chunks = chunks;
+  seg.tiles_per_set = (int32_t)((w.nu_count + per_wg - 1) / per_wg);
+  const int64_t total_wgs = (int64_t)B * seg.tiles_per_set;
+  if (total_wgs > 0x7fffffff) return set_error(HR2_E_OUT_OF_RANGE, "launch too large");
+  if ((st = upload_cached(ctx, ctx->segs, ctx->segs_shadow, &seg, sizeof(seg), s)) != HR2_OK)
+    return st;
+  if (timed) HIP_TRY(hipEventRecord(ev[1], s));
+  HIP_TRY(launch_column(t->view, (const ColSeg *)ctx->segs.ptr, 1, total_wgs, ctx->recs.ptr,
+                        nullptr, fplus, n_mu, false, s));
+  ConvSeg cs{};
+  cs.wave_begin = 0;
+  cs.K = o->d_K;
+  cs.kstart = o->d_kstart;
+  cs.mlo = o->d_mlo;
+  cs.mlen = o->d_mlen;
+  cs.in_offset = 0;
+  cs.in_stride = w.nu_count;
+  cs.out_offset = 0;
+  cs.scale = cv.scale;
+  cs.scale_const = 0.0;
+  cs.n_sets = B;
+  cs.n_bins = o->n_bins;
+  if ((st = upload_cached(ctx, ctx->convsegs, ctx->convsegs_shadow, &cs, sizeof(cs), s)) != HR2_OK)
+    return st;
+  if (timed) HIP_TRY(hipEventRecord(ev[2], s));
+  HIP_TRY(launch_convolve_bin(o->fp64, (const ConvSeg *)ctx->convsegs.ptr, 1,
+                              (int64_t)B * o->n_bins, fplus, bins, s));
+  if (timed) {
+    HIP_TRY(hipEventRecord(ev[3], s));
+    ctx->tev_used += 4;
+  }
+  return HR2_OK;
+}
+
+}  // namespace hr2
+
+extern "C" hr2_status hr2_forward_batch(hr2_ctx *ctx, const hr2_tables *t, const hr2_obs *o,
+                                        int n_sets, const hr2_column *cols, int n_mu, void *bins,
+                                        void *fplus, void *stream) {
+  if (!ctx || !t || !o || !cols || !bins) return set_error(HR2_E_INVALID_ARG, "NULL argument");
+  if (o->tables != t) return set_error(HR2_E_INVALID_ARG, "layout was made for other tables");
+  if (n_sets < 1) return set_error(HR2_E_INVALID_ARG, "n_sets must be >= 1");
+  hr2_status st = check_n_mu(n_mu);
+  if (st != HR2_OK) return st;
+  for (int i = 0; i < n_sets; ++i)
+    if ((st = check_column(t, cols[i], cols[0].n_levels)) != HR2_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  if ((st = ctx_begin(ctx, s)) != HR2_OK) return st;
+  std::vector<double> buf;
+  pack_columns(t, n_sets, cols, buf);
+  if ((st = stage_upload(ctx, ctx->cols, buf.data(), buf.size() * sizeof(double), s)) != HR2_OK)
+    return st;
+  const ColumnsView cv = columns_view(ctx->cols.ptr, n_sets, cols[0].n_levels, t->view.S);
+  if ((st = run_forward(ctx, t, o, cv, n_mu, bins, fplus, nullptr, s)) != HR2_OK) return st;
+  return ctx_end(ctx, s);
+}
+
+extern "C" hr2_status hr2_forward_batch_dev(hr2_ctx *ctx, const hr2_tables *t, const hr2_obs *o,
+                                            int n_sets, int n_levels, const double *p_dev,
+                                            const double *T_dev, const double *x_dev,
+                                            const double *logg_dev, const double *scale_dev,
+                                            int n_mu, void *bins, void *fplus, int *status_dev,
+                                            void *stream) {
+  if (!ctx || !t || !o || !p_dev || !T_dev || !x_dev || !logg_dev || !scale_dev || !bins)
+    return set_error(HR2_E_INVALID_ARG, "NULL argument");
+  if (o->tables != t) return set_error(HR2_E_INVALID_ARG, "layout was made for other tables");
+  if (n_sets < 1) return set_error(HR2_E_INVALID_ARG, "n_sets must be >= 1");
+  if (n_levels < 2 || n_levels > HR2_MAX_LEVELS)
+    return set_error(HR2_E_INVALID_ARG, "n_levels must be in [2, 1024]");
+  hr2_status st = check_n_mu(n_mu);
+  if (st != HR2_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  if ((st = ctx_begin(ctx, s)) != HR2_OK) return st;
+  ColumnsView cv;
+  cv.p = p_dev;
+  cv.T = T_dev;
+  cv.x = x_dev;
+  cv.logg = logg_dev;
+  cv.scale = scale_dev;
+  cv.B = n_sets;
+  cv.L = n_levels;
+  if ((st = run_forward(ctx, t, o, cv, n_mu, bins, fplus, status_dev, s)) != HR2_OK) return st;
+  return ctx_end(ctx, s);
+}
+
+extern "C" hr2_status hr2_ctx_collect_timing(hr2_ctx *ctx, double ms[3], int64_t *n_calls) {
+  if (!ctx || !ms || !n_calls) return set_error(HR2_E_INVALID_ARG, "NULL argument");
+  ms[0] = ms[1] = ms[2] = 0.0;
+  *n_calls = (int64_t)(ctx->tev_used / 4);
+  for (size_t c = 0; c + 4 <= ctx->tev_used; c += 4) {
+    HIP_TRY(hipEventSynchronize(ctx->tev[c + 3]));
+    for (int k = 0; k < 3; ++k) {
+      float t = 0.0f;
+      HIP_TRY(hipEventElapsedTime(&t, ctx->tev[c + k], ctx->tev[c + k + 1]));
+      ms[k] += t;
+    }
+  }
+  ctx->tev_used = 0;
+  return HR2_OK;
+}

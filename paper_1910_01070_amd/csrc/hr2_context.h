@@ -1,0 +1,70 @@
+// hr2_context.h — the context object and host helpers shared by api.cpp and
+// serve.cpp.  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "hr2_internal.h"
+
+namespace hr2 {
+
+// Grow-only device buffer.
+struct DevBuf {
+  void *ptr = nullptr;
+  size_t cap = 0;
+  hr2_status ensure(size_t bytes);
+  void release();
+};
+
+hr2_status set_error(hr2_status st, const std::string &msg);
+hr2_status hip_error(hipError_t e, const char *what);
+
+}  // namespace hr2
+
+struct hr2_ctx {
+  int device = 0;
+  hipStream_t internal = nullptr;   // layout builds
+  hipEvent_t scratch_event = nullptr;
+  bool scratch_used = false;
+  hipEvent_t pinned_event = nullptr;
+  bool pinned_pending = false;
+  void *pinned = nullptr;
+  size_t pinned_cap = 0;
+  int opt_chunks = 0;
+  bool timing = false;
+  std::vector<hipEvent_t> tev;     // 4 events per timed call
+  size_t tev_used = 0;             // events recorded since the last collection
+  hr2::DevBuf recs, fplus, cols, segs, convsegs;
+  std::vector<unsigned char> segs_shadow, convsegs_shadow;
+};
+
+namespace hr2 {
+
+hr2_status ctx_begin(hr2_ctx *ctx, hipStream_t stream);
+hr2_status ctx_end(hr2_ctx *ctx, hipStream_t stream);
+hr2_status stage_upload(hr2_ctx *ctx, DevBuf &dst, const void *src, size_t bytes,
+                        hipStream_t stream);
+hr2_status check_window(const hr2_tables *t, const hr2_window &w);
+hr2_status check_column(const hr2_tables *t, const hr2_column &c, int want_levels);
+hr2_status check_n_mu(int n_mu);
+void pack_columns(const hr2_tables *t, int n_sets, const hr2_column *cols,
+                  std::vector<double> &buf);
+ColumnsView columns_view(const void *dev, int n_sets, int L, int S);
+int auto_chunks(int64_t base_waves, int n_levels);
+
+struct ObsPlan {
+  int64_t N = 0, i0 = 0, n_pts = 0, nnz = 0;
+  double first = 0, dnu = 0, R = 0;
+  int n_bins = 0;
+  std::vector<int64_t> idx;      // snapped edges [n_bins + 1]
+  std::vector<int32_t> h;        // 5 sigma half widths of points i0 .. i0 + n_pts - 1
+  std::vector<int64_t> kstart;   // [n_bins]
+  std::vector<int32_t> mlo, mlen;
+};
+hr2_status plan_obs(const hr2_tables *t, const hr2_window &w, double R, int n_bins,
+                    const double *edges, ObsPlan &plan);
+
+}  // namespace hr2

@@ -1,0 +1,177 @@
+// hr2_internal.h — structures shared by the host side (api.cpp, serve.cpp)
+// and the kernels (kernels.hip) of libhr2.  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "hr2.h"
+
+namespace hr2 {
+
+// ---------------------------------------------------------------- level records
+// One record per (set, level), written by the level kernel and read with
+// scalar loads by the column kernels.  The four "slots" hold the four
+// table rows of the bilinear cell (Sect. 2.3 reading: bilinear in
+// (T, log10 p)); a slot keeps its row across levels when the next level's
+// cell still needs that row, so only rows new to the column are fetched.
+// The CIA (linear in T) uses two slots the same way.
+constexpr int kMaxSpecies = HR2_MAX_SPECIES;
+constexpr int kMaxMu = HR2_MAX_MU;
+
+struct alignas(16) LevelRecF {
+  float w[4];            // slot weights (bilinear corner weights)
+  int32_t row[4];        // row held by each slot: iT * n_p + ip
+  int32_t mask;          // bit k < 4: species slot k changes here; bit 4 + q: CIA slot q
+  int32_t cia_row[2];    // CIA slot rows (T node)
+  float cia_w[2];        // CIA slot weights
+  float a_cia[2];        // n_H2^2 2^{c}, n_H2 n_He 2^{c'} (c: interpolated row offsets)
+  float hdz;             // dz_l / 2 of layer l -> l+1 (0 at the top level)
+  float pl_hi, pl_lo;    // c2 log2(e) / T_l as an unevaluated float sum
+  float a_s[kMaxSpecies];  // n_s 2^{c_s}
+  float pad[2];
+};
+static_assert(sizeof(LevelRecF) == 128, "LevelRecF must be 128 bytes");
+
+struct alignas(16) LevelRecD {
+  double w[4];
+  int32_t row[4];
+  int32_t mask;
+  int32_t cia_row[2];
+  int32_t pad0;
+  double cia_w[2];
+  double a_cia[2];
+  double hdz;
+  double T;               // level temperature (Planck in FP64)
+  double a_s[kMaxSpecies];
+  double pad[6];
+};
+static_assert(sizeof(LevelRecD) == 256, "LevelRecD must be 256 bytes");
+
+template <typename Real> struct RecOf;
+template <> struct RecOf<float> { using type = LevelRecF; };
+template <> struct RecOf<double> { using type = LevelRecD; };
+
+// --------------------------------------------------------------- table meta
+// Device view of a resident table set.
+struct TableView {
+  const void *tab;          // [S][nT][nP][pitch] storage elements
+  const void *cia;          // [n_cia][nT][pitch] float (double for F64)
+  const double *T_axis;     // [nT]
+  const double *lp_axis;    // [nP]
+  const double *off;        // [S][nT][nP] log2 offsets of the rows
+  const double *off_cia;    // [n_cia][nT]
+  const double *mass;       // [S] g/mol
+  int S, nT, nP, n_cia;
+  int64_t n_nu, pitch;
+  double nu0, dnu, he_ratio;
+  int dtype;                // hr2_table_dtype
+};
+
+// Packed device columns of one batch (FP64).
+struct ColumnsView {
+  const double *p;      // [B][L]
+  const double *T;      // [B][L]
+  const double *x;      // [B][S]
+  const double *logg;   // [B]
+  const double *scale;  // [B]
+  int B, L;
+};
+
+// One segment of a column-kernel launch: a batch of sets sharing levels and
+// a wavenumber window (a forward_batch call, or one request when serving).
+struct ColSeg {
+  int64_t wg_begin;        // first workgroup of the segment
+  int64_t nu_begin, nu_count, nu_stride;
+  int64_t rec_offset;      // records of set s: recs + rec_offset + s * n_levels
+  int64_t out_offset;      // F+ of set s: out + out_offset + s * out_stride
+  int64_t out_stride;
+  int64_t chi_offset;      // stage call only: chi + chi_offset + l * nu_count
+  int32_t n_sets, n_levels, tiles_per_set, n_mu;
+  int32_t chunks;          // layer chunks per wavenumber sub-tile: 1, 2 or 4
+  int32_t pad;
+};
+
+// One segment of a convolve/bin launch: n_sets spectra against one layout.
+struct ConvSeg {
+  int64_t wave_begin;       // first wave (one wave per (set, bin))
+  const void *K;            // weights (Real)
+  const int64_t *kstart;    // [n_bins]
+  const int32_t *mlo;       // [n_bins] first window point of the support
+  const int32_t *mlen;      // [n_bins] support length
+  int64_t in_offset, in_stride;    // F+ of set s
+  int64_t out_offset;              // bins of set s: out + out_offset + s * n_bins
+  const double *scale;      // [n_sets] or NULL
+  double scale_const;       // used when scale == NULL
+  int32_t n_sets, n_bins;
+};
+
+// Angular quadrature constants for n_mu = 1..8 (Eq. 8): row n-1.
+struct AngleTable {
+  float mu[kMaxMu][kMaxMu];
+  float l2e_mu[kMaxMu][kMaxMu];   // log2(e) / mu
+  float inv_mu[kMaxMu][kMaxMu];
+  float cw[kMaxMu][kMaxMu];       // 2 pi w mu
+  double mu_d[kMaxMu][kMaxMu];
+  double inv_mu_d[kMaxMu][kMaxMu];
+  double cw_d[kMaxMu][kMaxMu];
+};
+
+// ----------------------------------------------------------------- launchers
+// All launchers enqueue on `stream` and return hipSuccess or the launch error.
+hipError_t upload_angle_table(const AngleTable &t);
+
+hipError_t launch_levels(const TableView &tv, const ColumnsView &cv, void *recs,
+                         int *status, bool fp64, hipStream_t stream);
+
+hipError_t launch_column(const TableView &tv, const ColSeg *segs_dev, int n_segs,
+                         int64_t total_wgs, const void *recs, const void *chi_in, void *out,
+                         int max_mu, bool opacity_from_memory, hipStream_t stream);
+int column_nu_per_wg(int chunks);
+
+hipError_t launch_opacity_only(const TableView &tv, const void *recs, int n_levels,
+                               int64_t nu_begin, int64_t nu_count, int64_t nu_stride,
+                               void *chi, hipStream_t stream);
+
+hipError_t launch_convolve_bin(bool fp64, const ConvSeg *segs_dev, int n_segs,
+                               int64_t total_waves, const void *in, void *out,
+                               hipStream_t stream);
+
+// Observation layout build: Z_i and q_i for window points [i0, i0 + n)
+// then the banded per-bin weights.
+hipError_t launch_obs_build(bool fp64, int64_t N, double nu_first, double dnu_eff, double R,
+                            int n_bins, const int64_t *edge_idx_dev, const int32_t *h_dev,
+                            int64_t i0, int64_t n_pts, void *q_scratch, void *invz_scratch,
+                            const int64_t *kstart_dev, const int32_t *mlo_dev,
+                            const int32_t *mlen_dev, void *K_dev, hipStream_t stream);
+
+}  // namespace hr2
+
+// ------------------------------------------------------------- handle types
+struct hr2_tables {
+  hr2_ctx *ctx = nullptr;
+  hr2::TableView view{};
+  void *d_tab = nullptr, *d_cia = nullptr;
+  double *d_meta = nullptr;
+  std::vector<double> T_axis, lp_axis, off, off_cia, mass;
+  size_t bytes = 0;
+};
+
+struct hr2_obs {
+  hr2_ctx *ctx = nullptr;
+  const hr2_tables *tables = nullptr;
+  hr2_window window{};
+  double R = 0;
+  int n_bins = 0;
+  bool fp64 = false;
+  int64_t nnz = 0;
+  std::vector<int64_t> edge_idx;     // [n_bins + 1]
+  void *d_K = nullptr;               // Real[nnz]
+  int64_t *d_kstart = nullptr;       // [n_bins]
+  int32_t *d_mlo = nullptr, *d_mlen = nullptr;
+  size_t bytes = 0;
+};

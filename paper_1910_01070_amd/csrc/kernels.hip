@@ -1,0 +1,785 @@
+// kernels.hip — gfx950 kernels of libhr2: level records, the fused
+// opacity + short-characteristics column kernel, the stage-1 opacity kernel,
+// the observation-layout build and the convolve/bin kernel.
+//
+// Paper: Kitzmann et al. 2020 (arXiv:1910.01070), Sect. 2.1-2.3, 2.7, 2.8,
+// Eq. 2, 4-9, 17.  Design: wavefronts of 64 lanes own 64 consecutive window
+// points each (coalesced table rows); all per-level quantities are uniform
+// across the workgroup and arrive through scalar loads of a 128-byte record;
+// the table rows of the bilinear cell stay in registers between levels; the
+// layer recurrence may be split into up to four chunks whose affine maps
+// I_out = exp(-tau_c / mu) I_in + B_c are combined through LDS.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <type_traits>
+
+#include "hr2_internal.h"
+
+namespace hr2 {
+
+// CODATA 2018 exact constants (cgs) and the atomic mass constant.
+constexpr double kH = 6.62607015e-27;
+constexpr double kC = 2.99792458e10;
+constexpr double kKB = 1.380649e-16;
+constexpr double kAMU = 1.66053906660e-24;
+constexpr double kMH2 = 2.016;
+constexpr double kMHe = 4.0026;
+constexpr double kC2 = kH * kC / kKB;          // second radiation constant, cm K
+constexpr double kC1 = 2.0 * kH * kC * kC;     // 2 h c^2
+constexpr double kLog2e = 1.4426950408889634074;
+constexpr float kLn2f = 0.69314718055994530942f;
+
+__constant__ AngleTable c_ang;
+
+hipError_t upload_angle_table(const AngleTable &t) {
+  return hipMemcpyToSymbol(HIP_SYMBOL(c_ang), &t, sizeof(AngleTable), 0, hipMemcpyHostToDevice);
+}
+
+// ------------------------------------------------------------ small helpers
+
+// Workgroups are dispatched round-robin over the eight XCDs; hand each XCD a
+// contiguous range of logical work items so that the sets of one wavenumber
+// tile (which read the same table rows) share that XCD's L2.
+__device__ __forceinline__ int64_t xcd_remap(int64_t g, int64_t n) {
+  const int64_t x = g & 7, k = g >> 3;
+  const int64_t q = n >> 3, r = n & 7;
+  return x * q + (x < r ? x : r) + k;
+}
+
+template <typename TT> __device__ __forceinline__ float to_float(TT v);
+template <> __device__ __forceinline__ float to_float<float>(float v) { return v; }
+template <> __device__ __forceinline__ float to_float<_Float16>(_Float16 v) { return (float)v; }
+template <> __device__ __forceinline__ float to_float<uint16_t>(uint16_t v) {
+  return __uint_as_float(((uint32_t)v) << 16);   // bfloat16 -> float is exact
+}
+
+__device__ __forceinline__ float fexp2(float x) { return __builtin_amdgcn_exp2f(x); }
+__device__ __forceinline__ float frcp(float x) { return __builtin_amdgcn_rcpf(x); }
+
+// Axis lookup of the table (reading of Sect. 2.3): clamp, lower node = the
+// largest index with axis[i] <= v capped at n-2, w = (v - a_i)/(a_{i+1} - a_i).
+__device__ __forceinline__ void locate(const double *axis, int n, double v, int &i, double &w) {
+  v = v < axis[0] ? axis[0] : v;
+  v = v > axis[n - 1] ? axis[n - 1] : v;
+  int k = 0;
+  for (int q = 1; q < n; ++q)
+    if (axis[q] <= v) k = q;
+  if (k > n - 2) k = n - 2;
+  i = k;
+  w = (v - axis[k]) / (axis[k + 1] - axis[k]);
+}
+
+// ------------------------------------------------------------ level records
+// One thread per (set, level).  Everything here is FP64; the column kernel
+// gets FP32 (FP64 for F64 tables) per-level constants:
+//   n = p / (k_B T); n_s = x_s n; x_H2 = (1 - sum x)/(1 + r), x_He = r x_H2;
+//   mubar; dz_l = k_B (T_l + T_l+1)/2 / (mubar m_u g) ln(p_l / p_l+1)
+//   (Sect. 2, 2.4, 5.2 and the hydrostatic reading of the optical depths);
+// the bilinear cell of (T, log10 p) and its corner weights, the corner rows
+// assigned to slots by node parity (slot = (row_T & 1) * 2 + (row_p & 1)),
+// so a row shared by consecutive levels keeps its slot and is not reloaded.
+struct CellW {
+  int iT, ip;
+  double wT, wp;
+};
+
+__device__ __forceinline__ CellW cell_of(const TableView &tv, double T, double p) {
+  CellW c;
+  locate(tv.T_axis, tv.nT, T, c.iT, c.wT);
+  locate(tv.lp_axis, tv.nP, log10(p), c.ip, c.wp);
+  return c;
+}
+
+// slot k <-> corner (a, b) of the cell with row parity k
+__device__ __forceinline__ void slot_corner(const CellW &c, int k, int nP, int &row, double &w) {
+  const int a = ((k >> 1) ^ c.iT) & 1;
+  const int b = ((k & 1) ^ c.ip) & 1;
+  row = (c.iT + a) * nP + (c.ip + b);
+  w = (a ? c.wT : 1.0 - c.wT) * (b ? c.wp : 1.0 - c.wp);
+}
+
+__device__ __forceinline__ void cia_slot(const CellW &c, int k, int &row, double &w) {
+  const int a = (k ^ c.iT) & 1;
+  row = c.iT + a;
+  w = a ? c.wT : 1.0 - c.wT;
+}
+
+template <typename Real>
+__global__ __launch_bounds__(256) void k_levels(TableView tv, ColumnsView cv,
+                                                typename RecOf<Real>::type *recs, int *status) {
+  using Rec = typename RecOf<Real>::type;
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int L = cv.L;
+  if (gid >= (int64_t)cv.B * L) return;
+  const int s = (int)(gid / L), l = (int)(gid % L);
+  const int S = tv.S;
+  const double *p = cv.p + (int64_t)s * L;
+  const double *T = cv.T + (int64_t)s * L;
+  const double *x = cv.x + (int64_t)s * S;
+
+  // column-wide validity (every thread of the set reaches the same verdict)
+  bool bad = false;
+  double xs = 0.0, mm = 0.0;
+  for (int q = 0; q < S; ++q) {
+    bad |= !(x[q] >= 0.0) || !isfinite(x[q]);
+    xs += x[q];
+    mm += x[q] * tv.mass[q];
+  }
+  bad |= !(xs < 1.0) || !isfinite(cv.logg[s]) || !isfinite(cv.scale[s]);
+  for (int q = 0; q < L; ++q) {
+    bad |= !(p[q] > 0.0) || !isfinite(p[q]) || !(T[q] > 0.0) || !isfinite(T[q]);
+    if (q + 1 < L) bad |= !(p[q] > p[q + 1]);
+  }
+  if (status != nullptr && l == 0) status[s] = bad ? (int)HR2_E_INVALID_ARG : 0;
+
+  const double h2 = (1.0 - xs) / (1.0 + tv.he_ratio);
+  const double he = tv.he_ratio * h2;
+  mm += h2 * kMH2 + he * kMHe;
+  const double g = pow(10.0, cv.logg[s]);
+  const double n = p[l] * 1.0e6 / (kKB * T[l]);
+
+  Rec r;
+  const CellW c = cell_of(tv, T[l], p[l]);
+  CellW cp = c;
+  const bool has_prev = l > 0;
+  if (has_prev) cp = cell_of(tv, T[l - 1], p[l - 1]);
+  int mask = 0;
+  double wsl[4];
+  int rowsl[4];
+  for (int k = 0; k < 4; ++k) {
+    int row, rowp;
+    double w, wp;
+    slot_corner(c, k, tv.nP, row, w);
+    slot_corner(cp, k, tv.nP, rowp, wp);
+    wsl[k] = w;
+    rowsl[k] = row;
+    r.w[k] = (Real)w;
+    r.row[k] = row;
+    const bool nz = w != 0.0;
+    const bool kept = has_prev && wp != 0.0 && rowp == row;
+    if (nz) mask |= 1 << (8 + k);
+    if (nz && !kept) mask |= 1 << k;
+  }
+  for (int k = 0; k < 2; ++k) {
+    int row, rowp;
+    double w, wp;
+    cia_slot(c, k, row, w);
+    cia_slot(cp, k, rowp, wp);
+    r.cia_row[k] = row;
+    r.cia_w[k] = (Real)w;
+    const bool nz = w != 0.0 && tv.n_cia > 0;
+    const bool kept = has_prev && wp != 0.0 && rowp == row;
+    if (nz) mask |= 1 << (12 + k);
+    if (nz && !kept) mask |= 1 << (4 + k);
+  }
+  r.mask = mask;
+
+  // n_s 2^{interpolated row offset}: the kernel exponentiates only the
+  // stored (offset-free) part, keeping its exp2 argument small.
+  const int64_t rows_per_species = (int64_t)tv.nT * tv.nP;
+  for (int q = 0; q < kMaxSpecies; ++q) {
+    double a = 0.0;
+    if (q < S) {
+      double cq = 0.0;
+      for (int k = 0; k < 4; ++k) cq += wsl[k] * tv.off[q * rows_per_species + rowsl[k]];
+      a = x[q] * n * exp2(cq);
+    }
+    r.a_s[q] = (Real)a;
+  }
+  for (int q = 0; q < 2; ++q) {
+    double a = 0.0;
+    if (q < tv.n_cia) {
+      double cq = 0.0;
+      for (int k = 0; k < 2; ++k) {
+        int row;
+        double w;
+        cia_slot(c, k, row, w);
+        cq += w * tv.off_cia[q * tv.nT + row];
+      }
+      const double nh2 = h2 * n, nhe = he * n;
+      a = (q == 0 ? nh2 * nh2 : nh2 * nhe) * exp2(cq);
+    }
+    r.a_cia[q] = (Real)a;
+  }
+  double hdz = 0.0;
+  if (l + 1 < L) {
+    const double tbar = 0.5 * (T[l] + T[l + 1]);
+    hdz = 0.5 * kKB * tbar / (mm * kAMU * g) * log(p[l] / p[l + 1]);
+  }
+  if (bad) hdz = __builtin_nan("");
+  r.hdz = (Real)hdz;
+  if constexpr (std::is_same<Real, float>::value) {
+    const double pl = kC2 * kLog2e / T[l];
+    const float hi = (float)pl;
+    r.pl_hi = hi;
+    r.pl_lo = (float)(pl - (double)hi);
+    r.pad[0] = r.pad[1] = 0.0f;
+  } else {
+    r.T = T[l];
+    r.pad0 = 0;
+    for (int q = 0; q < 6; ++q) r.pad[q] = 0.0;
+  }
+  recs[(int64_t)s * L + l] = r;
+}
+
+hipError_t launch_levels(const TableView &tv, const ColumnsView &cv, void *recs, int *status,
+                         bool fp64, hipStream_t stream) {
+  const int64_t n = (int64_t)cv.B * cv.L;
+  const dim3 grid((unsigned)((n + 255) / 256));
+  if (fp64)
+    hipLaunchKernelGGL(k_levels<double>, grid, dim3(256), 0, stream, tv, cv,
+                       (LevelRecD *)recs, status);
+  else
+    hipLaunchKernelGGL(k_levels<float>, grid, dim3(256), 0, stream, tv, cv,
+                       (LevelRecF *)recs, status);
+  return hipGetLastError();
+}
+
+// --------------------------------------------------------------- RT pieces
+
+// Planck source, Eq. 2 (wavenumber form), FP32: x = c2 nu / T is formed as
+// an unevaluated float sum (pl_hi + pl_lo)(nu_hi + nu_lo) in log2 units so
+// that exp stays accurate for large x; expm1 by its series below x = 1/2.
+__device__ __forceinline__ float planck_f(float nu_hi, float nu_lo, float c1nu3, float pl_hi,
+                                          float pl_lo) {
+  const float p_hi = pl_hi * nu_hi;
+  const float p_err = fmaf(pl_hi, nu_hi, -p_hi);
+  const float p_lo = fmaf(pl_hi, nu_lo, fmaf(pl_lo, nu_hi, p_err));
+  const float xl2 = p_hi + p_lo;
+  float em;
+  if (xl2 < 0.72134752044448170f) {   // x < 1/2
+    const float x = xl2 * kLn2f;
+    float t = 1.0f / 40320.0f;
+    t = fmaf(t, x, 1.0f / 5040.0f);
+    t = fmaf(t, x, 1.0f / 720.0f);
+    t = fmaf(t, x, 1.0f / 120.0f);
+    t = fmaf(t, x, 1.0f / 24.0f);
+    t = fmaf(t, x, 1.0f / 6.0f);
+    t = fmaf(t, x, 0.5f);
+    t = fmaf(t, x, 1.0f);
+    em = t * x;
+  } else {
+    const float e = fexp2(p_hi);
+    em = fmaf(e, p_lo * kLn2f, e) - 1.0f;
+  }
+  return c1nu3 * frcp(em);
+}
+
+__device__ __forceinline__ double planck_d(double nu, double c1nu3, double T) {
+  return c1nu3 / expm1(kC2 * nu / T);
+}
+
+// One layer of Eq. 4-7 for one angle (FP32).  Linear source, alpha = 0,
+// attenuation exp(-Delta), Delta = dtau / mu; beta = 1 - u, gamma = u - e,
+// u = (1 - e)/Delta.  Below Delta = 1/2, beta comes from its Taylor series
+// and gamma = Delta (1 - beta) - beta, e = 1 - Delta (1 - beta), which avoids
+// the cancellation in 1 - u.
+__device__ __forceinline__ float sc_step_f(float I, float dtau, float rdt, float S1, float S0,
+                                           float inv_mu, float l2e_mu, float mu) {
+  const float d = dtau * inv_mu;
+  float e, beta, gamma;
+  if (d < 0.5f) {
+    float b = -1.0f / 362880.0f;
+    b = fmaf(b, d, 1.0f / 40320.0f);
+    b = fmaf(b, d, -1.0f / 5040.0f);
+    b = fmaf(b, d, 1.0f / 720.0f);
+    b = fmaf(b, d, -1.0f / 120.0f);
+    b = fmaf(b, d, 1.0f / 24.0f);
+    b = fmaf(b, d, -1.0f / 6.0f);
+    b = fmaf(b, d, 0.5f);
+    beta = b * d;
+    const float ome = d * (1.0f - beta);
+    gamma = ome - beta;
+    e = 1.0f - ome;
+  } else {
+    e = fexp2(-dtau * l2e_mu);
+    const float u = (1.0f - e) * (rdt * mu);
+    beta = 1.0f - u;
+    gamma = u - e;
+  }
+  return fmaf(e, I, fmaf(beta, S1, gamma * S0));
+}
+
+__device__ __forceinline__ double sc_step_d(double I, double dtau, double S1, double S0,
+                                            double mu) {
+  const double d = dtau / mu;
+  const double e = exp(-d);
+  const double u = d > 0.0 ? -expm1(-d) / d : 1.0;
+  const double beta = 1.0 - u, gamma = u - e;
+  return e * I + beta * S1 + gamma * S0;
+}
+
+// ------------------------------------------------------------ column kernel
+// Workgroup = 4 waves.  With C chunks, wave w handles sub-tile w / C (64
+// window points) and layer chunk w % C.  Each lane sweeps its chunk's levels
+// bottom to top: stage 1 (opacity, Sect. 2.3) from the slot registers,
+// dtau (trapezoid over the layer), Planck, and the recurrence for every
+// angle; then the chunks' affine maps are combined and Eq. 8 applied.
+template <typename Real, typename TT, int NS, int MAXMU, bool FROM_CHI>
+__global__ __launch_bounds__(256) void k_column(TableView tv, const ColSeg *__restrict__ segs,
+                                                int n_segs, int64_t total_wgs,
+                                                const typename RecOf<Real>::type *__restrict__ recs,
+                                                const Real *__restrict__ chi_in,
+                                                Real *__restrict__ out) {
+  using Rec = typename RecOf<Real>::type;
+  constexpr bool kF64 = std::is_same<Real, double>::value;
+  __shared__ Real sh_B[4][MAXMU][64];
+  __shared__ Real sh_tau[4][64];
+
+  const int64_t g = xcd_remap(blockIdx.x, total_wgs);
+  int sg = 0;
+  for (int i = 1; i < n_segs; ++i)
+    if (segs[i].wg_begin <= g) sg = i;
+  const ColSeg &d = segs[sg];
+  const int n_sets = d.n_sets;
+  const int C = d.chunks;
+  const int64_t local = g - d.wg_begin;
+  const int64_t t = local / n_sets;
+  const int s = (int)(local - t * n_sets);
+
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int chunk = wave % C, sub = wave / C;
+  const int L = d.n_levels, nlay = L - 1;
+  const int m = (nlay + C - 1) / C;
+  const int l0 = chunk * m;
+  const int l1 = min(l0 + m, nlay);
+  const int64_t nu_count = d.nu_count;
+  const int64_t j = t * (int64_t)(4 / C) * 64 + sub * 64 + lane;
+  const bool active = j < nu_count;
+  const int64_t jj = active ? j : nu_count - 1;
+  const int64_t kidx = d.nu_begin + jj * d.nu_stride;
+  const uint32_t kk = (uint32_t)kidx;
+  const Rec *rec = recs + d.rec_offset + (int64_t)s * L;
+  const int nmu = d.n_mu;
+
+  const double nu_d = tv.nu0 + (double)kidx * tv.dnu;
+  const double c1nu3_d = kC1 * nu_d * nu_d * nu_d;
+  const float nu_hi = (float)nu_d;
+  const float nu_lo = (float)(nu_d - (double)nu_hi);
+  const float c1nu3_f = (float)c1nu3_d;
+
+  const int64_t pitch = tv.pitch;
+  const int64_t sp_stride = (int64_t)tv.nT * tv.nP * pitch;
+  const TT *tab = (const TT *)tv.tab;
+  const Real *cia = (const Real *)tv.cia;
+
+  Real slot[NS][4];
+  Real cslot[2][2];
+#pragma unroll
+  for (int q = 0; q < NS; ++q)
+#pragma unroll
+    for (int k = 0; k < 4; ++k) slot[q][k] = (Real)0;
+#pragma unroll
+  for (int q = 0; q < 2; ++q) cslot[q][0] = cslot[q][1] = (Real)0;
+
+  Real I[MAXMU];
+#pragma unroll
+  for (int k = 0; k < MAXMU; ++k) I[k] = (Real)0;
+  Real tau = (Real)0, chi_prev = (Real)0, S_prev = (Real)0, hdz_prev = (Real)0;
+
+  if (l0 < nlay) {
+    for (int l = l0; l <= l1; ++l) {
+      const Rec &r = rec[l];
+      Real chi;
+      if constexpr (FROM_CHI) {
+        chi = chi_in[d.chi_offset + (int64_t)l * nu_count + jj];
+      } else {
+        const int mask = (l == l0) ? (r.mask >> 8) : r.mask;
+        chi = (Real)0;
+#pragma unroll
+        for (int q = 0; q < NS; ++q) {
+          if (q < tv.S) {
+            const TT *base = tab + q * sp_stride;
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+              if (mask & (1 << k)) {
+                const TT v = base[(int64_t)r.row[k] * pitch + kk];
+                if constexpr (kF64)
+                  slot[q][k] = (Real)v;
+                else
+                  slot[q][k] = to_float<TT>(v);
+              }
+            const Real y = r.w[0] * slot[q][0] + r.w[1] * slot[q][1] + r.w[2] * slot[q][2] +
+                           r.w[3] * slot[q][3];
+            if constexpr (kF64)
+              chi += r.a_s[q] * exp2(y);
+            else
+              chi = fmaf(r.a_s[q], fexp2(y), chi);
+          }
+        }
+        if (tv.n_cia > 0) {
+#pragma unroll
+          for (int q = 0; q < 2; ++q) {
+            const Real *cbase = cia + (int64_t)q * tv.nT * pitch;
+#pragma unroll
+            for (int k = 0; k < 2; ++k)
+              if (mask & (16 << k)) cslot[q][k] = cbase[(int64_t)r.cia_row[k] * pitch + kk];
+            const Real y = r.cia_w[0] * cslot[q][0] + r.cia_w[1] * cslot[q][1];
+            if constexpr (kF64)
+              chi += r.a_cia[q] * exp2(y);
+            else
+              chi = fmaf(r.a_cia[q], fexp2(y), chi);
+          }
+        }
+      }
+      Real S;
+      if constexpr (kF64)
+        S = planck_d(nu_d, c1nu3_d, r.T);
+      else
+        S = planck_f(nu_hi, nu_lo, c1nu3_f, r.pl_hi, r.pl_lo);
+      if (l == l0) {
+#pragma unroll
+        for (int k = 0; k < MAXMU; ++k) I[k] = (chunk == 0) ? S : (Real)0;
+      } else {
+        const Real dtau = (chi_prev + chi) * hdz_prev;
+        tau += dtau;
+        if constexpr (kF64) {
+#pragma unroll
+          for (int k = 0; k < MAXMU; ++k)
+            if (k < nmu) I[k] = sc_step_d(I[k], dtau, S, S_prev, c_ang.mu_d[nmu - 1][k]);
+        } else {
+          const float rdt = frcp(dtau);
+#pragma unroll
+          for (int k = 0; k < MAXMU; ++k)
+            if (k < nmu)
+              I[k] = sc_step_f(I[k], dtau, rdt, S, S_prev, c_ang.inv_mu[nmu - 1][k],
+                               c_ang.l2e_mu[nmu - 1][k], c_ang.mu[nmu - 1][k]);
+        }
+      }
+      chi_prev = chi;
+      S_prev = S;
+      hdz_prev = r.hdz;
+    }
+  }
+
+  Real F = (Real)0;
+  if (C == 1) {
+#pragma unroll
+    for (int k = 0; k < MAXMU; ++k)
+      if (k < nmu) {
+        if constexpr (kF64)
+          F += c_ang.cw_d[nmu - 1][k] * I[k];
+        else
+          F = fmaf(c_ang.cw[nmu - 1][k], I[k], F);
+      }
+  } else {
+    sh_tau[wave][lane] = tau;
+#pragma unroll
+    for (int k = 0; k < MAXMU; ++k) sh_B[wave][k][lane] = I[k];
+    __syncthreads();
+    if (chunk == C - 1) {
+      const int w0 = sub * C;
+#pragma unroll
+      for (int k = 0; k < MAXMU; ++k)
+        if (k < nmu) {
+          Real acc = sh_B[w0][k][lane];
+          for (int c = 1; c < C; ++c) {
+            Real tr;
+            if constexpr (kF64)
+              tr = exp(-sh_tau[w0 + c][lane] / c_ang.mu_d[nmu - 1][k]);
+            else
+              tr = fexp2(-sh_tau[w0 + c][lane] * c_ang.l2e_mu[nmu - 1][k]);
+            acc = tr * acc + sh_B[w0 + c][k][lane];
+          }
+          if constexpr (kF64)
+            F += c_ang.cw_d[nmu - 1][k] * acc;
+          else
+            F = fmaf(c_ang.cw[nmu - 1][k], acc, F);
+        }
+    }
+  }
+  if (active && chunk == C - 1) out[d.out_offset + (int64_t)s * d.out_stride + j] = F;
+}
+
+int column_nu_per_wg(int chunks) { return (4 / chunks) * 64; }
+
+template <typename Real, typename TT, int NS, int MAXMU, bool FROM_CHI>
+static hipError_t launch_column_t(const TableView &tv, const ColSeg *segs, int n_segs,
+                                  int64_t total_wgs, const void *recs, const void *chi_in,
+                                  void *out, hipStream_t stream) {
+  hipLaunchKernelGGL((k_column<Real, TT, NS, MAXMU, FROM_CHI>), dim3((unsigned)total_wgs),
+                     dim3(256), 0, stream, tv, segs, n_segs, total_wgs,
+                     (const typename RecOf<Real>::type *)recs, (const Real *)chi_in, (Real *)out);
+  return hipGetLastError();
+}
+
+template <typename Real, typename TT, bool FROM_CHI>
+static hipError_t launch_column_ns(const TableView &tv, const ColSeg *segs, int n_segs,
+                                   int64_t total_wgs, const void *recs, const void *chi_in,
+                                   void *out, int max_mu, hipStream_t stream) {
+  const int S = tv.S;
+  if constexpr (FROM_CHI) {
+    if (max_mu <= 4)
+      return launch_column_t<Real, TT, 1, 4, true>(tv, segs, n_segs, total_wgs, recs, chi_in, out,
+                                                   stream);
+    return launch_column_t<Real, TT, 1, 8, true>(tv, segs, n_segs, total_wgs, recs, chi_in, out,
+                                                 stream);
+  } else {
+    if (max_mu <= 4) {
+      if (S <= 1)
+        return launch_column_t<Real, TT, 1, 4, false>(tv, segs, n_segs, total_wgs, recs, chi_in,
+                                                      out, stream);
+      if (S <= 8)
+        return launch_column_t<Real, TT, 8, 4, false>(tv, segs, n_segs, total_wgs, recs, chi_in,
+                                                      out, stream);
+      return launch_column_t<Real, TT, kMaxSpecies, 4, false>(tv, segs, n_segs, total_wgs, recs,
+                                                              chi_in, out, stream);
+    }
+    if (S <= 1)
+      return launch_column_t<Real, TT, 1, 8, false>(tv, segs, n_segs, total_wgs, recs, chi_in,
+                                                    out, stream);
+    if (S <= 8)
+      return launch_column_t<Real, TT, 8, 8, false>(tv, segs, n_segs, total_wgs, recs, chi_in,
+                                                    out, stream);
+    return launch_column_t<Real, TT, kMaxSpecies, 8, false>(tv, segs, n_segs, total_wgs, recs,
+                                                            chi_in, out, stream);
+  }
+}
+
+hipError_t launch_column(const TableView &tv, const ColSeg *segs_dev, int n_segs,
+                         int64_t total_wgs, const void *recs, const void *chi_in, void *out,
+                         int max_mu, bool opacity_from_memory, hipStream_t stream) {
+  if (total_wgs <= 0) return hipSuccess;
+  if (opacity_from_memory) {
+    // stage 2 alone: the storage type is irrelevant
+    if (tv.dtype == HR2_TABLE_F64)
+      return launch_column_ns<double, double, true>(tv, segs_dev, n_segs, total_wgs, recs, chi_in,
+                                                    out, max_mu, stream);
+    return launch_column_ns<float, float, true>(tv, segs_dev, n_segs, total_wgs, recs, chi_in,
+                                                out, max_mu, stream);
+  }
+  switch (tv.dtype) {
+    case HR2_TABLE_F64:
+      return launch_column_ns<double, double, false>(tv, segs_dev, n_segs, total_wgs, recs,
+                                                     chi_in, out, max_mu, stream);
+    case HR2_TABLE_F16:
+      return launch_column_ns<float, _Float16, false>(tv, segs_dev, n_segs, total_wgs, recs,
+                                                      chi_in, out, max_mu, stream);
+    case HR2_TABLE_BF16:
+      return launch_column_ns<float, uint16_t, false>(tv, segs_dev, n_segs, total_wgs, recs,
+                                                      chi_in, out, max_mu, stream);
+    default:
+      return launch_column_ns<float, float, false>(tv, segs_dev, n_segs, total_wgs, recs, chi_in,
+                                                   out, max_mu, stream);
+  }
+}
+
+// ------------------------------------------------------- stage 1 on its own
+// chi_l(nu) for every (level, window point): one thread each, the four
+// corner rows of the level's cell read directly (Sect. 2.3).
+template <typename Real, typename TT>
+__global__ __launch_bounds__(256) void k_opacity_only(TableView tv,
+                                                      const typename RecOf<Real>::type *recs,
+                                                      int64_t nu_begin, int64_t nu_count,
+                                                      int64_t nu_stride, Real *chi) {
+  constexpr bool kF64 = std::is_same<Real, double>::value;
+  const int l = blockIdx.y;
+  const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (j >= nu_count) return;
+  const auto &r = recs[l];
+  const uint32_t kk = (uint32_t)(nu_begin + j * nu_stride);
+  const int64_t pitch = tv.pitch;
+  const int64_t sp_stride = (int64_t)tv.nT * tv.nP * pitch;
+  const TT *tab = (const TT *)tv.tab;
+  Real c = (Real)0;
+  for (int q = 0; q < tv.S; ++q) {
+    const TT *base = tab + q * sp_stride;
+    Real y = (Real)0;
+    for (int k = 0; k < 4; ++k) {
+      Real v;
+      if constexpr (kF64)
+        v = (Real)base[(int64_t)r.row[k] * pitch + kk];
+      else
+        v = to_float<TT>(base[(int64_t)r.row[k] * pitch + kk]);
+      y += r.w[k] * v;
+    }
+    if constexpr (kF64)
+      c += r.a_s[q] * exp2(y);
+    else
+      c = fmaf(r.a_s[q], fexp2(y), c);
+  }
+  const Real *cia = (const Real *)tv.cia;
+  for (int q = 0; q < tv.n_cia; ++q) {
+    const Real *cbase = cia + (int64_t)q * tv.nT * pitch;
+    const Real y = r.cia_w[0] * cbase[(int64_t)r.cia_row[0] * pitch + kk] +
+                   r.cia_w[1] * cbase[(int64_t)r.cia_row[1] * pitch + kk];
+    if constexpr (kF64)
+      c += r.a_cia[q] * exp2(y);
+    else
+      c = fmaf(r.a_cia[q], fexp2(y), c);
+  }
+  chi[(int64_t)l * nu_count + j] = c;
+}
+
+hipError_t launch_opacity_only(const TableView &tv, const void *recs, int n_levels,
+                               int64_t nu_begin, int64_t nu_count, int64_t nu_stride, void *chi,
+                               hipStream_t stream) {
+  const dim3 grid((unsigned)((nu_count + 255) / 256), (unsigned)n_levels);
+  switch (tv.dtype) {
+    case HR2_TABLE_F64:
+      hipLaunchKernelGGL((k_opacity_only<double, double>), grid, dim3(256), 0, stream, tv,
+                         (const LevelRecD *)recs, nu_begin, nu_count, nu_stride, (double *)chi);
+      break;
+    case HR2_TABLE_F16:
+      hipLaunchKernelGGL((k_opacity_only<float, _Float16>), grid, dim3(256), 0, stream, tv,
+                         (const LevelRecF *)recs, nu_begin, nu_count, nu_stride, (float *)chi);
+      break;
+    case HR2_TABLE_BF16:
+      hipLaunchKernelGGL((k_opacity_only<float, uint16_t>), grid, dim3(256), 0, stream, tv,
+                         (const LevelRecF *)recs, nu_begin, nu_count, nu_stride, (float *)chi);
+      break;
+    default:
+      hipLaunchKernelGGL((k_opacity_only<float, float>), grid, dim3(256), 0, stream, tv,
+                         (const LevelRecF *)recs, nu_begin, nu_count, nu_stride, (float *)chi);
+  }
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------ convolution + bins
+// One wave per (set, bin): bin_j = scale * sum_m K_j[m] F+[m] over the
+// bin's support (Eq. 9, 17 and the binning, composed into one banded row per
+// bin).  Lane-strided partial sums then a fixed butterfly: the result does
+// not depend on what else is in the launch.
+template <typename Real>
+__global__ __launch_bounds__(256) void k_convolve_bin(const ConvSeg *__restrict__ segs,
+                                                      int n_segs, int64_t total_waves,
+                                                      const Real *__restrict__ in,
+                                                      Real *__restrict__ out) {
+  const int64_t wv = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (wv >= total_waves) return;
+  int sg = 0;
+  for (int i = 1; i < n_segs; ++i)
+    if (segs[i].wave_begin <= wv) sg = i;
+  const ConvSeg &d = segs[sg];
+  const int64_t local = wv - d.wave_begin;
+  const int s = (int)(local / d.n_bins);
+  const int jb = (int)(local - (int64_t)s * d.n_bins);
+  const Real *K = (const Real *)d.K + d.kstart[jb];
+  const int len = d.mlen[jb];
+  const Real *F = in + d.in_offset + (int64_t)s * d.in_stride + d.mlo[jb];
+  Real acc = (Real)0;
+  for (int q = lane; q < len; q += 64) acc += K[q] * F[q];
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+  if (lane == 0) {
+    const double sc = d.scale ? d.scale[s] : d.scale_const;
+    out[d.out_offset + (int64_t)s * d.n_bins + jb] = acc * (Real)sc;
+  }
+}
+
+hipError_t launch_convolve_bin(bool fp64, const ConvSeg *segs_dev, int n_segs,
+                               int64_t total_waves, const void *in, void *out,
+                               hipStream_t stream) {
+  if (total_waves <= 0) return hipSuccess;
+  const dim3 grid((unsigned)((total_waves + 3) / 4));
+  if (fp64)
+    hipLaunchKernelGGL(k_convolve_bin<double>, grid, dim3(256), 0, stream, segs_dev, n_segs,
+                       total_waves, (const double *)in, (double *)out);
+  else
+    hipLaunchKernelGGL(k_convolve_bin<float>, grid, dim3(256), 0, stream, segs_dev, n_segs,
+                       total_waves, (const float *)in, (float *)out);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------ observation layout build
+// Eq. 17 with the 5 sigma cut: for window point i, sigma_i = nu_i / (R 2
+// sqrt(2 ln 2)), h_i = the largest k with k dnu <= 5 sigma_i (host-computed),
+// g_i(k) = exp(-(k dnu)^2 / (2 sigma_i^2)), Z_i = sum of g_i over the
+// window.  Then per bin j with edges a < b: K_j(x) = 1/(b - a) *
+// sum_{i=a}^{b} c_i g_i(x - i) / Z_i, c_i = 1/2 at i = a, b and 1 inside
+// (trapezoid rule over the bin's points, divided by its width).
+template <typename Real>
+__global__ __launch_bounds__(256) void k_obs_norm(int64_t N, double nu_first, double dnu,
+                                                  double R, const int32_t *h, int64_t i0,
+                                                  int64_t n, Real *q_out, Real *invz_out) {
+  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (t >= n) return;
+  const int64_t i = i0 + t;
+  const double sig = (nu_first + (double)i * dnu) / (R * 2.0 * sqrt(2.0 * log(2.0)));
+  const int hi = h[t];
+  int64_t klo = -hi, khi = hi;
+  if (i + klo < 0) klo = -i;
+  if (i + khi > N - 1) khi = N - 1 - i;
+  if constexpr (std::is_same<Real, double>::value) {
+    double z = 0.0;
+    for (int64_t k = klo; k <= khi; ++k) {
+      const double dx = (double)(k < 0 ? -k : k) * dnu;
+      z += exp(-dx * dx / (2.0 * sig * sig));
+    }
+    q_out[t] = 1.0 / (2.0 * sig * sig);
+    invz_out[t] = 1.0 / z;
+  } else {
+    const float q = (float)(dnu * dnu * kLog2e / (2.0 * sig * sig));
+    float z = 0.0f;
+    for (int64_t k = klo; k <= khi; ++k) {
+      const float kf = (float)k;
+      z += fexp2(-(kf * kf) * q);
+    }
+    q_out[t] = q;
+    invz_out[t] = 1.0f / z;
+  }
+}
+
+template <typename Real>
+__global__ __launch_bounds__(256) void k_obs_weights(const int64_t *edge_idx, const int32_t *h,
+                                                     int64_t i0, const Real *q, const Real *invz,
+                                                     double dnu, const int64_t *kstart,
+                                                     const int32_t *mlo, const int32_t *mlen,
+                                                     Real *K) {
+  const int jb = blockIdx.x;
+  const int64_t a = edge_idx[jb], b = edge_idx[jb + 1];
+  const int64_t lo = mlo[jb];
+  const int len = mlen[jb];
+  const int hmax = h[b - i0] > h[a - i0] ? h[b - i0] : h[a - i0];
+  const Real coef = (Real)(1.0 / (double)(b - a));
+  for (int xo = threadIdx.x; xo < len; xo += 256) {
+    const int64_t x = lo + xo;
+    int64_t ia = x - hmax, ib = x + hmax;
+    if (ia < a) ia = a;
+    if (ib > b) ib = b;
+    Real acc = (Real)0;
+    for (int64_t i = ia; i <= ib; ++i) {
+      const int64_t k = x - i;
+      const int64_t ak = k < 0 ? -k : k;
+      if (ak > h[i - i0]) continue;
+      const Real ci = (i == a || i == b) ? (Real)0.5 : (Real)1;
+      Real gk;
+      if constexpr (std::is_same<Real, double>::value) {
+        const double dx = (double)ak * dnu;
+        gk = exp(-dx * dx * q[i - i0]);
+      } else {
+        const float kf = (float)ak;
+        gk = fexp2(-(kf * kf) * q[i - i0]);
+      }
+      acc += ci * gk * invz[i - i0];
+    }
+    K[kstart[jb] + xo] = acc * coef;
+  }
+}
+
+hipError_t launch_obs_build(bool fp64, int64_t N, double nu_first, double dnu_eff, double R,
+                            int n_bins, const int64_t *edge_idx_dev, const int32_t *h_dev,
+                            int64_t i0, int64_t n_pts, void *q_scratch, void *invz_scratch,
+                            const int64_t *kstart_dev, const int32_t *mlo_dev,
+                            const int32_t *mlen_dev, void *K_dev, hipStream_t stream) {
+  const dim3 g1((unsigned)((n_pts + 255) / 256));
+  if (fp64) {
+    hipLaunchKernelGGL(k_obs_norm<double>, g1, dim3(256), 0, stream, N, nu_first, dnu_eff, R,
+                       h_dev, i0, n_pts, (double *)q_scratch, (double *)invz_scratch);
+    hipLaunchKernelGGL(k_obs_weights<double>, dim3(n_bins), dim3(256), 0, stream, edge_idx_dev,
+                       h_dev, i0, (const double *)q_scratch, (const double *)invz_scratch,
+                       dnu_eff, kstart_dev, mlo_dev, mlen_dev, (double *)K_dev);
+  } else {
+    hipLaunchKernelGGL(k_obs_norm<float>, g1, dim3(256), 0, stream, N, nu_first, dnu_eff, R,
+                       h_dev, i0, n_pts, (float *)q_scratch, (float *)invz_scratch);
+    hipLaunchKernelGGL(k_obs_weights<float>, dim3(n_bins), dim3(256), 0, stream, edge_idx_dev,
+                       h_dev, i0, (const float *)q_scratch, (const float *)invz_scratch, dnu_eff,
+                       kstart_dev, mlo_dev, mlen_dev, (float *)K_dev);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace hr2

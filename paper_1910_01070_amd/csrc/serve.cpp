@@ -1,0 +1,610 @@
+// serve.cpp — continuous batching of uneven forward-model requests.
+//
+// A scheduler thread owns two streams and a device arena of the server's
+// byte budget.  Requests are admitted first-in first-out while their
+// footprint fits the arena and a slot is free; each step launches the work
+// of every admitted, not yet launched request: per-request level records
+// and layout builds, then ONE column-kernel launch and ONE convolve/bin
+// launch over all of them (one segment per request), then the bins are
+// copied to pinned host memory.  Up to two steps are in flight, one per
+// stream, so a step admitted while another runs overlaps it on the device.
+// Per-set arithmetic does not depend on the other requests of a step (the
+// layer-chunk count is a function of the request alone), so a result is
+// bit-identical alone and in the mix.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <ctime>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "hr2_context.h"
+#include "hr2_internal.h"
+
+using namespace hr2;
+
+namespace {
+
+double now_s() {
+  timespec ts;
+  clock_gettime(CLOCK_MONOTONIC, &ts);
+  return (double)ts.tv_sec + 1e-9 * (double)ts.tv_nsec;
+}
+
+size_t round256(size_t n) { return (n + 255) & ~size_t(255); }
+
+// First-fit allocator over [0, cap) in 256-byte units.
+class Arena {
+ public:
+  explicit Arena(size_t cap = 0) { reset(cap); }
+  void reset(size_t cap) {
+    free_.clear();
+    cap_ = cap;
+    used_ = 0;
+    if (cap) free_[0] = cap;
+  }
+  bool alloc(size_t n, size_t *off) {
+    n = round256(n);
+    for (auto it = free_.begin(); it != free_.end(); ++it) {
+      if (it->second < n) continue;
+      *off = it->first;
+      const size_t rest = it->second - n, start = it->first + n;
+      free_.erase(it);
+      if (rest) free_[start] = rest;
+      used_ += n;
+      return true;
+    }
+    return false;
+  }
+  void release(size_t off, size_t n) {
+    n = round256(n);
+    used_ -= n;
+    auto it = free_.emplace(off, n).first;
+    auto nx = std::next(it);
+    if (nx != free_.end() && it->first + it->second == nx->first) {
+      it->second += nx->second;
+      free_.erase(nx);
+    }
+    if (it != free_.begin()) {
+      auto pv = std::prev(it);
+      if (pv->first + pv->second == it->first) {
+        pv->second += it->second;
+        free_.erase(it);
+      }
+    }
+  }
+  size_t used() const { return used_; }
+  size_t cap() const { return cap_; }
+
+ private:
+  std::map<size_t, size_t> free_;
+  size_t cap_ = 0, used_ = 0;
+};
+
+struct Req {
+  uint64_t ticket = 0;
+  hr2_request_info info{};
+  hr2_window window{};
+  int n_bins = 0, n_sets = 0, L = 0, n_mu = 0, chunks = 1;
+  std::vector<double> cols;   // packed p, T, x, log g, scale
+  ObsPlan plan;
+  // byte offsets inside the request's device block; [0, upload) is copied
+  // from the pinned image at launch
+  size_t o_cols = 0, o_kstart = 0, o_mlo = 0, o_mlen = 0, o_edges = 0, o_h = 0, upload = 0;
+  size_t o_recs = 0, o_fplus = 0, o_bins = 0, o_K = 0, o_q = 0, o_z = 0, bytes = 0;
+  size_t bins_bytes = 0, pin_bytes = 0;
+  size_t dev_off = 0, pin_off = 0;
+  bool admitted = false;
+  std::vector<unsigned char> result;
+};
+
+struct StepSlot {
+  hipStream_t stream = nullptr;
+  hipEvent_t done = nullptr;
+  DevBuf desc;                 // ColSeg[] then ConvSeg[]
+  void *pinned = nullptr;      // host image of the descriptors
+  size_t pinned_cap = 0;
+  std::vector<Req *> reqs;
+  bool busy = false;
+  uint64_t seq = 0;
+};
+
+}  // namespace
+
+struct hr2_server {
+  hr2_ctx *ctx = nullptr;
+  const hr2_tables *tables = nullptr;
+  size_t budget = 0;
+  int max_slots = 1;
+  void *arena_dev = nullptr;
+  void *arena_pin = nullptr;
+  size_t pin_cap = 0;
+  Arena dev, pin;
+  StepSlot slots[2];
+  uint64_t step_seq = 0;
+
+  std::mutex mu;
+  std::condition_variable cv_work;   // wakes the scheduler
+  std::condition_variable cv_done;   // wakes waiters
+  std::deque<Req *> pending;         // submitted, not admitted
+  std::vector<Req *> admitted;       // admitted, not launched
+  std::unordered_map<uint64_t, std::unique_ptr<Req>> all;
+  uint64_t next_ticket = 1;
+  int n_admitted = 0;                // admitted and not finished
+  bool stop = false;
+  bool fail_next = false;
+  hr2_serve_stats stats{};
+  std::thread thr;
+
+  void run();
+  void finish_step(StepSlot &sl);
+  void release(Req *r);
+  bool launch_step(StepSlot &sl, std::vector<Req *> &reqs);
+};
+
+namespace {
+
+size_t real_bytes(const hr2_tables *t) {
+  return t->view.dtype == HR2_TABLE_F64 ? sizeof(double) : sizeof(float);
+}
+size_t rec_bytes(const hr2_tables *t) {
+  return t->view.dtype == HR2_TABLE_F64 ? sizeof(LevelRecD) : sizeof(LevelRecF);
+}
+
+void layout_request(const hr2_tables *t, Req &r) {
+  const size_t rs = real_bytes(t);
+  size_t o = 0;
+  auto take = [&o](size_t n) {
+    const size_t at = o;
+    o += round256(std::max<size_t>(n, 1));
+    return at;
+  };
+  const int S = t->view.S;
+  r.o_cols = take(r.cols.size() * sizeof(double));
+  r.o_kstart = take(r.n_bins * sizeof(int64_t));
+  r.o_mlo = take(r.n_bins * sizeof(int32_t));
+  r.o_mlen = take(r.n_bins * sizeof(int32_t));
+  r.o_edges = take((r.n_bins + 1) * sizeof(int64_t));
+  r.o_h = take(r.plan.n_pts * sizeof(int32_t));
+  r.upload = o;
+  r.o_recs = take((size_t)r.n_sets * r.L * rec_bytes(t));
+  r.o_fplus = take((size_t)r.n_sets * r.window.nu_count * rs);
+  r.bins_bytes = (size_t)r.n_sets * r.n_bins * rs;
+  r.o_bins = take(r.bins_bytes);
+  r.o_K = take((size_t)r.plan.nnz * rs);
+  r.o_q = take((size_t)r.plan.n_pts * rs);
+  r.o_z = take((size_t)r.plan.n_pts * rs);
+  r.bytes = o;
+  r.pin_bytes = round256(r.upload) + round256(r.bins_bytes);
+  (void)S;
+}
+
+void fill_upload_image(const Req &r, unsigned char *img) {
+  std::memset(img, 0, r.upload);
+  std::memcpy(img + r.o_cols, r.cols.data(), r.cols.size() * sizeof(double));
+  std::memcpy(img + r.o_kstart, r.plan.kstart.data(), r.n_bins * sizeof(int64_t));
+  std::memcpy(img + r.o_mlo, r.plan.mlo.data(), r.n_bins * sizeof(int32_t));
+  std::memcpy(img + r.o_mlen, r.plan.mlen.data(), r.n_bins * sizeof(int32_t));
+  std::memcpy(img + r.o_edges, r.plan.idx.data(), (r.n_bins + 1) * sizeof(int64_t));
+  std::memcpy(img + r.o_h, r.plan.h.data(), r.plan.n_pts * sizeof(int32_t));
+}
+
+}  // namespace
+
+// ------------------------------------------------------------- scheduler
+void hr2_server::release(Req *r) {
+  if (r->admitted) {
+    dev.release(r->dev_off, r->bytes);
+    pin.release(r->pin_off, r->pin_bytes);
+    r->admitted = false;
+    --n_admitted;
+  }
+}
+
+bool hr2_server::launch_step(StepSlot &sl, std::vector<Req *> &reqs) {
+  const TableView &tv = tables->view;
+  const bool fp64 = tv.dtype == HR2_TABLE_F64;
+  const size_t rs = real_bytes(tables), rb = rec_bytes(tables);
+  hipStream_t s = sl.stream;
+  unsigned char *base = (unsigned char *)arena_dev;
+  unsigned char *pbase = (unsigned char *)arena_pin;
+  if (hipSetDevice(ctx->device) != hipSuccess) return false;
+  std::vector<ColSeg> cs(reqs.size());
+  std::vector<ConvSeg> vs(reqs.size());
+  int64_t wg = 0, waves = 0;
+  int max_mu = 1;
+  for (size_t i = 0; i < reqs.size(); ++i) {
+    Req &r = *reqs[i];
+    unsigned char *blk = base + r.dev_off;
+    if (hipMemcpyAsync(blk, pbase + r.pin_off, r.upload, hipMemcpyHostToDevice, s) != hipSuccess)
+      return false;
+    const ColumnsView cv = columns_view(blk + r.o_cols, r.n_sets, r.L, tv.S);
+    if (launch_levels(tv, cv, blk + r.o_recs, nullptr, fp64, s) != hipSuccess) return false;
+    if (launch_obs_build(fp64, r.plan.N, r.plan.first, r.plan.dnu, r.plan.R, r.n_bins,
+                         (const int64_t *)(blk + r.o_edges), (const int32_t *)(blk + r.o_h),
+                         r.plan.i0, r.plan.n_pts, blk + r.o_q, blk + r.o_z,
+                         (const int64_t *)(blk + r.o_kstart), (const int32_t *)(blk + r.o_mlo),
+                         (const int32_t *)(blk + r.o_mlen), blk + r.o_K, s) != hipSuccess)
+      return false;
+    ColSeg &c = cs[i];
+    std::memset(&c, 0, sizeof(c));
+    const int per_wg = column_nu_per_wg(r.chunks);
+    c.wg_begin = wg;
+    c.nu_begin = r.window.nu_begin;
+    c.nu_count = r.window.nu_count;
+    c.nu_stride = r.window.nu_stride;
+    c.rec_offset = (int64_t)((r.dev_off + r.o_recs) / rb);
+    c.out_offset = (int64_t)((r.dev_off + r.o_fplus) / rs);
+    c.out_stride = r.window.nu_count;
+    c.n_sets = r.n_sets;
+    c.n_levels = r.L;
+    c.n_mu = r.n_mu;
+    c.chunks = r.chunks;
+    c.tiles_per_set = (int32_t)((r.window.nu_count + per_wg - 1) / per_wg);
+    wg += (int64_t)r.n_sets * c.tiles_per_set;
+    max_mu = std::max(max_mu, r.n_mu);
+    ConvSeg &v = vs[i];
+    std::memset(&v, 0, sizeof(v));
+    v.wave_begin = waves;
+    v.K = blk + r.o_K;
+    v.kstart = (const int64_t *)(blk + r.o_kstart);
+    v.mlo = (const int32_t *)(blk + r.o_mlo);
+    v.mlen = (const int32_t *)(blk + r.o_mlen);
+    v.in_offset = c.out_offset;
+    v.in_stride = r.window.nu_count;
+    v.out_offset = (int64_t)((r.dev_off + r.o_bins) / rs);
+    v.scale = cv.scale;
+    v.n_sets = r.n_sets;
+    v.n_bins = r.n_bins;
+    waves += (int64_t)r.n_sets * r.n_bins;
+  }
+  if (wg > 0x7fffffff) return false;
+  const size_t bytes_c = cs.size() * sizeof(ColSeg), bytes_v = vs.size() * sizeof(ConvSeg);
+  const size_t total = round256(bytes_c) + bytes_v;
+  if (sl.desc.ensure(total) != HR2_OK) return false;
+  if (sl.pinned_cap < total) {
+    if (sl.pinned) (void)hipHostFree(sl.pinned);
+    sl.pinned = nullptr;
+    if (hipHostMalloc(&sl.pinned, total, hipHostMallocDefault) != hipSuccess) return false;
+    sl.pinned_cap = total;
+  }
+  std::memcpy(sl.pinned, cs.data(), bytes_c);
+  std::memcpy((unsigned char *)sl.pinned + round256(bytes_c), vs.data(), bytes_v);
+  if (hipMemcpyAsync(sl.desc.ptr, sl.pinned, total, hipMemcpyHostToDevice, s) != hipSuccess)
+    return false;
+  const ColSeg *dcs = (const ColSeg *)sl.desc.ptr;
+  const ConvSeg *dvs = (const ConvSeg *)((unsigned char *)sl.desc.ptr + round256(bytes_c));
+  if (launch_column(tv, dcs, (int)cs.size(), wg, base, nullptr, base, max_mu, false, s) !=
+      hipSuccess)
+    return false;
+  if (launch_convolve_bin(fp64, dvs, (int)vs.size(), waves, base, base, s) != hipSuccess)
+    return false;
+  for (Req *r : reqs)
+    if (hipMemcpyAsync(pbase + r->pin_off + round256(r->upload), base + r->dev_off + r->o_bins,
+                       r->bins_bytes, hipMemcpyDeviceToHost, s) != hipSuccess)
+      return false;
+  return hipEventRecord(sl.done, s) == hipSuccess;
+}
+
+void hr2_server::finish_step(StepSlot &sl) {
+  // called with mu held, after sl.done completed
+  const hipError_t e = hipEventQuery(sl.done);
+  const double t = now_s();
+  for (Req *r : sl.reqs) {
+    if (e == hipSuccess) {
+      const unsigned char *src = (const unsigned char *)arena_pin + r->pin_off + round256(r->upload);
+      r->result.assign(src, src + r->bins_bytes);
+      r->info.state = HR2_REQ_DONE;
+      r->info.error = HR2_OK;
+      ++stats.requests_done;
+    } else {
+      r->info.state = HR2_REQ_ERROR;
+      r->info.error = HR2_E_DEVICE;
+      ++stats.requests_failed;
+    }
+    r->info.t_done = t;
+    release(r);
+  }
+  sl.reqs.clear();
+  sl.busy = false;
+  cv_done.notify_all();
+}
+
+void hr2_server::run() {
+  (void)hipSetDevice(ctx->device);
+  std::unique_lock<std::mutex> lk(mu);
+  for (;;) {
+    // retire finished steps, oldest first
+    for (;;) {
+      StepSlot *oldest = nullptr;
+      for (auto &sl : slots)
+        if (sl.busy && (!oldest || sl.seq < oldest->seq)) oldest = &sl;
+      if (!oldest) break;
+      const hipError_t q = hipEventQuery(oldest->done);
+      if (q == hipErrorNotReady) break;
+      finish_step(*oldest);
+    }
+    if (stop) {
+      for (Req *r : pending) {
+        r->info.state = HR2_REQ_CANCELLED;
+        r->info.error = HR2_E_CANCELLED;
+        r->info.t_done = now_s();
+      }
+      pending.clear();
+      for (Req *r : admitted) {
+        r->info.state = HR2_REQ_CANCELLED;
+        r->info.error = HR2_E_CANCELLED;
+        r->info.t_done = now_s();
+        release(r);
+      }
+      admitted.clear();
+      cv_done.notify_all();
+      bool any = false;
+      for (auto &sl : slots) any |= sl.busy;
+      if (!any) break;
+    }
+    // admit first-in first-out while memory and slots allow
+    while (!stop && !pending.empty() && n_admitted < max_slots) {
+      Req *r = pending.front();
+      size_t doff, poff;
+      if (!dev.alloc(r->bytes, &doff)) break;
+      if (!pin.alloc(r->pin_bytes, &poff)) {
+        dev.release(doff, r->bytes);
+        break;
+      }
+      r->dev_off = doff;
+      r->pin_off = poff;
+      r->admitted = true;
+      ++n_admitted;
+      stats.peak_bytes = std::max(stats.peak_bytes, dev.used());
+      stats.max_inflight = std::max<uint64_t>(stats.max_inflight, (uint64_t)n_admitted);
+      r->info.t_admit = now_s();
+      r->info.state = HR2_REQ_RUNNING;
+      fill_upload_image(*r, (unsigned char *)arena_pin + poff);
+      pending.pop_front();
+      admitted.push_back(r);
+    }
+    // launch a step on a free slot
+    StepSlot *free_slot = nullptr;
+    for (auto &sl : slots)
+      if (!sl.busy) free_slot = &sl;
+    if (!stop && !admitted.empty() && free_slot) {
+      std::vector<Req *> reqs;
+      reqs.swap(admitted);
+      StepSlot &sl = *free_slot;
+      sl.busy = true;
+      sl.seq = ++step_seq;
+      sl.reqs = reqs;
+      ++stats.steps;
+      if (fail_next) {
+        // injected failure: nothing is enqueued for this step
+        fail_next = false;
+        const double t = now_s();
+        for (Req *r : reqs) {
+          r->info.state = HR2_REQ_ERROR;
+          r->info.error = HR2_E_DEVICE;
+          r->info.t_done = t;
+          ++stats.requests_failed;
+          release(r);
+        }
+        sl.reqs.clear();
+        sl.busy = false;
+        cv_done.notify_all();
+        continue;
+      }
+      lk.unlock();
+      const bool ok = launch_step(sl, reqs);
+      if (!ok) {
+        (void)hipGetLastError();
+        (void)hipStreamSynchronize(sl.stream);
+      }
+      lk.lock();
+      if (!ok) {
+        const double t = now_s();
+        for (Req *r : sl.reqs) {
+          r->info.state = HR2_REQ_ERROR;
+          r->info.error = HR2_E_DEVICE;
+          r->info.t_done = t;
+          ++stats.requests_failed;
+          release(r);
+        }
+        sl.reqs.clear();
+        sl.busy = false;
+        cv_done.notify_all();
+      }
+      continue;
+    }
+    // nothing to launch: wait for a submission or for the device
+    bool any_busy = false;
+    for (auto &sl : slots) any_busy |= sl.busy;
+    if (any_busy) {
+      StepSlot *oldest = nullptr;
+      for (auto &sl : slots)
+        if (sl.busy && (!oldest || sl.seq < oldest->seq)) oldest = &sl;
+      if (!free_slot || (pending.empty() && admitted.empty())) {
+        // block on the device (no new step could start anyway)
+        hipEvent_t ev = oldest->done;
+        lk.unlock();
+        (void)hipEventSynchronize(ev);
+        lk.lock();
+      } else {
+        cv_work.wait_for(lk, std::chrono::microseconds(50));
+      }
+    } else if (!stop) {
+      cv_work.wait(lk, [this] { return stop || !pending.empty(); });
+    }
+  }
+}
+
+// ------------------------------------------------------------------ C ABI
+extern "C" hr2_status hr2_serve_create(hr2_ctx *ctx, const hr2_tables *t, size_t budget,
+                                       int max_slots, hr2_server **out) {
+  if (!ctx || !t || !out) return set_error(HR2_E_INVALID_ARG, "NULL argument");
+  *out = nullptr;
+  if (budget < 4096) return set_error(HR2_E_INVALID_ARG, "budget must be at least 4096 bytes");
+  if (max_slots < 1) return set_error(HR2_E_INVALID_ARG, "max_slots must be >= 1");
+  if (hipSetDevice(ctx->device) != hipSuccess) return set_error(HR2_E_DEVICE, "hipSetDevice");
+  auto *srv = new hr2_server();
+  srv->ctx = ctx;
+  srv->tables = t;
+  srv->budget = round256(budget);
+  srv->max_slots = max_slots;
+  // pinned staging: inputs and results of the admitted requests
+  srv->pin_cap = std::min<size_t>(std::max<size_t>(srv->budget / 4, size_t(1) << 20), size_t(1) << 30);
+  hipError_t e = hipMalloc(&srv->arena_dev, srv->budget);
+  if (e == hipSuccess) e = hipHostMalloc(&srv->arena_pin, srv->pin_cap, hipHostMallocDefault);
+  for (auto &sl : srv->slots) {
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&sl.done, hipEventDisableTiming);
+  }
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    if (srv->arena_dev) (void)hipFree(srv->arena_dev);
+    if (srv->arena_pin) (void)hipHostFree(srv->arena_pin);
+    for (auto &sl : srv->slots) {
+      if (sl.stream) (void)hipStreamDestroy(sl.stream);
+      if (sl.done) (void)hipEventDestroy(sl.done);
+    }
+    delete srv;
+    return set_error(e == hipErrorOutOfMemory ? HR2_E_NO_MEMORY : HR2_E_DEVICE,
+                     std::string("server setup: ") + hipGetErrorString(e));
+  }
+  srv->dev.reset(srv->budget);
+  srv->pin.reset(srv->pin_cap);
+  srv->thr = std::thread([srv] { srv->run(); });
+  *out = srv;
+  return HR2_OK;
+}
+
+extern "C" hr2_status hr2_serve_submit(hr2_server *srv, const hr2_request *q, uint64_t *ticket) {
+  if (!srv || !q || !ticket) return set_error(HR2_E_INVALID_ARG, "NULL argument");
+  const hr2_tables *t = srv->tables;
+  if (q->n_sets < 1 || !q->cols) return set_error(HR2_E_INVALID_ARG, "request needs columns");
+  hr2_status st = check_n_mu(q->n_mu);
+  if (st != HR2_OK) return st;
+  for (int i = 0; i < q->n_sets; ++i)
+    if ((st = check_column(t, q->cols[i], q->cols[0].n_levels)) != HR2_OK) return st;
+  auto r = std::make_unique<Req>();
+  if ((st = plan_obs(t, q->window, q->resolving_power, q->n_bins, q->bin_edges_cm, r->plan)) !=
+      HR2_OK)
+    return st;
+  r->window = q->window;
+  r->n_bins = q->n_bins;
+  r->n_sets = q->n_sets;
+  r->L = q->cols[0].n_levels;
+  r->n_mu = q->n_mu;
+  r->chunks = auto_chunks((int64_t)r->n_sets * ((r->window.nu_count + 63) / 64), r->L);
+  pack_columns(t, q->n_sets, q->cols, r->cols);
+  layout_request(t, *r);
+  if (r->bytes > srv->budget)
+    return set_error(HR2_E_NO_MEMORY, "request needs " + std::to_string(r->bytes) +
+                                          " device bytes, budget is " + std::to_string(srv->budget));
+  if (r->pin_bytes > srv->pin_cap)
+    return set_error(HR2_E_NO_MEMORY, "request exceeds the pinned staging of the server");
+  r->info.state = HR2_REQ_PENDING;
+  r->info.t_submit = now_s();
+  r->info.n_bins = r->n_bins;
+  r->info.n_sets = r->n_sets;
+  {
+    std::lock_guard<std::mutex> lk(srv->mu);
+    if (srv->stop) return set_error(HR2_E_CANCELLED, "server is shutting down");
+    r->ticket = srv->next_ticket++;
+    *ticket = r->ticket;
+    srv->pending.push_back(r.get());
+    srv->all.emplace(r->ticket, std::move(r));
+  }
+  srv->cv_work.notify_one();
+  return HR2_OK;
+}
+
+static hr2_status poll_locked(hr2_server *srv, uint64_t ticket, void *bins, size_t cap,
+                              hr2_request_info *info) {
+  auto it = srv->all.find(ticket);
+  if (it == srv->all.end()) return set_error(HR2_E_NOT_FOUND, "unknown or released ticket");
+  Req &r = *it->second;
+  if (info) *info = r.info;
+  switch (r.info.state) {
+    case HR2_REQ_PENDING:
+    case HR2_REQ_RUNNING:
+      return HR2_NOT_READY;
+    case HR2_REQ_DONE: {
+      const size_t elems = (size_t)r.n_sets * r.n_bins;
+      if (bins == nullptr || cap < elems)
+        return set_error(HR2_E_INVALID_ARG, "result buffer too small: need " + std::to_string(elems));
+      std::memcpy(bins, r.result.data(), r.result.size());
+      srv->all.erase(it);
+      return HR2_OK;
+    }
+    default: {
+      const hr2_status e = r.info.error;
+      srv->all.erase(it);
+      return set_error(e, e == HR2_E_CANCELLED ? "request cancelled" : "request failed");
+    }
+  }
+}
+
+extern "C" hr2_status hr2_serve_poll(hr2_server *srv, uint64_t ticket, void *bins, size_t cap,
+                                     hr2_request_info *info) {
+  if (!srv) return set_error(HR2_E_INVALID_ARG, "NULL server");
+  std::lock_guard<std::mutex> lk(srv->mu);
+  return poll_locked(srv, ticket, bins, cap, info);
+}
+
+extern "C" hr2_status hr2_serve_wait(hr2_server *srv, uint64_t ticket, double timeout_s,
+                                     void *bins, size_t cap, hr2_request_info *info) {
+  if (!srv) return set_error(HR2_E_INVALID_ARG, "NULL server");
+  std::unique_lock<std::mutex> lk(srv->mu);
+  const auto until = std::chrono::steady_clock::now() +
+                     std::chrono::duration_cast<std::chrono::steady_clock::duration>(
+                         std::chrono::duration<double>(std::max(0.0, timeout_s)));
+  srv->cv_done.wait_until(lk, until, [&] {
+    auto it = srv->all.find(ticket);
+    return it == srv->all.end() || it->second->info.state >= HR2_REQ_DONE;
+  });
+  return poll_locked(srv, ticket, bins, cap, info);
+}
+
+extern "C" hr2_status hr2_serve_debug_fail_next_step(hr2_server *srv) {
+  if (!srv) return set_error(HR2_E_INVALID_ARG, "NULL server");
+  std::lock_guard<std::mutex> lk(srv->mu);
+  srv->fail_next = true;
+  return HR2_OK;
+}
+
+extern "C" hr2_status hr2_serve_get_stats(hr2_server *srv, hr2_serve_stats *out) {
+  if (!srv || !out) return set_error(HR2_E_INVALID_ARG, "NULL argument");
+  std::lock_guard<std::mutex> lk(srv->mu);
+  *out = srv->stats;
+  return HR2_OK;
+}
+
+extern "C" void hr2_serve_destroy(hr2_server *srv) {
+  if (!srv) return;
+  {
+    std::lock_guard<std::mutex> lk(srv->mu);
+    srv->stop = true;
+  }
+  srv->cv_work.notify_all();
+  if (srv->thr.joinable()) srv->thr.join();
+  (void)hipSetDevice(srv->ctx->device);
+  for (auto &sl : srv->slots) {
+    if (sl.stream) {
+      (void)hipStreamSynchronize(sl.stream);
+      (void)hipStreamDestroy(sl.stream);
+    }
+    if (sl.done) (void)hipEventDestroy(sl.done);
+    sl.desc.release();
+    if (sl.pinned) (void)hipHostFree(sl.pinned);
+  }
+  if (srv->arena_dev) (void)hipFree(srv->arena_dev);
+  if (srv->arena_pin) (void)hipHostFree(srv->arena_pin);
+  delete srv;
+}

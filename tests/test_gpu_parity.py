@@ -1,0 +1,303 @@
+"""GPU parity: the HIP path against the FP64 oracle on the same seeded inputs.
+
+Tolerances (per spectrum, max relative error with a 1e-30 * max floor):
+FP64 tables -> 1e-12, FP32 tables -> 1e-5 (F+ and bins), FP16 tables ->
+1e-3 on bins against the FP64-source oracle.  Every call goes through the
+C ABI (ctypes binding)."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as wl
+from tests import hr2_testutil as tu
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from paper_1910_01070_amd import hr2  # noqa: E402
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    c = hr2.Context(0)
+    yield c
+    torch.cuda.synchronize()
+    c.close()
+
+
+def run_forward(ctx, tables, obs, cols, n_mu=3, chunks=0):
+    ctx.set_option(hr2.OPT_CHUNKS, chunks)
+    B = len(cols)
+    bins = torch.empty(B * obs.n_bins, dtype=tables.real, device="cuda")
+    fplus = torch.empty(B * obs.window.count, dtype=tables.real, device="cuda")
+    hr2.forward_batch(ctx, tables, obs, cols, n_mu, bins, fplus)
+    torch.cuda.synchronize()
+    return (bins.cpu().numpy().reshape(B, obs.n_bins).astype(np.float64),
+            fplus.cpu().numpy().reshape(B, obs.window.count).astype(np.float64))
+
+
+# ------------------------------------------------------------------- C1
+
+
+@pytest.mark.parametrize("dtype,tol", [("f64", 1e-12), ("f32", 1e-5)])
+def test_c1_full_chain(ctx, dtype, tol):
+    """C1: 1 absorber, 5x5 table, 2000 points, 20 layers, 3 angles, R=300, 50 bins."""
+    tab = tu.c1_table()
+    cols = wl.c1_columns()
+    spec = wl.c1_obs(tab)
+    say(f"C1 {dtype}: tables + layout")
+    T = hr2.Tables(ctx, tab, dtype)
+    obs = hr2.Obs(ctx, T, spec.window, spec.resolving_power, spec.edges_cm)
+    for chunks in (0, 1, 2, 4):
+        say(f"C1 {dtype}: forward, chunks={chunks}")
+        bins, fplus = run_forward(ctx, T, obs, cols, 3, chunks)
+        for s, col in enumerate(cols):
+            ref = oracle.forward(tab, col, spec.window, spec.resolving_power, spec.edges_cm, 3)
+            e_f, _ = tu.max_rel_err(fplus[s], ref["fplus"])
+            e_b, _ = tu.max_rel_err(bins[s], ref["bins"])
+            say(f"  set {s}: F+ {e_f:.2e} bins {e_b:.2e}")
+            assert e_f <= tol and e_b <= tol, (dtype, chunks, s, e_f, e_b)
+
+
+@pytest.mark.parametrize("dtype,tol", [("f64", 1e-12), ("f32", 1e-5)])
+def test_stage_calls(ctx, dtype, tol):
+    """hr2_opacity, hr2_rt_emission and hr2_convolve_bin one at a time, each
+    fed the oracle's previous stage."""
+    tab = tu.small_multi_table()
+    col = tu.small_columns(tab, 1, seed=3)[0]
+    w = wl.Window(7, 2900, 1)
+    T = hr2.Tables(ctx, tab, dtype)
+    L = col.n_levels
+    say(f"stage calls {dtype}: opacity")
+    chi = torch.empty(L * w.count, dtype=T.real, device="cuda")
+    hr2.opacity(ctx, T, col, w, chi)
+    torch.cuda.synchronize()
+    chi_ref = oracle.opacity(tab, col, oracle.window_indices(w))
+    e, _ = tu.max_rel_err(chi.cpu().numpy().reshape(L, w.count), chi_ref)
+    say(f"  chi {e:.2e}")
+    assert e <= tol
+    say(f"stage calls {dtype}: rt_emission from the oracle's chi")
+    chi_in = torch.from_numpy(chi_ref.astype(np.float64 if dtype == "f64" else np.float32)).cuda()
+    fplus = torch.empty(w.count, dtype=T.real, device="cuda")
+    for n_mu in (1, 2, 3, 5, 8):
+        hr2.rt_emission(ctx, T, col, w, chi_in.reshape(-1), n_mu, fplus)
+        torch.cuda.synchronize()
+        st = oracle.column_state(tab, col)
+        nu = tab.nu0_cm + oracle.window_indices(w) * tab.dnu_cm
+        ref = oracle.rt_emission(chi_ref, st["dz"], col.T_K, nu, n_mu)
+        e, _ = tu.max_rel_err(fplus.cpu().numpy(), ref)
+        say(f"  n_mu={n_mu}: F+ {e:.2e}")
+        assert e <= tol
+    say(f"stage calls {dtype}: convolve_bin from the oracle's F+")
+    edges = wl.snapped_edges(tab, w, wl.log_edges(2030.0, 3430.0, 37))
+    obs = hr2.Obs(ctx, T, w, 250.0, edges)
+    ref_f = oracle.rt_emission(chi_ref, oracle.column_state(tab, col)["dz"], col.T_K,
+                               tab.nu0_cm + oracle.window_indices(w) * tab.dnu_cm, 3)
+    fin = torch.from_numpy(ref_f.astype(np.float64 if dtype == "f64" else np.float32)).cuda()
+    bins = torch.empty(obs.n_bins, dtype=T.real, device="cuda")
+    hr2.convolve_bin(ctx, obs, fin, col.scale, bins)
+    torch.cuda.synchronize()
+    nu_first, dnu = oracle.window_grid(tab, w)
+    idx = oracle.snap_edges(edges, nu_first, dnu, w.count)
+    fd = np.zeros(w.count)
+    fd[idx[0]:idx[-1] + 1] = oracle.convolve(ref_f, nu_first, dnu, 250.0,
+                                             np.arange(idx[0], idx[-1] + 1))
+    ref_b = oracle.bin_spectrum(fd, idx, nu_first, dnu, col.scale)
+    e, _ = tu.max_rel_err(bins.cpu().numpy(), ref_b)
+    say(f"  bins {e:.2e}")
+    assert e <= tol
+
+
+@pytest.mark.parametrize("dtype,tol", [("f64", 1e-12), ("f32", 1e-5)])
+def test_multispecies_cia_windows(ctx, dtype, tol):
+    """3 species + CIA; ragged and strided windows; L = 2 and L = 41; all chunkings."""
+    tab = tu.small_multi_table()
+    T = hr2.Tables(ctx, tab, dtype)
+    cases = [(wl.Window(0, 3000, 1), 41), (wl.Window(13, 1001, 2), 41), (wl.Window(5, 333, 7), 41),
+             (wl.Window(100, 2500, 1), 2), (wl.Window(0, 64, 1), 3)]
+    for w, L in cases:
+        cols = tu.small_columns(tab, 3, seed=L + w.begin, n_levels=L)
+        nu_first, dnu = oracle.window_grid(tab, w)
+        lo = nu_first + 0.2 * (w.count - 1) * dnu
+        hi = nu_first + 0.8 * (w.count - 1) * dnu
+        edges = wl.snapped_edges(tab, w, wl.log_edges(lo, hi, 9))
+        obs = hr2.Obs(ctx, T, w, 400.0, edges)
+        for chunks in (1, 2, 4):
+            say(f"window {w} L={L} {dtype} chunks={chunks}")
+            bins, fplus = run_forward(ctx, T, obs, cols, 3, chunks)
+            for s, col in enumerate(cols):
+                ref = oracle.forward(tab, col, w, 400.0, edges, 3)
+                e_f, _ = tu.max_rel_err(fplus[s], ref["fplus"])
+                e_b, _ = tu.max_rel_err(bins[s], ref["bins"])
+                assert e_f <= tol and e_b <= tol, (w, L, chunks, s, e_f, e_b)
+
+
+def test_isothermal_and_transparent_limits(ctx):
+    """P3/P5 on the GPU: isothermal columns give pi B(T) at every point (FP32)."""
+    tab = tu.c1_table()
+    T = hr2.Tables(ctx, tab, "f32")
+    p = wl.levels(21, 2.0, -4.0)
+    w = wl.Window(0, tab.n_nu, 1)
+    spec = wl.c1_obs(tab)
+    obs = hr2.Obs(ctx, T, w, 300.0, spec.edges_cm)
+    cols = [wl.Column(p, np.full(21, t), np.array([1e-3]), 4.75, 1.0) for t in (300.0, 900.0, 1733.0)]
+    say("isothermal columns, f32")
+    _, fplus = run_forward(ctx, T, obs, cols)
+    nu = tab.nu(0, tab.n_nu, 1)
+    for s, c in enumerate(cols):
+        ref = np.pi * oracle.planck(nu, np.full(nu.shape, c.T_K[0]))
+        e, _ = tu.max_rel_err(fplus[s], ref)
+        say(f"  T={c.T_K[0]}: {e:.2e}")
+        assert e <= 1e-5
+
+
+def test_batch_independence_and_device_entry(ctx):
+    """P15: a set's result does not depend on the other sets of the launch
+    (bit-identical), and the device-column entry equals the host entry."""
+    tab = tu.c1_table()
+    T = hr2.Tables(ctx, tab, "f32")
+    spec = wl.c1_obs(tab)
+    obs = hr2.Obs(ctx, T, spec.window, spec.resolving_power, spec.edges_cm)
+    cols = wl.c3_columns(64, seed=9)
+    say("batch of 64 vs singles (chunks fixed at 1)")
+    bins_b, fp_b = run_forward(ctx, T, obs, cols, 3, chunks=1)
+    for s in (0, 17, 63):
+        b1, f1 = run_forward(ctx, T, obs, [cols[s]], 3, chunks=1)
+        assert np.array_equal(b1[0], bins_b[s]) and np.array_equal(f1[0], fp_b[s])
+    say("device-column entry")
+    B, L = len(cols), cols[0].n_levels
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+    p = dev(np.stack([c.p_bar for c in cols]))
+    Tk = dev(np.stack([c.T_K for c in cols]))
+    x = dev(np.stack([c.x for c in cols]))
+    lg = dev([c.log_g for c in cols])
+    sc = dev([c.scale for c in cols])
+    bins = torch.empty(B * obs.n_bins, dtype=torch.float32, device="cuda")
+    status = torch.full((B,), 7, dtype=torch.int32, device="cuda")
+    ctx.set_option(hr2.OPT_CHUNKS, 1)
+    hr2.forward_batch_dev(ctx, T, obs, p, Tk, x, lg, sc, 3, bins, None, status)
+    torch.cuda.synchronize()
+    assert np.array_equal(bins.cpu().numpy().reshape(B, -1), bins_b.astype(np.float32))
+    assert int(status.abs().sum()) == 0
+    say("device-column entry with one invalid set")
+    Tbad = Tk.clone()
+    Tbad[5, 3] = -10.0
+    hr2.forward_batch_dev(ctx, T, obs, p, Tbad, x, lg, sc, 3, bins, None, status)
+    torch.cuda.synchronize()
+    out = bins.cpu().numpy().reshape(B, -1)
+    st = status.cpu().numpy()
+    assert st[5] == hr2.E_INVALID_ARG and np.all(np.delete(st, 5) == 0)
+    assert np.all(np.isnan(out[5]))
+    assert np.array_equal(np.delete(out, 5, axis=0), np.delete(bins_b.astype(np.float32), 5, axis=0))
+    ctx.set_option(hr2.OPT_CHUNKS, 0)
+
+
+def test_c3_batch_512(ctx):
+    """C3: 512 sets on the C1 grid in one launch; every 31st set against the oracle."""
+    tab = tu.c1_table()
+    T = hr2.Tables(ctx, tab, "f32")
+    spec = wl.c1_obs(tab)
+    obs = hr2.Obs(ctx, T, spec.window, spec.resolving_power, spec.edges_cm)
+    cols = wl.c3_columns()
+    say("C3 512 sets f32")
+    bins, fplus = run_forward(ctx, T, obs, cols)
+    worst = 0.0
+    for s in range(0, 512, 31):
+        ref = oracle.forward(tab, cols[s], spec.window, spec.resolving_power, spec.edges_cm, 3)
+        e_b, _ = tu.max_rel_err(bins[s], ref["bins"])
+        e_f, _ = tu.max_rel_err(fplus[s], ref["fplus"])
+        worst = max(worst, e_b, e_f)
+    say(f"  worst {worst:.2e}")
+    assert worst <= 1e-5
+
+
+def test_abi_errors_leave_outputs_untouched(ctx):
+    """Invalid arguments return the documented codes before anything is enqueued."""
+    tab = tu.c1_table()
+    T = hr2.Tables(ctx, tab, "f32")
+    spec = wl.c1_obs(tab)
+    obs = hr2.Obs(ctx, T, spec.window, spec.resolving_power, spec.edges_cm)
+    good = wl.c1_columns()[2]
+    bins = torch.full((obs.n_bins,), 123.0, dtype=torch.float32, device="cuda")
+
+    def expect(status, cols, n_mu=3):
+        with pytest.raises(hr2.HR2Error) as ei:
+            hr2.forward_batch(ctx, T, obs, cols, n_mu, bins)
+        assert ei.value.status == status, ei.value
+
+    bad_T = wl.Column(good.p_bar, good.T_K.copy(), good.x, good.log_g, good.scale)
+    bad_T.T_K[4] = np.nan
+    expect(hr2.E_INVALID_ARG, [bad_T])
+    bad_p = wl.Column(good.p_bar[::-1].copy(), good.T_K, good.x, good.log_g, good.scale)
+    expect(hr2.E_INVALID_ARG, [bad_p])
+    expect(hr2.E_INVALID_ARG, [wl.Column(good.p_bar, good.T_K, np.array([1.5]), 4.0, 1.0)])
+    expect(hr2.E_OUT_OF_RANGE, [good], n_mu=0)
+    expect(hr2.E_OUT_OF_RANGE, [good], n_mu=9)
+    short = wl.Column(good.p_bar[:1], good.T_K[:1], good.x, good.log_g, good.scale)
+    expect(hr2.E_INVALID_ARG, [short])
+    torch.cuda.synchronize()
+    assert torch.all(bins == 123.0)
+    with pytest.raises(hr2.HR2Error) as ei:
+        hr2.Obs(ctx, T, wl.Window(0, 3000, 1), 300.0, spec.edges_cm)
+    assert ei.value.status == hr2.E_OUT_OF_RANGE
+    with pytest.raises(hr2.HR2Error) as ei:
+        hr2.Obs(ctx, T, spec.window, 300.0, [4100.0, 4100.2, 4300.0])
+    assert ei.value.status == hr2.E_INVALID_ARG
+
+
+# ------------------------------------------------------------------- C2 / C4
+
+
+@pytest.fixture(scope="module")
+def c2():
+    say("generating the C2 table (8 x 27 x 19 x 150000)")
+    return tu.c2_table()
+
+
+def _c2_sampled_check(ctx, tab, T, dtype, tol_bins, tol_fplus, ref_table=None):
+    ref_table = tab if ref_table is None else ref_table
+    spec = wl.c2_obs(tab)
+    col = wl.c2_column()
+    obs = hr2.Obs(ctx, T, spec.window, spec.resolving_power, spec.edges_cm)
+    say(f"C2 {dtype}: forward (single spectrum)")
+    bins, fplus = run_forward(ctx, T, obs, [col])
+    rng = np.random.default_rng(1)
+    pts = np.sort(rng.choice(tab.n_nu, 400, replace=False))
+    pts = np.concatenate([[0, tab.n_nu - 1], pts])
+    ref_f = oracle.fplus(ref_table, col, spec.window, 3, pts)
+    e_f, nf = tu.max_rel_err(fplus[0, pts], ref_f)
+    bin_ids = [0, 1, 57, 133, 200, 271, 333, 398, 399]
+    ref_b = oracle.forward_bins_subset(ref_table, col, spec.window, spec.resolving_power,
+                                       spec.edges_cm, 3, bin_ids)
+    e_b, nb = tu.max_rel_err(bins[0, bin_ids], ref_b)
+    say(f"  C2 {dtype}: sampled F+ {e_f:.2e} (floored {nf}), sampled bins {e_b:.2e}")
+    if tol_fplus is not None:
+        assert e_f <= tol_fplus
+    assert e_b <= tol_bins
+    return e_f, e_b
+
+
+def test_c2_fp32_sampled(ctx, c2):
+    """C2 at full size, FP32 tables, the launch bench.py times: sampled points and bins."""
+    T = hr2.Tables(ctx, c2, "f32")
+    _c2_sampled_check(ctx, c2, T, "f32", 1e-5, 1e-5)
+    T.close()
+
+
+@pytest.mark.parametrize("dtype", ["f16", "bf16"])
+def test_c4_reduced_precision_errors(ctx, c2, dtype):
+    """C4: FP16/BF16 log tables.  Against the oracle on the dequantised table
+    the arithmetic matches to FP32 level; against the FP64 source the error is
+    the quantisation's, reported per spectrum (FP16 held to 1e-3 on bins)."""
+    T = hr2.Tables(ctx, c2, dtype)
+    deq = tu.dequantised(c2, dtype)
+    e_f, e_b = _c2_sampled_check(ctx, c2, T, dtype + " vs dequantised", 1e-5, None, ref_table=deq)
+    e_f_src, e_b_src = _c2_sampled_check(ctx, c2, T, dtype + " vs FP64 source",
+                                         1e-3 if dtype == "f16" else 1.0, None)
+    say(f"  {dtype}: bins vs source {e_b_src:.2e}, F+ vs source {e_f_src:.2e}")
+    T.close()
