@@ -111,6 +111,8 @@ def main():
     ap.add_argument("--chunks", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget-s", type=float, default=20.0)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a plain 1 GiB device-to-device copy 5 times (counter scale)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
@@ -121,6 +123,15 @@ def main():
     from paper_1910_01070_amd import hr2
 
     assert torch.cuda.is_available(), "bench needs a HIP device"
+    if args.calibrate_copy:
+        n = (1 << 30) // 4
+        a = torch.ones(n, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibrate_copy_bytes_read": n * 4, "bytes_written": n * 4, "repeats": 5}))
+        return
     log("generating tables")
     t0 = time.perf_counter()
     tab = wl.c2_table(n_nu=args.n_nu)

@@ -348,11 +348,14 @@ extern "C" hr2_status hr2_tables_create(hr2_ctx *ctx, const hr2_tables_desc *d, 
   if (d->dtype < HR2_TABLE_F32 || d->dtype > HR2_TABLE_F64)
     return set_error(HR2_E_INVALID_ARG, "unknown table dtype");
 
+  const int S = d->n_species, nT = d->n_T, nP = d->n_p, nc = d->n_cia;
+  const int64_t n_nu = d->n_nu, pitch = (n_nu + 63) / 64 * 64;
+  // rows are addressed by 32-bit byte offsets inside one species block
+  if ((double)nT * nP * pitch * 8.0 >= 4294967296.0)
+    return set_error(HR2_E_OUT_OF_RANGE, "one species block of the table must stay below 4 GiB");
   HIP_TRY(hipSetDevice(ctx->device));
   auto *t = new hr2_tables();
   t->ctx = ctx;
-  const int S = d->n_species, nT = d->n_T, nP = d->n_p, nc = d->n_cia;
-  const int64_t n_nu = d->n_nu, pitch = (n_nu + 63) / 64 * 64;
   t->T_axis.assign(d->T_K, d->T_K + nT);
   t->lp_axis.assign(d->log10_p_bar, d->log10_p_bar + nP);
   t->mass.assign(d->molar_mass, d->molar_mass + S);
@@ -426,6 +429,8 @@ extern "C" hr2_status hr2_tables_create(hr2_ctx *ctx, const hr2_tables_desc *d, 
   v.dnu = d->dnu_cm;
   v.he_ratio = d->he_h2_ratio;
   v.dtype = d->dtype;
+  v.tab_elem = d->dtype == HR2_TABLE_F64 ? 8 : (d->dtype == HR2_TABLE_F32 ? 4 : 2);
+  v.cia_elem = f64 ? 8 : 4;
   *out = t;
   return HR2_OK;
 }
@@ -740,7 +745,7 @@ extern "C" hr2_status hr2_convolve_bin(hr2_ctx *ctx, const hr2_obs *o, const voi
   hr2_status st;
   if ((st = ctx_begin(ctx, s)) != HR2_OK) return st;
   ConvSeg cs{};
-  cs.wave_begin = 0;
+  cs.item_begin = 0;
   cs.K = o->d_K;
   cs.kstart = o->d_kstart;
   cs.mlo = o->d_mlo;
@@ -817,7 +822,7 @@ hr2_status run_forward(hr2_ctx *ctx, const hr2_tables *t, const hr2_obs *o, cons
   HIP_TRY(launch_column(t->view, (const ColSeg *)ctx->segs.ptr, 1, total_wgs, ctx->recs.ptr,
                         nullptr, fplus, n_mu, false, s));
   ConvSeg cs{};
-  cs.wave_begin = 0;
+  cs.item_begin = 0;
   cs.K = o->d_K;
   cs.kstart = o->d_kstart;
   cs.mlo = o->d_mlo;

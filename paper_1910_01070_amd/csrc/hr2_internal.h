@@ -25,9 +25,10 @@ constexpr int kMaxMu = HR2_MAX_MU;
 
 struct alignas(16) LevelRecF {
   float w[4];            // slot weights (bilinear corner weights)
-  int32_t row[4];        // row held by each slot: iT * n_p + ip
-  int32_t mask;          // bit k < 4: species slot k changes here; bit 4 + q: CIA slot q
-  int32_t cia_row[2];    // CIA slot rows (T node)
+  uint32_t rowb[4];      // byte offset of each slot's row in a species block: (iT n_p + ip) pitch b
+  int32_t mask;          // bit k < 4: species slot k changes here; bit 4 + q: CIA slot q;
+                         // bits 8 + k, 12 + q: the slot's weight is nonzero
+  uint32_t cia_rowb[2];  // byte offset of each CIA slot's row (T node) in a pair block
   float cia_w[2];        // CIA slot weights
   float a_cia[2];        // n_H2^2 2^{c}, n_H2 n_He 2^{c'} (c: interpolated row offsets)
   float hdz;             // dz_l / 2 of layer l -> l+1 (0 at the top level)
@@ -39,9 +40,9 @@ static_assert(sizeof(LevelRecF) == 128, "LevelRecF must be 128 bytes");
 
 struct alignas(16) LevelRecD {
   double w[4];
-  int32_t row[4];
+  uint32_t rowb[4];
   int32_t mask;
-  int32_t cia_row[2];
+  uint32_t cia_rowb[2];
   int32_t pad0;
   double cia_w[2];
   double a_cia[2];
@@ -70,6 +71,7 @@ struct TableView {
   int64_t n_nu, pitch;
   double nu0, dnu, he_ratio;
   int dtype;                // hr2_table_dtype
+  int tab_elem, cia_elem;   // bytes per stored entry
 };
 
 // Packed device columns of one batch (FP64).
@@ -98,7 +100,7 @@ struct ColSeg {
 
 // One segment of a convolve/bin launch: n_sets spectra against one layout.
 struct ConvSeg {
-  int64_t wave_begin;       // first wave (one wave per (set, bin))
+  int64_t item_begin;       // first workgroup (one per (set, bin))
   const void *K;            // weights (Real)
   const int64_t *kstart;    // [n_bins]
   const int32_t *mlo;       // [n_bins] first window point of the support
@@ -138,7 +140,7 @@ hipError_t launch_opacity_only(const TableView &tv, const void *recs, int n_leve
                                void *chi, hipStream_t stream);
 
 hipError_t launch_convolve_bin(bool fp64, const ConvSeg *segs_dev, int n_segs,
-                               int64_t total_waves, const void *in, void *out,
+                               int64_t total_items, const void *in, void *out,
                                hipStream_t stream);
 
 // Observation layout build: Z_i and q_i for window points [i0, i0 + n)

@@ -55,6 +55,36 @@ template <> __device__ __forceinline__ float to_float<uint16_t>(uint16_t v) {
   return __uint_as_float(((uint32_t)v) << 16);   // bfloat16 -> float is exact
 }
 
+// Table reads go through buffer resources (base + byte size in SGPRs, the
+// lane's 32-bit byte offset in a VGPR): one address add per load, and the
+// hardware returns 0 for any offset past the resource instead of faulting.
+using rsrc_t = __amdgpu_buffer_rsrc_t;
+__device__ __forceinline__ rsrc_t make_rsrc(const void *base, int64_t bytes) {
+  const uint32_t n = bytes >= 0xFFFFFFFFll ? 0xFFFFFFFFu : (uint32_t)bytes;
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, (int)n,
+                                           0x00020000);
+}
+// soff: a uniform byte offset added by the hardware (scalar operand).
+template <typename TT> __device__ __forceinline__ TT buf_load(rsrc_t r, uint32_t off, uint32_t soff);
+template <>
+__device__ __forceinline__ float buf_load<float>(rsrc_t r, uint32_t off, uint32_t soff) {
+  return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, off, soff, 0));
+}
+template <>
+__device__ __forceinline__ _Float16 buf_load<_Float16>(rsrc_t r, uint32_t off, uint32_t soff) {
+  const unsigned short u = __builtin_amdgcn_raw_buffer_load_b16(r, off, soff, 0);
+  return __builtin_bit_cast(_Float16, u);
+}
+template <>
+__device__ __forceinline__ uint16_t buf_load<uint16_t>(rsrc_t r, uint32_t off, uint32_t soff) {
+  return __builtin_amdgcn_raw_buffer_load_b16(r, off, soff, 0);
+}
+template <>
+__device__ __forceinline__ double buf_load<double>(rsrc_t r, uint32_t off, uint32_t soff) {
+  const auto v = __builtin_amdgcn_raw_buffer_load_b64(r, off, soff, 0);
+  return __builtin_bit_cast(double, v);
+}
+
 __device__ __forceinline__ float fexp2(float x) { return __builtin_amdgcn_exp2f(x); }
 __device__ __forceinline__ float frcp(float x) { return __builtin_amdgcn_rcpf(x); }
 
@@ -107,19 +137,17 @@ __device__ __forceinline__ void cia_slot(const CellW &c, int k, int &row, double
 }
 
 template <typename Real>
-__global__ __launch_bounds__(256) void k_levels(TableView tv, ColumnsView cv,
+__global__ __launch_bounds__(128) void k_levels(TableView tv, ColumnsView cv,
                                                 typename RecOf<Real>::type *recs, int *status) {
   using Rec = typename RecOf<Real>::type;
-  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int s = blockIdx.x;
   const int L = cv.L;
-  if (gid >= (int64_t)cv.B * L) return;
-  const int s = (int)(gid / L), l = (int)(gid % L);
   const int S = tv.S;
   const double *p = cv.p + (int64_t)s * L;
   const double *T = cv.T + (int64_t)s * L;
   const double *x = cv.x + (int64_t)s * S;
 
-  // column-wide validity (every thread of the set reaches the same verdict)
+  // column-wide quantities and validity (Sect. 5.2 filler gas, Table 1 inputs)
   bool bad = false;
   double xs = 0.0, mm = 0.0;
   for (int q = 0; q < S; ++q) {
@@ -128,111 +156,115 @@ __global__ __launch_bounds__(256) void k_levels(TableView tv, ColumnsView cv,
     mm += x[q] * tv.mass[q];
   }
   bad |= !(xs < 1.0) || !isfinite(cv.logg[s]) || !isfinite(cv.scale[s]);
-  for (int q = 0; q < L; ++q) {
-    bad |= !(p[q] > 0.0) || !isfinite(p[q]) || !(T[q] > 0.0) || !isfinite(T[q]);
-    if (q + 1 < L) bad |= !(p[q] > p[q + 1]);
+  for (int l = threadIdx.x; l < L; l += blockDim.x) {
+    bad |= !(p[l] > 0.0) || !isfinite(p[l]) || !(T[l] > 0.0) || !isfinite(T[l]);
+    if (l + 1 < L) bad |= !(p[l] > p[l + 1]);
   }
-  if (status != nullptr && l == 0) status[s] = bad ? (int)HR2_E_INVALID_ARG : 0;
+  bad = __syncthreads_or(bad);
+  if (status != nullptr && threadIdx.x == 0) status[s] = bad ? (int)HR2_E_INVALID_ARG : 0;
 
   const double h2 = (1.0 - xs) / (1.0 + tv.he_ratio);
   const double he = tv.he_ratio * h2;
   mm += h2 * kMH2 + he * kMHe;
   const double g = pow(10.0, cv.logg[s]);
-  const double n = p[l] * 1.0e6 / (kKB * T[l]);
-
-  Rec r;
-  const CellW c = cell_of(tv, T[l], p[l]);
-  CellW cp = c;
-  const bool has_prev = l > 0;
-  if (has_prev) cp = cell_of(tv, T[l - 1], p[l - 1]);
-  int mask = 0;
-  double wsl[4];
-  int rowsl[4];
-  for (int k = 0; k < 4; ++k) {
-    int row, rowp;
-    double w, wp;
-    slot_corner(c, k, tv.nP, row, w);
-    slot_corner(cp, k, tv.nP, rowp, wp);
-    wsl[k] = w;
-    rowsl[k] = row;
-    r.w[k] = (Real)w;
-    r.row[k] = row;
-    const bool nz = w != 0.0;
-    const bool kept = has_prev && wp != 0.0 && rowp == row;
-    if (nz) mask |= 1 << (8 + k);
-    if (nz && !kept) mask |= 1 << k;
-  }
-  for (int k = 0; k < 2; ++k) {
-    int row, rowp;
-    double w, wp;
-    cia_slot(c, k, row, w);
-    cia_slot(cp, k, rowp, wp);
-    r.cia_row[k] = row;
-    r.cia_w[k] = (Real)w;
-    const bool nz = w != 0.0 && tv.n_cia > 0;
-    const bool kept = has_prev && wp != 0.0 && rowp == row;
-    if (nz) mask |= 1 << (12 + k);
-    if (nz && !kept) mask |= 1 << (4 + k);
-  }
-  r.mask = mask;
-
-  // n_s 2^{interpolated row offset}: the kernel exponentiates only the
-  // stored (offset-free) part, keeping its exp2 argument small.
   const int64_t rows_per_species = (int64_t)tv.nT * tv.nP;
-  for (int q = 0; q < kMaxSpecies; ++q) {
-    double a = 0.0;
-    if (q < S) {
-      double cq = 0.0;
-      for (int k = 0; k < 4; ++k) cq += wsl[k] * tv.off[q * rows_per_species + rowsl[k]];
-      a = x[q] * n * exp2(cq);
+  const uint32_t row_bytes = (uint32_t)(tv.pitch * tv.tab_elem);
+  const uint32_t cia_row_bytes = (uint32_t)(tv.pitch * tv.cia_elem);
+
+  for (int l = threadIdx.x; l < L; l += blockDim.x) {
+    const double n = p[l] * 1.0e6 / (kKB * T[l]);
+    Rec r;
+    const CellW c = cell_of(tv, T[l], p[l]);
+    CellW cp = c;
+    const bool has_prev = l > 0;
+    if (has_prev) cp = cell_of(tv, T[l - 1], p[l - 1]);
+    int mask = 0;
+    double wsl[4];
+    int rowsl[4];
+    for (int k = 0; k < 4; ++k) {
+      int row, rowp;
+      double w, wp;
+      slot_corner(c, k, tv.nP, row, w);
+      slot_corner(cp, k, tv.nP, rowp, wp);
+      wsl[k] = w;
+      rowsl[k] = row;
+      r.w[k] = (Real)w;
+      r.rowb[k] = (uint32_t)row * row_bytes;
+      const bool nz = w != 0.0;
+      const bool kept = has_prev && wp != 0.0 && rowp == row;
+      if (nz) mask |= 1 << (8 + k);
+      if (nz && !kept) mask |= 1 << k;
     }
-    r.a_s[q] = (Real)a;
-  }
-  for (int q = 0; q < 2; ++q) {
-    double a = 0.0;
-    if (q < tv.n_cia) {
-      double cq = 0.0;
-      for (int k = 0; k < 2; ++k) {
-        int row;
-        double w;
-        cia_slot(c, k, row, w);
-        cq += w * tv.off_cia[q * tv.nT + row];
+    for (int k = 0; k < 2; ++k) {
+      int row, rowp;
+      double w, wp;
+      cia_slot(c, k, row, w);
+      cia_slot(cp, k, rowp, wp);
+      r.cia_rowb[k] = (uint32_t)row * cia_row_bytes;
+      r.cia_w[k] = (Real)w;
+      const bool nz = w != 0.0 && tv.n_cia > 0;
+      const bool kept = has_prev && wp != 0.0 && rowp == row;
+      if (nz) mask |= 1 << (12 + k);
+      if (nz && !kept) mask |= 1 << (4 + k);
+    }
+    r.mask = mask;
+
+    // n_s 2^{interpolated row offset}: the kernel exponentiates only the
+    // stored (offset-free) part, keeping its exp2 argument small.
+    for (int q = 0; q < kMaxSpecies; ++q) {
+      double a = 0.0;
+      if (q < S) {
+        double cq = 0.0;
+        for (int k = 0; k < 4; ++k) cq += wsl[k] * tv.off[q * rows_per_species + rowsl[k]];
+        a = x[q] * n * exp2(cq);
       }
-      const double nh2 = h2 * n, nhe = he * n;
-      a = (q == 0 ? nh2 * nh2 : nh2 * nhe) * exp2(cq);
+      r.a_s[q] = (Real)a;
     }
-    r.a_cia[q] = (Real)a;
+    for (int q = 0; q < 2; ++q) {
+      double a = 0.0;
+      if (q < tv.n_cia) {
+        double cq = 0.0;
+        for (int k = 0; k < 2; ++k) {
+          int row;
+          double w;
+          cia_slot(c, k, row, w);
+          cq += w * tv.off_cia[q * tv.nT + row];
+        }
+        const double nh2 = h2 * n, nhe = he * n;
+        a = (q == 0 ? nh2 * nh2 : nh2 * nhe) * exp2(cq);
+      }
+      r.a_cia[q] = (Real)a;
+    }
+    double hdz = 0.0;
+    if (l + 1 < L) {
+      const double tbar = 0.5 * (T[l] + T[l + 1]);
+      hdz = 0.5 * kKB * tbar / (mm * kAMU * g) * log(p[l] / p[l + 1]);
+    }
+    if (bad) hdz = __builtin_nan("");
+    r.hdz = (Real)hdz;
+    if constexpr (std::is_same<Real, float>::value) {
+      const double pl = kC2 * kLog2e / T[l];
+      const float hi = (float)pl;
+      r.pl_hi = hi;
+      r.pl_lo = (float)(pl - (double)hi);
+      r.pad[0] = r.pad[1] = 0.0f;
+    } else {
+      r.T = T[l];
+      r.pad0 = 0;
+      for (int q = 0; q < 6; ++q) r.pad[q] = 0.0;
+    }
+    recs[(int64_t)s * L + l] = r;
   }
-  double hdz = 0.0;
-  if (l + 1 < L) {
-    const double tbar = 0.5 * (T[l] + T[l + 1]);
-    hdz = 0.5 * kKB * tbar / (mm * kAMU * g) * log(p[l] / p[l + 1]);
-  }
-  if (bad) hdz = __builtin_nan("");
-  r.hdz = (Real)hdz;
-  if constexpr (std::is_same<Real, float>::value) {
-    const double pl = kC2 * kLog2e / T[l];
-    const float hi = (float)pl;
-    r.pl_hi = hi;
-    r.pl_lo = (float)(pl - (double)hi);
-    r.pad[0] = r.pad[1] = 0.0f;
-  } else {
-    r.T = T[l];
-    r.pad0 = 0;
-    for (int q = 0; q < 6; ++q) r.pad[q] = 0.0;
-  }
-  recs[(int64_t)s * L + l] = r;
 }
 
 hipError_t launch_levels(const TableView &tv, const ColumnsView &cv, void *recs, int *status,
                          bool fp64, hipStream_t stream) {
-  const int64_t n = (int64_t)cv.B * cv.L;
-  const dim3 grid((unsigned)((n + 255) / 256));
+  const dim3 grid((unsigned)cv.B);
   if (fp64)
-    hipLaunchKernelGGL(k_levels<double>, grid, dim3(256), 0, stream, tv, cv,
+    hipLaunchKernelGGL(k_levels<double>, grid, dim3(128), 0, stream, tv, cv,
                        (LevelRecD *)recs, status);
   else
-    hipLaunchKernelGGL(k_levels<float>, grid, dim3(256), 0, stream, tv, cv,
+    hipLaunchKernelGGL(k_levels<float>, grid, dim3(128), 0, stream, tv, cv,
                        (LevelRecF *)recs, status);
   return hipGetLastError();
 }
@@ -317,7 +349,12 @@ __device__ __forceinline__ double sc_step_d(double I, double dtau, double S1, do
 // bottom to top: stage 1 (opacity, Sect. 2.3) from the slot registers,
 // dtau (trapezoid over the layer), Planck, and the recurrence for every
 // angle; then the chunks' affine maps are combined and Eq. 8 applied.
-template <typename Real, typename TT, int NS, int MAXMU, bool FROM_CHI>
+// BIG: the table spans 4 GiB or more, so each species gets its own buffer
+// resource; otherwise one resource covers the table and the species offset
+// rides in the scalar offset operand.
+// NS: species slots compiled; a negative NS means exactly -NS species (no
+// per-species guards), otherwise tv.S <= NS species with uniform guards.
+template <typename Real, typename TT, int NSS, int MAXMU, bool FROM_CHI, bool BIG>
 __global__ __launch_bounds__(256) void k_column(TableView tv, const ColSeg *__restrict__ segs,
                                                 int n_segs, int64_t total_wgs,
                                                 const typename RecOf<Real>::type *__restrict__ recs,
@@ -325,6 +362,8 @@ __global__ __launch_bounds__(256) void k_column(TableView tv, const ColSeg *__re
                                                 Real *__restrict__ out) {
   using Rec = typename RecOf<Real>::type;
   constexpr bool kF64 = std::is_same<Real, double>::value;
+  constexpr int NS = NSS < 0 ? -NSS : NSS;
+  constexpr bool kExact = NSS < 0;
   __shared__ Real sh_B[4][MAXMU][64];
   __shared__ Real sh_tau[4][64];
 
@@ -339,7 +378,10 @@ __global__ __launch_bounds__(256) void k_column(TableView tv, const ColSeg *__re
   const int64_t t = local / n_sets;
   const int s = (int)(local - t * n_sets);
 
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  // the wave index is uniform across a wavefront; say so, so that everything
+  // derived from it (chunk, levels, records, load masks) stays scalar
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
   const int chunk = wave % C, sub = wave / C;
   const int L = d.n_levels, nlay = L - 1;
   const int m = (nlay + C - 1) / C;
@@ -360,10 +402,24 @@ __global__ __launch_bounds__(256) void k_column(TableView tv, const ColSeg *__re
   const float nu_lo = (float)(nu_d - (double)nu_hi);
   const float c1nu3_f = (float)c1nu3_d;
 
-  const int64_t pitch = tv.pitch;
-  const int64_t sp_stride = (int64_t)tv.nT * tv.nP * pitch;
-  const TT *tab = (const TT *)tv.tab;
-  const Real *cia = (const Real *)tv.cia;
+  // per-species and per-pair base pointers (uniform) and this lane's byte
+  // offset in a row: each load is base + (row offset + lane offset)
+  const int64_t sp_bytes = (int64_t)tv.nT * tv.nP * tv.pitch * (int64_t)sizeof(TT);
+  const int64_t pair_bytes = (int64_t)tv.nT * tv.pitch * (int64_t)sizeof(Real);
+  const char *tab = (const char *)tv.tab;
+  const char *cia = (const char *)tv.cia;
+  rsrc_t rs[BIG ? NS : 1];
+  if constexpr (BIG) {
+#pragma unroll
+    for (int q = 0; q < NS; ++q) rs[q] = make_rsrc(tab + q * sp_bytes, sp_bytes);
+  } else {
+    rs[0] = make_rsrc(tab, sp_bytes * tv.S);
+  }
+  const rsrc_t rc = make_rsrc(cia, 2 * pair_bytes);
+  const uint32_t kb = kk * (uint32_t)sizeof(TT);
+  const uint32_t kbc = kk * (uint32_t)sizeof(Real);
+  const int S = kExact ? NS : tv.S;
+  const bool has_cia = tv.n_cia > 0;
 
   Real slot[NS][4];
   Real cslot[2][2];
@@ -375,32 +431,58 @@ __global__ __launch_bounds__(256) void k_column(TableView tv, const ColSeg *__re
   for (int q = 0; q < 2; ++q) cslot[q][0] = cslot[q][1] = (Real)0;
 
   Real I[MAXMU];
+  float a_mu[MAXMU], a_inv[MAXMU], a_l2e[MAXMU];
+  double a_mud[MAXMU];
 #pragma unroll
-  for (int k = 0; k < MAXMU; ++k) I[k] = (Real)0;
+  for (int k = 0; k < MAXMU; ++k) {
+    I[k] = (Real)0;
+    a_mu[k] = c_ang.mu[nmu - 1][k];
+    a_inv[k] = c_ang.inv_mu[nmu - 1][k];
+    a_l2e[k] = c_ang.l2e_mu[nmu - 1][k];
+    a_mud[k] = kF64 ? c_ang.mu_d[nmu - 1][k] : 0.0;
+  }
   Real tau = (Real)0, chi_prev = (Real)0, S_prev = (Real)0, hdz_prev = (Real)0;
 
   if (l0 < nlay) {
     for (int l = l0; l <= l1; ++l) {
-      const Rec &r = rec[l];
+      const Rec r = rec[l];
       Real chi;
       if constexpr (FROM_CHI) {
         chi = chi_in[d.chi_offset + (int64_t)l * nu_count + jj];
       } else {
         const int mask = (l == l0) ? (r.mask >> 8) : r.mask;
-        chi = (Real)0;
+        // fetch the rows new to this level, slot by slot
 #pragma unroll
-        for (int q = 0; q < NS; ++q) {
-          if (q < tv.S) {
-            const TT *base = tab + q * sp_stride;
+        for (int k = 0; k < 4; ++k) {
+          if (mask & (1 << k)) {
+            const uint32_t off = r.rowb[k] + kb;
 #pragma unroll
-            for (int k = 0; k < 4; ++k)
-              if (mask & (1 << k)) {
-                const TT v = base[(int64_t)r.row[k] * pitch + kk];
+            for (int q = 0; q < NS; ++q) {
+              if (q < S) {
+                const TT v = BIG ? buf_load<TT>(rs[BIG ? q : 0], off, 0)
+                                 : buf_load<TT>(rs[0], off, (uint32_t)(q * sp_bytes));
                 if constexpr (kF64)
                   slot[q][k] = (Real)v;
                 else
                   slot[q][k] = to_float<TT>(v);
               }
+            }
+          }
+        }
+        if (has_cia) {
+#pragma unroll
+          for (int k = 0; k < 2; ++k) {
+            if (mask & (16 << k)) {
+              const uint32_t off = r.cia_rowb[k] + kbc;
+              cslot[0][k] = buf_load<Real>(rc, off, 0);
+              cslot[1][k] = buf_load<Real>(rc, off, (uint32_t)pair_bytes);
+            }
+          }
+        }
+        chi = (Real)0;
+#pragma unroll
+        for (int q = 0; q < NS; ++q) {
+          if (q < S) {
             const Real y = r.w[0] * slot[q][0] + r.w[1] * slot[q][1] + r.w[2] * slot[q][2] +
                            r.w[3] * slot[q][3];
             if constexpr (kF64)
@@ -409,13 +491,9 @@ __global__ __launch_bounds__(256) void k_column(TableView tv, const ColSeg *__re
               chi = fmaf(r.a_s[q], fexp2(y), chi);
           }
         }
-        if (tv.n_cia > 0) {
+        if (has_cia) {
 #pragma unroll
           for (int q = 0; q < 2; ++q) {
-            const Real *cbase = cia + (int64_t)q * tv.nT * pitch;
-#pragma unroll
-            for (int k = 0; k < 2; ++k)
-              if (mask & (16 << k)) cslot[q][k] = cbase[(int64_t)r.cia_row[k] * pitch + kk];
             const Real y = r.cia_w[0] * cslot[q][0] + r.cia_w[1] * cslot[q][1];
             if constexpr (kF64)
               chi += r.a_cia[q] * exp2(y);
@@ -438,14 +516,13 @@ __global__ __launch_bounds__(256) void k_column(TableView tv, const ColSeg *__re
         if constexpr (kF64) {
 #pragma unroll
           for (int k = 0; k < MAXMU; ++k)
-            if (k < nmu) I[k] = sc_step_d(I[k], dtau, S, S_prev, c_ang.mu_d[nmu - 1][k]);
+            if (k < nmu) I[k] = sc_step_d(I[k], dtau, S, S_prev, a_mud[k]);
         } else {
           const float rdt = frcp(dtau);
 #pragma unroll
           for (int k = 0; k < MAXMU; ++k)
             if (k < nmu)
-              I[k] = sc_step_f(I[k], dtau, rdt, S, S_prev, c_ang.inv_mu[nmu - 1][k],
-                               c_ang.l2e_mu[nmu - 1][k], c_ang.mu[nmu - 1][k]);
+              I[k] = sc_step_f(I[k], dtau, rdt, S, S_prev, a_inv[k], a_l2e[k], a_mu[k]);
         }
       }
       chi_prev = chi;
@@ -495,11 +572,11 @@ __global__ __launch_bounds__(256) void k_column(TableView tv, const ColSeg *__re
 
 int column_nu_per_wg(int chunks) { return (4 / chunks) * 64; }
 
-template <typename Real, typename TT, int NS, int MAXMU, bool FROM_CHI>
+template <typename Real, typename TT, int NS, int MAXMU, bool FROM_CHI, bool BIG = false>
 static hipError_t launch_column_t(const TableView &tv, const ColSeg *segs, int n_segs,
                                   int64_t total_wgs, const void *recs, const void *chi_in,
                                   void *out, hipStream_t stream) {
-  hipLaunchKernelGGL((k_column<Real, TT, NS, MAXMU, FROM_CHI>), dim3((unsigned)total_wgs),
+  hipLaunchKernelGGL((k_column<Real, TT, NS, MAXMU, FROM_CHI, BIG>), dim3((unsigned)total_wgs),
                      dim3(256), 0, stream, tv, segs, n_segs, total_wgs,
                      (const typename RecOf<Real>::type *)recs, (const Real *)chi_in, (Real *)out);
   return hipGetLastError();
@@ -517,10 +594,17 @@ static hipError_t launch_column_ns(const TableView &tv, const ColSeg *segs, int 
     return launch_column_t<Real, TT, 1, 8, true>(tv, segs, n_segs, total_wgs, recs, chi_in, out,
                                                  stream);
   } else {
+    const int64_t table_bytes = (int64_t)tv.S * tv.nT * tv.nP * tv.pitch * (int64_t)sizeof(TT);
+    if (table_bytes >= 0xFFFFFFFFll)
+      return launch_column_t<Real, TT, kMaxSpecies, 8, false, true>(tv, segs, n_segs, total_wgs,
+                                                                    recs, chi_in, out, stream);
     if (max_mu <= 4) {
       if (S <= 1)
-        return launch_column_t<Real, TT, 1, 4, false>(tv, segs, n_segs, total_wgs, recs, chi_in,
-                                                      out, stream);
+        return launch_column_t<Real, TT, -1, 4, false>(tv, segs, n_segs, total_wgs, recs, chi_in,
+                                                       out, stream);
+      if (S == 8)
+        return launch_column_t<Real, TT, -8, 4, false>(tv, segs, n_segs, total_wgs, recs, chi_in,
+                                                       out, stream);
       if (S <= 8)
         return launch_column_t<Real, TT, 8, 4, false>(tv, segs, n_segs, total_wgs, recs, chi_in,
                                                       out, stream);
@@ -528,8 +612,8 @@ static hipError_t launch_column_ns(const TableView &tv, const ColSeg *segs, int 
                                                               chi_in, out, stream);
     }
     if (S <= 1)
-      return launch_column_t<Real, TT, 1, 8, false>(tv, segs, n_segs, total_wgs, recs, chi_in,
-                                                    out, stream);
+      return launch_column_t<Real, TT, -1, 8, false>(tv, segs, n_segs, total_wgs, recs, chi_in,
+                                                     out, stream);
     if (S <= 8)
       return launch_column_t<Real, TT, 8, 8, false>(tv, segs, n_segs, total_wgs, recs, chi_in,
                                                     out, stream);
@@ -580,19 +664,19 @@ __global__ __launch_bounds__(256) void k_opacity_only(TableView tv,
   if (j >= nu_count) return;
   const auto &r = recs[l];
   const uint32_t kk = (uint32_t)(nu_begin + j * nu_stride);
-  const int64_t pitch = tv.pitch;
-  const int64_t sp_stride = (int64_t)tv.nT * tv.nP * pitch;
-  const TT *tab = (const TT *)tv.tab;
+  const int64_t sp_bytes = (int64_t)tv.nT * tv.nP * tv.pitch * (int64_t)sizeof(TT);
+  const char *tab = (const char *)tv.tab;
   Real c = (Real)0;
   for (int q = 0; q < tv.S; ++q) {
-    const TT *base = tab + q * sp_stride;
+    const char *base = tab + q * sp_bytes;
     Real y = (Real)0;
     for (int k = 0; k < 4; ++k) {
+      const TT e = *(const TT *)(base + r.rowb[k] + kk * (uint32_t)sizeof(TT));
       Real v;
       if constexpr (kF64)
-        v = (Real)base[(int64_t)r.row[k] * pitch + kk];
+        v = (Real)e;
       else
-        v = to_float<TT>(base[(int64_t)r.row[k] * pitch + kk]);
+        v = to_float<TT>(e);
       y += r.w[k] * v;
     }
     if constexpr (kF64)
@@ -600,11 +684,13 @@ __global__ __launch_bounds__(256) void k_opacity_only(TableView tv,
     else
       c = fmaf(r.a_s[q], fexp2(y), c);
   }
-  const Real *cia = (const Real *)tv.cia;
+  const char *cia = (const char *)tv.cia;
+  const int64_t pair_bytes = (int64_t)tv.nT * tv.pitch * (int64_t)sizeof(Real);
   for (int q = 0; q < tv.n_cia; ++q) {
-    const Real *cbase = cia + (int64_t)q * tv.nT * pitch;
-    const Real y = r.cia_w[0] * cbase[(int64_t)r.cia_row[0] * pitch + kk] +
-                   r.cia_w[1] * cbase[(int64_t)r.cia_row[1] * pitch + kk];
+    const char *cbase = cia + q * pair_bytes;
+    const uint32_t kc = kk * (uint32_t)sizeof(Real);
+    const Real y = r.cia_w[0] * *(const Real *)(cbase + r.cia_rowb[0] + kc) +
+                   r.cia_w[1] * *(const Real *)(cbase + r.cia_rowb[1] + kc);
     if constexpr (kF64)
       c += r.a_cia[q] * exp2(y);
     else
@@ -644,43 +730,46 @@ hipError_t launch_opacity_only(const TableView &tv, const void *recs, int n_leve
 // not depend on what else is in the launch.
 template <typename Real>
 __global__ __launch_bounds__(256) void k_convolve_bin(const ConvSeg *__restrict__ segs,
-                                                      int n_segs, int64_t total_waves,
+                                                      int n_segs, int64_t total_items,
                                                       const Real *__restrict__ in,
                                                       Real *__restrict__ out) {
-  const int64_t wv = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  const int lane = threadIdx.x & 63;
-  if (wv >= total_waves) return;
+  __shared__ Real part[4];
+  const int64_t it = blockIdx.x;
   int sg = 0;
   for (int i = 1; i < n_segs; ++i)
-    if (segs[i].wave_begin <= wv) sg = i;
+    if (segs[i].item_begin <= it) sg = i;
   const ConvSeg &d = segs[sg];
-  const int64_t local = wv - d.wave_begin;
+  const int64_t local = it - d.item_begin;
   const int s = (int)(local / d.n_bins);
   const int jb = (int)(local - (int64_t)s * d.n_bins);
   const Real *K = (const Real *)d.K + d.kstart[jb];
   const int len = d.mlen[jb];
   const Real *F = in + d.in_offset + (int64_t)s * d.in_stride + d.mlo[jb];
   Real acc = (Real)0;
-  for (int q = lane; q < len; q += 64) acc += K[q] * F[q];
+  for (int q = threadIdx.x; q < len; q += 256) acc += K[q] * F[q];
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
-  if (lane == 0) {
+  const int wave = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) part[wave] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const Real tot = (part[0] + part[1]) + (part[2] + part[3]);
     const double sc = d.scale ? d.scale[s] : d.scale_const;
-    out[d.out_offset + (int64_t)s * d.n_bins + jb] = acc * (Real)sc;
+    out[d.out_offset + (int64_t)s * d.n_bins + jb] = tot * (Real)sc;
   }
 }
 
 hipError_t launch_convolve_bin(bool fp64, const ConvSeg *segs_dev, int n_segs,
-                               int64_t total_waves, const void *in, void *out,
+                               int64_t total_items, const void *in, void *out,
                                hipStream_t stream) {
-  if (total_waves <= 0) return hipSuccess;
-  const dim3 grid((unsigned)((total_waves + 3) / 4));
+  if (total_items <= 0) return hipSuccess;
+  const dim3 grid((unsigned)total_items);
   if (fp64)
     hipLaunchKernelGGL(k_convolve_bin<double>, grid, dim3(256), 0, stream, segs_dev, n_segs,
-                       total_waves, (const double *)in, (double *)out);
+                       total_items, (const double *)in, (double *)out);
   else
     hipLaunchKernelGGL(k_convolve_bin<float>, grid, dim3(256), 0, stream, segs_dev, n_segs,
-                       total_waves, (const float *)in, (float *)out);
+                       total_items, (const float *)in, (float *)out);
   return hipGetLastError();
 }
 

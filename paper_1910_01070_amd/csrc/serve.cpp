@@ -253,7 +253,7 @@ bool hr2_server::launch_step(StepSlot &sl, std::vector<Req *> &reqs) {
     max_mu = std::max(max_mu, r.n_mu);
     ConvSeg &v = vs[i];
     std::memset(&v, 0, sizeof(v));
-    v.wave_begin = waves;
+    v.item_begin = waves;
     v.K = blk + r.o_K;
     v.kstart = (const int64_t *)(blk + r.o_kstart);
     v.mlo = (const int32_t *)(blk + r.o_mlo);
