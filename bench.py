@@ -113,6 +113,12 @@ def main():
     ap.add_argument("--cpu-budget-s", type=float, default=20.0)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy 5 times (counter scale)")
+    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4", "c5"],
+                    help="c2 (default): one realistic spectrum per step; c3: 512-set C1 batch "
+                         "as a HIP graph vs 512 sequential calls; c4: reduced-precision "
+                         "batches; c5: Poisson serving trace")
+    ap.add_argument("--rate", type=float, default=2000.0, help="c5 arrival rate, requests/s")
+    ap.add_argument("--duration", type=float, default=10.0, help="c5 trace length, s")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
@@ -132,6 +138,12 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"calibrate_copy_bytes_read": n * 4, "bytes_written": n * 4, "repeats": 5}))
         return
+    if args.workload == "c3":
+        return run_c3(args)
+    if args.workload == "c4":
+        return run_c4(args)
+    if args.workload == "c5":
+        return run_c5(args)
     log("generating tables")
     t0 = time.perf_counter()
     tab = wl.c2_table(n_nu=args.n_nu)
@@ -227,6 +239,192 @@ def main():
         log("timing the oracle on the host")
         res["cpu_baseline"] = cpu_baseline(tab, cols[0], spec, n_mu, args.cpu_budget_s)
     print(json.dumps(res))
+
+
+def _dev_columns(cols):
+    import torch
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+    return (dev(np.stack([c.p_bar for c in cols])), dev(np.stack([c.T_K for c in cols])),
+            dev(np.stack([c.x for c in cols])), dev([c.log_g for c in cols]),
+            dev([c.scale for c in cols]))
+
+
+def run_c3(args):
+    """512 C1 sets: one batched launch captured in a HIP graph and replayed,
+    against 512 sequential one-set calls (each synchronised)."""
+    import torch
+    import workloads as wl
+    from paper_1910_01070_amd import hr2
+    tab = wl.c1_table()
+    spec = wl.c1_obs(tab)
+    cols = wl.c3_columns()
+    B = len(cols)
+    ctx = hr2.Context(0)
+    T = hr2.Tables(ctx, tab, "f32")
+    obs = hr2.Obs(ctx, T, spec.window, spec.resolving_power, spec.edges_cm)
+    p, Tk, x, lg, sc = _dev_columns(cols)
+    bins = torch.empty(B * obs.n_bins, dtype=torch.float32, device="cuda")
+    fplus = torch.empty(B * spec.window.count, dtype=torch.float32, device="cuda")
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        for _ in range(3):
+            hr2.forward_batch_dev(ctx, T, obs, p, Tk, x, lg, sc, 3, bins, fplus, None, s)
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=s):
+            hr2.forward_batch_dev(ctx, T, obs, p, Tk, x, lg, sc, 3, bins, fplus, None, s)
+    torch.cuda.synchronize()
+    for _ in range(args.warmup):
+        g.replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        g.replay()
+    torch.cuda.synchronize()
+    t_graph = (time.perf_counter() - t0) / args.steps
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        hr2.forward_batch_dev(ctx, T, obs, p, Tk, x, lg, sc, 3, bins, fplus)
+    torch.cuda.synchronize()
+    t_eager = (time.perf_counter() - t0) / args.steps
+    one = torch.empty(obs.n_bins, dtype=torch.float32, device="cuda")
+    for c in cols[:16]:
+        hr2.forward_batch(ctx, T, obs, [c], 3, one)
+        torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for c in cols:
+        hr2.forward_batch(ctx, T, obs, [c], 3, one)
+        torch.cuda.synchronize()
+    t_seq = time.perf_counter() - t0
+    layer_nu = (cols[0].n_levels - 1) * spec.window.count
+    print(json.dumps({
+        "metric": METRIC, "value": B / t_graph, "unit": "spectra/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": t_graph * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "512 C1 sets (1 absorber, 5x5 table, 2000 points, 20 layers, "
+                               "3 angles, R=300, 50 bins) per launch, HIP graph replay"},
+        "layer_nu_points_per_s": B * layer_nu / t_graph,
+        "eager_batch_spectra_per_s": B / t_eager,
+        "sequential_512_calls_spectra_per_s": B / t_seq,
+        "graph_speedup_vs_sequential": t_seq / t_graph,
+    }))
+
+
+def run_c4(args):
+    """C2 columns in batches of 1, 64 and 512 with FP32, FP16 and BF16 tables."""
+    import torch
+    import workloads as wl
+    from paper_1910_01070_amd import hr2
+    tab = wl.c2_table(n_nu=args.n_nu)
+    spec = wl.c2_obs(tab)
+    ctx = hr2.Context(0)
+    rows = []
+    for dt in ("f32", "f16", "bf16"):
+        T = hr2.Tables(ctx, tab, dt)
+        obs = hr2.Obs(ctx, T, spec.window, spec.resolving_power, spec.edges_cm)
+        for B in (1, 64, 512):
+            cols = wl.c4_columns(B)
+            p, Tk, x, lg, sc = _dev_columns(cols)
+            bins = torch.empty(B * obs.n_bins, dtype=torch.float32, device="cuda")
+            steps = max(3, min(args.steps, 2000 // B))
+            for _ in range(2):
+                hr2.forward_batch_dev(ctx, T, obs, p, Tk, x, lg, sc, 3, bins)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                hr2.forward_batch_dev(ctx, T, obs, p, Tk, x, lg, sc, 3, bins)
+            torch.cuda.synchronize()
+            dt_s = (time.perf_counter() - t0) / steps
+            layer_nu = (cols[0].n_levels - 1) * spec.window.count
+            rows.append({"table": dt, "batch": B, "ms_per_launch": dt_s * 1e3,
+                         "spectra_per_s": B / dt_s, "layer_nu_per_s": B * layer_nu / dt_s})
+            log(rows[-1])
+            del p, Tk, x, lg, sc, bins
+        obs.close()
+        T.close()
+    print(json.dumps({"workload": "C4 reduced precision (C2 columns, batches)", "rows": rows}))
+
+
+def run_c5(args):
+    """Poisson arrivals of uneven requests against the FP16-table server;
+    then the plain FP32 one-request-at-a-time path on a sample of them."""
+    import threading
+    import torch
+    import workloads as wl
+    from paper_1910_01070_amd import hr2
+    tab = wl.c2_table(n_nu=args.n_nu)
+    log("generating the trace")
+    trace = wl.c5_trace_packed(tab, rate_hz=args.rate, duration_s=args.duration)
+    log(f"  {len(trace)} requests")
+    ctx = hr2.Context(0)
+    T16 = hr2.Tables(ctx, tab, args.dtype if args.dtype != "f32" else "f16")
+    srv = hr2.Server(ctx, T16, 16 << 30, 512)
+    # warm the kernels once
+    r = trace[0]
+    t = srv.submit_packed(r.obs.window, r.obs.resolving_power, r.obs.edges_cm, r.p, r.T, r.x,
+                          r.log_g, r.scale)
+    srv.poll(t, r.n_sets * r.obs.n_bins, wait_s=60.0)
+    tickets = [None] * len(trace)
+    lat, done_t, sub_t = [], [], []
+    fails = [0]
+
+    def collect():
+        for i, rq in enumerate(trace):
+            while tickets[i] is None:
+                time.sleep(0.0002)
+            st, _, info = srv.poll(tickets[i], rq.n_sets * rq.obs.n_bins, wait_s=600.0)
+            if st != hr2.OK:
+                fails[0] += 1
+                continue
+            lat.append(info.t_done - info.t_submit)
+            done_t.append(info.t_done)
+            sub_t.append(info.t_submit)
+
+    th = threading.Thread(target=collect)
+    th.start()
+    t0 = time.perf_counter()
+    for i, rq in enumerate(trace):
+        while time.perf_counter() - t0 < rq.t_arrival:
+            pass
+        tickets[i] = srv.submit_packed(rq.obs.window, rq.obs.resolving_power, rq.obs.edges_cm,
+                                       rq.p, rq.T, rq.x, rq.log_g, rq.scale)
+    t_sub_end = time.perf_counter() - t0
+    th.join()
+    stats = srv.stats()
+    srv.close()
+    span = max(done_t) - min(sub_t)
+    work = sum(rq.layer_nu for rq in trace)
+    lat = np.array(lat)
+    # the plain FP32 path: one request at a time, synchronous, same requests
+    T32 = hr2.Tables(ctx, tab, "f32")
+    sample = trace[: min(len(trace), 200)]
+    t0 = time.perf_counter()
+    for rq in sample:
+        obs = hr2.Obs(ctx, T32, rq.obs.window, rq.obs.resolving_power, rq.obs.edges_cm)
+        cols = [wl.Column(rq.p[i], rq.T[i], rq.x[i], rq.log_g[i], rq.scale[i])
+                for i in range(rq.n_sets)]
+        bins = torch.empty(rq.n_sets * obs.n_bins, dtype=torch.float32, device="cuda")
+        hr2.forward_batch(ctx, T32, obs, cols, 3, bins)
+        torch.cuda.synchronize()
+        obs.close()
+    t_plain = time.perf_counter() - t0
+    plain_rate = sum(rq.layer_nu for rq in sample) / t_plain
+    print(json.dumps({
+        "workload": f"C5 serving trace: Poisson {args.rate:g} req/s for {args.duration:g} s, "
+                    "50-200 layers, 20k-150k point windows at 0.1 or 1 cm^-1, R 100-1000, "
+                    "1-64 sets per request, FP16 tables resident",
+        "requests": len(trace), "failed": fails[0],
+        "offered_layer_nu_per_s": work / args.duration,
+        "served_layer_nu_per_s": work / span,
+        "served_requests_per_s": len(lat) / span,
+        "latency_s": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
+        "drain_s_after_last_arrival": max(done_t) - min(sub_t) - t_sub_end,
+        "steps": stats.steps, "max_admitted": stats.max_inflight, "peak_bytes": stats.peak_bytes,
+        "plain_fp32_one_at_a_time_layer_nu_per_s": plain_rate,
+        "speedup_vs_plain_fp32": (work / span) / plain_rate,
+    }))
 
 
 if __name__ == "__main__":

@@ -248,7 +248,10 @@ hr2_status hr2_forward_batch(hr2_ctx *ctx, const hr2_tables *tables, const hr2_o
  * Nothing is validated on the host (that would need a device read); the
  * level kernel checks every set and writes its status to set_status_dev
  * (device int[n_sets], may be NULL): 0 = valid, HR2_E_INVALID_ARG otherwise.
- * An invalid set's bins and F+ are NaN; other sets are unaffected. */
+ * An invalid set's bins and F+ are NaN; other sets are unaffected.
+ * This call may be captured into a HIP graph once it has been made with the
+ * same sizes outside capture (so no staging copy or scratch growth is
+ * needed; otherwise it returns HR2_E_UNSUPPORTED under capture). */
 hr2_status hr2_forward_batch_dev(hr2_ctx *ctx, const hr2_tables *tables, const hr2_obs *obs,
                                  int n_sets, int n_levels, const double *p_dev,
                                  const double *T_dev, const double *x_dev,
@@ -296,6 +299,14 @@ hr2_status hr2_serve_create(hr2_ctx *ctx, const hr2_tables *tables, size_t hbm_b
  * Errors: HR2_E_INVALID_ARG / HR2_E_OUT_OF_RANGE (validation),
  * HR2_E_NO_MEMORY (the request alone exceeds the budget). */
 hr2_status hr2_serve_submit(hr2_server *srv, const hr2_request *req, uint64_t *ticket);
+/* Same as hr2_serve_submit with the request's columns packed host arrays
+ * (FP64): p_bar[n_sets][n_levels], T_K[n_sets][n_levels],
+ * x[n_sets][n_species], log_g[n_sets], scale[n_sets].  Deep-copied. */
+hr2_status hr2_serve_submit_packed(hr2_server *srv, hr2_window window, double resolving_power,
+                                   int n_bins, const double *bin_edges_cm, int n_sets,
+                                   int n_levels, const double *p_bar, const double *T_K,
+                                   const double *x, const double *log_g, const double *scale,
+                                   int n_mu, uint64_t *ticket);
 /* HR2_NOT_READY while pending/running.  When done, copies n_sets * n_bins
  * results (float; double for F64 tables) to bins_host if capacity allows
  * (else HR2_E_INVALID_ARG, ticket kept), releases the ticket and returns

@@ -4,6 +4,9 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <map>
+#include <mutex>
+#include <tuple>
 #include <cmath>
 #include <cstring>
 #include <string>
@@ -121,13 +124,26 @@ static AngleTable make_angle_table() {
 
 // Make `stream` wait for the context's previous use of its scratch, so
 // scratch reuse is ordered even when calls alternate streams.
+// (Under stream capture the captured calls are ordered by the graph itself
+// and an event from outside the capture may not be waited on: skip both.)
+static bool capturing(hipStream_t stream) {
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(stream, &cs) != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  return cs != hipStreamCaptureStatusNone;
+}
+
 hr2_status ctx_begin(hr2_ctx *ctx, hipStream_t stream) {
   HIP_TRY(hipSetDevice(ctx->device));
-  if (ctx->scratch_used) HIP_TRY(hipStreamWaitEvent(stream, ctx->scratch_event, 0));
+  if (ctx->scratch_used && !capturing(stream))
+    HIP_TRY(hipStreamWaitEvent(stream, ctx->scratch_event, 0));
   return HR2_OK;
 }
 
 hr2_status ctx_end(hr2_ctx *ctx, hipStream_t stream) {
+  if (capturing(stream)) return HR2_OK;
   HIP_TRY(hipEventRecord(ctx->scratch_event, stream));
   ctx->scratch_used = true;
   return HR2_OK;
@@ -137,6 +153,9 @@ hr2_status ctx_end(hr2_ctx *ctx, hipStream_t stream) {
 hr2_status stage_upload(hr2_ctx *ctx, DevBuf &dst, const void *src, size_t bytes,
                         hipStream_t stream) {
   if (bytes == 0) return HR2_OK;
+  if (capturing(stream))
+    return set_error(HR2_E_UNSUPPORTED,
+                     "a staging copy cannot be captured: make the same call once before capture");
   hr2_status st = dst.ensure(bytes);
   if (st != HR2_OK) return st;
   if (ctx->pinned_pending) {
@@ -219,8 +238,7 @@ extern "C" hr2_status hr2_ctx_set_option(hr2_ctx *ctx, hr2_option opt, int value
   if (ctx == nullptr) return set_error(HR2_E_INVALID_ARG, "ctx is NULL");
   switch (opt) {
     case HR2_OPT_CHUNKS:
-      if (value != 0 && value != 1 && value != 2 && value != 4)
-        return set_error(HR2_E_INVALID_ARG, "chunks must be 0, 1, 2 or 4");
+      if (value < 0 || value > 8) return set_error(HR2_E_INVALID_ARG, "chunks must be in [0, 8]");
       ctx->opt_chunks = value;
       return HR2_OK;
     case HR2_OPT_NU_PER_LANE:
@@ -326,8 +344,8 @@ extern "C" hr2_status hr2_tables_create(hr2_ctx *ctx, const hr2_tables_desc *d, 
   *out = nullptr;
   if (d->n_species < 1 || d->n_species > HR2_MAX_SPECIES)
     return set_error(HR2_E_INVALID_ARG, "n_species must be in [1, 12]");
-  if (d->n_T < 2 || d->n_p < 2 || d->n_T > 4096 || d->n_p > 4096)
-    return set_error(HR2_E_INVALID_ARG, "n_T and n_p must be in [2, 4096]");
+  if (d->n_T < 2 || d->n_p < 2 || d->n_T > 256 || d->n_p > 256)
+    return set_error(HR2_E_INVALID_ARG, "n_T and n_p must be in [2, 256]");
   if (d->n_nu < 1 || d->n_nu > (int64_t(1) << 31) - 4096)
     return set_error(HR2_E_INVALID_ARG, "n_nu out of range");
   if (!d->T_K || !d->log10_p_bar || !d->log10_sigma || !d->molar_mass)
@@ -514,12 +532,41 @@ ColumnsView columns_view(const void *dev, int n_sets, int L, int S) {
   return v;
 }
 
-int auto_chunks(int64_t base_waves, int n_levels) {
-  int c = 1;
-  if (base_waves < 4096) c = 4;
-  else if (base_waves < 8192) c = 2;
-  while (c > 1 && c > n_levels - 1) c >>= 1;
-  return c;
+// Layer chunks per 64-point tile.  A launch of W = B * tiles * C waves
+// runs in ceil(W / capacity) rounds of resident waves, each wave sweeping
+// about (L - 1)/C layers plus one shared boundary level; pick the C with the
+// fewest wave-level steps on the critical path (small penalty per chunk for
+// the combine).  Depends on the request and the device only.
+int auto_chunks(const TableView &tv, int64_t base_waves, int n_levels, int n_mu,
+                bool from_chi) {
+  // capacities depend on the kernel variant and the device only: cache them
+  static std::mutex mu;
+  static std::map<std::tuple<int, int, int, int, int, bool, int>, int> cache;
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  auto capacity = [&](int c) {
+    const int big = (int64_t)tv.S * tv.nT * tv.nP * tv.pitch * tv.tab_elem >= 0xFFFFFFFFll;
+    const auto key = std::make_tuple(dev, tv.dtype, tv.S, big, n_mu > 4 ? 8 : 4, from_chi, c);
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = cache.find(key);
+    if (it != cache.end()) return it->second;
+    const int v = column_wave_capacity(tv, n_mu, from_chi, c);
+    cache.emplace(key, v);
+    return v;
+  };
+  int best = 1;
+  double best_cost = 1e300;
+  for (int c = 1; c <= 8 && c <= n_levels - 1; ++c) {
+    const int64_t cap = std::max(1, capacity(c));
+    const int64_t rounds = (base_waves * c + cap - 1) / cap;
+    const double per_wave = (double)((n_levels - 1 + c - 1) / c + 1);
+    const double cost = (double)rounds * per_wave * (1.0 + 0.02 * c);
+    if (cost < best_cost * 0.999) {
+      best_cost = cost;
+      best = c;
+    }
+  }
+  return best;
 }
 
 }  // namespace hr2
@@ -557,12 +604,17 @@ hr2_status plan_obs(const hr2_tables *t, const hr2_window &w, double R, int n_bi
   pl.n_pts = pl.idx[n_bins] - pl.i0 + 1;
   pl.h.assign(pl.n_pts, 0);
   const double denom = R * 2.0 * std::sqrt(2.0 * std::log(2.0));
+  // 5 sigma grows by less than one grid step per point, so h is found
+  // incrementally from its neighbour (the test itself is unchanged)
+  int64_t hh = -1;
   for (int64_t q = 0; q < pl.n_pts; ++q) {
     const int64_t i = pl.i0 + q;
     const double sig = (pl.first + (double)i * pl.dnu) / denom;
-    const double hv = std::floor(5.0 * sig / pl.dnu);
-    if (!(hv < 1e9)) return set_error(HR2_E_OUT_OF_RANGE, "instrument profile too wide");
-    int64_t hh = (int64_t)hv;
+    if (hh < 0) {
+      const double hv = std::floor(5.0 * sig / pl.dnu);
+      if (!(hv < 1e9)) return set_error(HR2_E_OUT_OF_RANGE, "instrument profile too wide");
+      hh = (int64_t)hv;
+    }
     while ((double)(hh + 1) * pl.dnu <= 5.0 * sig) ++hh;
     while (hh > 0 && (double)hh * pl.dnu > 5.0 * sig) --hh;
     pl.h[q] = (int32_t)std::min<int64_t>(hh, pl.N);
@@ -631,9 +683,9 @@ extern "C" hr2_status hr2_obs_create(hr2_ctx *ctx, const hr2_tables *t, hr2_wind
   if (e == hipSuccess)
     e = hipMemcpyAsync(d_h, pl.h.data(), n_pts * sizeof(int32_t), hipMemcpyHostToDevice, s);
   if (e == hipSuccess)
-    e = launch_obs_build(o->fp64, pl.N, pl.first, pl.dnu, R, n_bins, (const int64_t *)d_edges,
-                         (const int32_t *)d_h, pl.i0, n_pts, d_q, d_z, o->d_kstart, o->d_mlo,
-                         o->d_mlen, o->d_K, s);
+    e = launch_obs_build(o->fp64, pl.N, pl.first, pl.dnu, R, n_bins, nnz,
+                         (const int64_t *)d_edges, (const int32_t *)d_h, pl.i0, n_pts, d_q, d_z,
+                         o->d_kstart, o->d_mlo, o->d_K, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (d_edges) (void)hipFree(d_edges);
   if (d_h) (void)hipFree(d_h);
@@ -714,7 +766,8 @@ extern "C" hr2_status hr2_rt_emission(hr2_ctx *ctx, const hr2_tables *t, const h
   if ((st = one_column_records(ctx, t, col, s)) != HR2_OK) return st;
   const int64_t base_waves = (w.nu_count + 63) / 64;
   const int chunks = ctx->opt_chunks ? std::min(ctx->opt_chunks, std::max(1, col->n_levels - 1))
-                                     : auto_chunks(base_waves, col->n_levels);
+                                     : auto_chunks(t->view, base_waves, col->n_levels, n_mu,
+                                                   true);
   ColSeg seg{};
   seg.wg_begin = 0;
   seg.nu_begin = w.nu_begin;
@@ -732,7 +785,7 @@ extern "C" hr2_status hr2_rt_emission(hr2_ctx *ctx, const hr2_tables *t, const h
   seg.tiles_per_set = (int32_t)((w.nu_count + per_wg - 1) / per_wg);
   if ((st = upload_cached(ctx, ctx->segs, ctx->segs_shadow, &seg, sizeof(seg), s)) != HR2_OK)
     return st;
-  HIP_TRY(launch_column(t->view, (const ColSeg *)ctx->segs.ptr, 1, seg.tiles_per_set,
+  HIP_TRY(launch_column(t->view, (const ColSeg *)ctx->segs.ptr, 1, seg.tiles_per_set, chunks,
                         ctx->recs.ptr, chi, fplus, n_mu, true, s));
   return ctx_end(ctx, s);
 }
@@ -785,10 +838,15 @@ hr2_status run_forward(hr2_ctx *ctx, const hr2_tables *t, const hr2_obs *o, cons
                        int n_mu, void *bins, void *fplus, int *status, hipStream_t s) {
   const hr2_window &w = o->window;
   const int B = cv.B, L = cv.L;
-  hr2_status st = ctx->recs.ensure((size_t)B * L * rec_size(t));
+  const size_t rec_bytes = (size_t)B * L * rec_size(t);
+  const size_t fp_bytes = fplus == nullptr ? (size_t)B * w.nu_count * real_size(t) : 0;
+  if ((rec_bytes > ctx->recs.cap || fp_bytes > ctx->fplus.cap) && capturing(s))
+    return set_error(HR2_E_UNSUPPORTED,
+                     "scratch would grow under stream capture: make the same call once first");
+  hr2_status st = ctx->recs.ensure(rec_bytes);
   if (st != HR2_OK) return st;
   if (fplus == nullptr) {
-    if ((st = ctx->fplus.ensure((size_t)B * w.nu_count * real_size(t))) != HR2_OK) return st;
+    if ((st = ctx->fplus.ensure(fp_bytes)) != HR2_OK) return st;
     fplus = ctx->fplus.ptr;
   }
   hipEvent_t ev[4] = {timing_event(ctx, 0), timing_event(ctx, 1), timing_event(ctx, 2),
@@ -798,7 +856,7 @@ hr2_status run_forward(hr2_ctx *ctx, const hr2_tables *t, const hr2_obs *o, cons
   HIP_TRY(launch_levels(t->view, cv, ctx->recs.ptr, status, t->view.dtype == HR2_TABLE_F64, s));
   const int64_t base_waves = (int64_t)B * ((w.nu_count + 63) / 64);
   const int chunks = ctx->opt_chunks ? std::min(ctx->opt_chunks, std::max(1, L - 1))
-                                     : auto_chunks(base_waves, L);
+                                     : auto_chunks(t->view, base_waves, L, n_mu, false);
   const int per_wg = column_nu_per_wg(chunks);
   ColSeg seg{};
   seg.wg_begin = 0;
@@ -819,8 +877,8 @@ hr2_status run_forward(hr2_ctx *ctx, const hr2_tables *t, const hr2_obs *o, cons
   if ((st = upload_cached(ctx, ctx->segs, ctx->segs_shadow, &seg, sizeof(seg), s)) != HR2_OK)
     return st;
   if (timed) HIP_TRY(hipEventRecord(ev[1], s));
-  HIP_TRY(launch_column(t->view, (const ColSeg *)ctx->segs.ptr, 1, total_wgs, ctx->recs.ptr,
-                        nullptr, fplus, n_mu, false, s));
+  HIP_TRY(launch_column(t->view, (const ColSeg *)ctx->segs.ptr, 1, total_wgs, chunks,
+                        ctx->recs.ptr, nullptr, fplus, n_mu, false, s));
   ConvSeg cs{};
   cs.item_begin = 0;
   cs.K = o->d_K;

@@ -53,7 +53,7 @@ hr2_status check_n_mu(int n_mu);
 void pack_columns(const hr2_tables *t, int n_sets, const hr2_column *cols,
                   std::vector<double> &buf);
 ColumnsView columns_view(const void *dev, int n_sets, int L, int S);
-int auto_chunks(int64_t base_waves, int n_levels);
+int auto_chunks(const TableView &tv, int64_t base_waves, int n_levels, int n_mu, bool from_chi);
 
 struct ObsPlan {
   int64_t N = 0, i0 = 0, n_pts = 0, nnz = 0;

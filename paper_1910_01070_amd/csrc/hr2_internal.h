@@ -94,7 +94,7 @@ struct ColSeg {
   int64_t out_stride;
   int64_t chi_offset;      // stage call only: chi + chi_offset + l * nu_count
   int32_t n_sets, n_levels, tiles_per_set, n_mu;
-  int32_t chunks;          // layer chunks per wavenumber sub-tile: 1, 2 or 4
+  int32_t chunks;          // layer chunks per 64-point tile, 1..8 (= waves per workgroup)
   int32_t pad;
 };
 
@@ -130,10 +130,14 @@ hipError_t upload_angle_table(const AngleTable &t);
 hipError_t launch_levels(const TableView &tv, const ColumnsView &cv, void *recs,
                          int *status, bool fp64, hipStream_t stream);
 
+// One workgroup = `chunks` waves = one 64-point tile of one set; every
+// segment of the launch must use that chunk count.
 hipError_t launch_column(const TableView &tv, const ColSeg *segs_dev, int n_segs,
-                         int64_t total_wgs, const void *recs, const void *chi_in, void *out,
-                         int max_mu, bool opacity_from_memory, hipStream_t stream);
+                         int64_t total_wgs, int chunks, const void *recs, const void *chi_in,
+                         void *out, int max_mu, bool opacity_from_memory, hipStream_t stream);
 int column_nu_per_wg(int chunks);
+// Waves of the column kernel (with this chunk count) the device holds at once.
+int column_wave_capacity(const TableView &tv, int max_mu, bool opacity_from_memory, int chunks);
 
 hipError_t launch_opacity_only(const TableView &tv, const void *recs, int n_levels,
                                int64_t nu_begin, int64_t nu_count, int64_t nu_stride,
@@ -143,13 +147,13 @@ hipError_t launch_convolve_bin(bool fp64, const ConvSeg *segs_dev, int n_segs,
                                int64_t total_items, const void *in, void *out,
                                hipStream_t stream);
 
-// Observation layout build: Z_i and q_i for window points [i0, i0 + n)
-// then the banded per-bin weights.
+// Observation layout build: Z_i and q_i for window points [i0, i0 + n_pts),
+// then the nnz banded per-bin weights.
 hipError_t launch_obs_build(bool fp64, int64_t N, double nu_first, double dnu_eff, double R,
-                            int n_bins, const int64_t *edge_idx_dev, const int32_t *h_dev,
-                            int64_t i0, int64_t n_pts, void *q_scratch, void *invz_scratch,
-                            const int64_t *kstart_dev, const int32_t *mlo_dev,
-                            const int32_t *mlen_dev, void *K_dev, hipStream_t stream);
+                            int n_bins, int64_t nnz, const int64_t *edge_idx_dev,
+                            const int32_t *h_dev, int64_t i0, int64_t n_pts, void *q_scratch,
+                            void *invz_scratch, const int64_t *kstart_dev, const int32_t *mlo_dev,
+                            void *K_dev, hipStream_t stream);
 
 }  // namespace hr2
 

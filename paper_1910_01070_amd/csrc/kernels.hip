@@ -88,19 +88,6 @@ __device__ __forceinline__ double buf_load<double>(rsrc_t r, uint32_t off, uint3
 __device__ __forceinline__ float fexp2(float x) { return __builtin_amdgcn_exp2f(x); }
 __device__ __forceinline__ float frcp(float x) { return __builtin_amdgcn_rcpf(x); }
 
-// Axis lookup of the table (reading of Sect. 2.3): clamp, lower node = the
-// largest index with axis[i] <= v capped at n-2, w = (v - a_i)/(a_{i+1} - a_i).
-__device__ __forceinline__ void locate(const double *axis, int n, double v, int &i, double &w) {
-  v = v < axis[0] ? axis[0] : v;
-  v = v > axis[n - 1] ? axis[n - 1] : v;
-  int k = 0;
-  for (int q = 1; q < n; ++q)
-    if (axis[q] <= v) k = q;
-  if (k > n - 2) k = n - 2;
-  i = k;
-  w = (v - axis[k]) / (axis[k + 1] - axis[k]);
-}
-
 // ------------------------------------------------------------ level records
 // One thread per (set, level).  Everything here is FP64; the column kernel
 // gets FP32 (FP64 for F64 tables) per-level constants:
@@ -114,13 +101,6 @@ struct CellW {
   int iT, ip;
   double wT, wp;
 };
-
-__device__ __forceinline__ CellW cell_of(const TableView &tv, double T, double p) {
-  CellW c;
-  locate(tv.T_axis, tv.nT, T, c.iT, c.wT);
-  locate(tv.lp_axis, tv.nP, log10(p), c.ip, c.wp);
-  return c;
-}
 
 // slot k <-> corner (a, b) of the cell with row parity k
 __device__ __forceinline__ void slot_corner(const CellW &c, int k, int nP, int &row, double &w) {
@@ -136,16 +116,38 @@ __device__ __forceinline__ void cia_slot(const CellW &c, int k, int &row, double
   w = a ? c.wT : 1.0 - c.wT;
 }
 
+constexpr int kMaxAxis = 256;
+
+// Axis lookup (reading of Sect. 2.3): lower node = the largest index with
+// a[i] <= v (v clamped to the axis), at most n-2, and w = (v - a_i)/(a_{i+1}
+// - a_i); binary search over the LDS copy of the axis
+__device__ __forceinline__ void locate_lds(const double *a, int n, double v, int &i, double &w) {
+  v = v < a[0] ? a[0] : v;
+  v = v > a[n - 1] ? a[n - 1] : v;
+  int lo = 0, hi = n - 1;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (a[mid] <= v) lo = mid;
+    else hi = mid;
+  }
+  i = lo;
+  w = (v - a[lo]) / (a[lo + 1] - a[lo]);
+}
+
 template <typename Real>
 __global__ __launch_bounds__(128) void k_levels(TableView tv, ColumnsView cv,
                                                 typename RecOf<Real>::type *recs, int *status) {
   using Rec = typename RecOf<Real>::type;
+  __shared__ double s_T[kMaxAxis], s_lp[kMaxAxis];
+  __shared__ CellW s_cell[HR2_MAX_LEVELS];
   const int s = blockIdx.x;
   const int L = cv.L;
   const int S = tv.S;
   const double *p = cv.p + (int64_t)s * L;
   const double *T = cv.T + (int64_t)s * L;
   const double *x = cv.x + (int64_t)s * S;
+  for (int i = threadIdx.x; i < tv.nT; i += blockDim.x) s_T[i] = tv.T_axis[i];
+  for (int i = threadIdx.x; i < tv.nP; i += blockDim.x) s_lp[i] = tv.lp_axis[i];
 
   // column-wide quantities and validity (Sect. 5.2 filler gas, Table 1 inputs)
   bool bad = false;
@@ -160,8 +162,15 @@ __global__ __launch_bounds__(128) void k_levels(TableView tv, ColumnsView cv,
     bad |= !(p[l] > 0.0) || !isfinite(p[l]) || !(T[l] > 0.0) || !isfinite(T[l]);
     if (l + 1 < L) bad |= !(p[l] > p[l + 1]);
   }
-  bad = __syncthreads_or(bad);
+  bad = __syncthreads_or(bad);   // also orders the axis copies
   if (status != nullptr && threadIdx.x == 0) status[s] = bad ? (int)HR2_E_INVALID_ARG : 0;
+  for (int l = threadIdx.x; l < L; l += blockDim.x) {
+    CellW c;
+    locate_lds(s_T, tv.nT, T[l], c.iT, c.wT);
+    locate_lds(s_lp, tv.nP, log10(p[l]), c.ip, c.wp);
+    s_cell[l] = c;
+  }
+  __syncthreads();
 
   const double h2 = (1.0 - xs) / (1.0 + tv.he_ratio);
   const double he = tv.he_ratio * h2;
@@ -174,10 +183,9 @@ __global__ __launch_bounds__(128) void k_levels(TableView tv, ColumnsView cv,
   for (int l = threadIdx.x; l < L; l += blockDim.x) {
     const double n = p[l] * 1.0e6 / (kKB * T[l]);
     Rec r;
-    const CellW c = cell_of(tv, T[l], p[l]);
-    CellW cp = c;
+    const CellW c = s_cell[l];
     const bool has_prev = l > 0;
-    if (has_prev) cp = cell_of(tv, T[l - 1], p[l - 1]);
+    const CellW cp = has_prev ? s_cell[l - 1] : c;
     int mask = 0;
     double wsl[4];
     int rowsl[4];
@@ -210,12 +218,20 @@ __global__ __launch_bounds__(128) void k_levels(TableView tv, ColumnsView cv,
     r.mask = mask;
 
     // n_s 2^{interpolated row offset}: the kernel exponentiates only the
-    // stored (offset-free) part, keeping its exp2 argument small.
+    // stored (offset-free) part, keeping its exp2 argument small.  All
+    // offsets are fetched before any arithmetic so their latencies overlap.
+    double offv[kMaxSpecies][4];
+#pragma unroll
+    for (int q = 0; q < kMaxSpecies; ++q)
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+        offv[q][k] = q < S ? tv.off[q * rows_per_species + rowsl[k]] : 0.0;
+#pragma unroll
     for (int q = 0; q < kMaxSpecies; ++q) {
       double a = 0.0;
       if (q < S) {
-        double cq = 0.0;
-        for (int k = 0; k < 4; ++k) cq += wsl[k] * tv.off[q * rows_per_species + rowsl[k]];
+        const double cq = wsl[0] * offv[q][0] + wsl[1] * offv[q][1] + wsl[2] * offv[q][2] +
+                          wsl[3] * offv[q][3];
         a = x[q] * n * exp2(cq);
       }
       r.a_s[q] = (Real)a;
@@ -355,17 +371,21 @@ __device__ __forceinline__ double sc_step_d(double I, double dtau, double S1, do
 // NS: species slots compiled; a negative NS means exactly -NS species (no
 // per-species guards), otherwise tv.S <= NS species with uniform guards.
 template <typename Real, typename TT, int NSS, int MAXMU, bool FROM_CHI, bool BIG>
-__global__ __launch_bounds__(256) void k_column(TableView tv, const ColSeg *__restrict__ segs,
+__global__ __launch_bounds__(512) void k_column(TableView tv, const ColSeg *__restrict__ segs,
                                                 int n_segs, int64_t total_wgs,
-                                                const typename RecOf<Real>::type *__restrict__ recs,
-                                                const Real *__restrict__ chi_in,
-                                                Real *__restrict__ out) {
+                                                const void *__restrict__ recs_v,
+                                                const void *__restrict__ chi_in_v,
+                                                void *__restrict__ out_v) {
   using Rec = typename RecOf<Real>::type;
   constexpr bool kF64 = std::is_same<Real, double>::value;
   constexpr int NS = NSS < 0 ? -NSS : NSS;
   constexpr bool kExact = NSS < 0;
-  __shared__ Real sh_B[4][MAXMU][64];
-  __shared__ Real sh_tau[4][64];
+  const Rec *__restrict__ recs = (const Rec *)recs_v;
+  const Real *__restrict__ chi_in = (const Real *)chi_in_v;
+  Real *__restrict__ out = (Real *)out_v;
+  // chunk c's affine map (per angle: B, then the chunk's optical depth)
+  extern __shared__ unsigned char sh_raw[];
+  Real *sh = (Real *)sh_raw;
 
   const int64_t g = xcd_remap(blockIdx.x, total_wgs);
   int sg = 0;
@@ -373,22 +393,21 @@ __global__ __launch_bounds__(256) void k_column(TableView tv, const ColSeg *__re
     if (segs[i].wg_begin <= g) sg = i;
   const ColSeg &d = segs[sg];
   const int n_sets = d.n_sets;
-  const int C = d.chunks;
+  const int C = blockDim.x >> 6;   // one wave per layer chunk (the segment's chunks)
   const int64_t local = g - d.wg_begin;
   const int64_t t = local / n_sets;
   const int s = (int)(local - t * n_sets);
 
   // the wave index is uniform across a wavefront; say so, so that everything
   // derived from it (chunk, levels, records, load masks) stays scalar
-  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int chunk = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
-  const int chunk = wave % C, sub = wave / C;
   const int L = d.n_levels, nlay = L - 1;
   const int m = (nlay + C - 1) / C;
   const int l0 = chunk * m;
   const int l1 = min(l0 + m, nlay);
   const int64_t nu_count = d.nu_count;
-  const int64_t j = t * (int64_t)(4 / C) * 64 + sub * 64 + lane;
+  const int64_t j = t * 64 + lane;
   const bool active = j < nu_count;
   const int64_t jj = active ? j : nu_count - 1;
   const int64_t kidx = d.nu_begin + jj * d.nu_stride;
@@ -542,23 +561,24 @@ __global__ __launch_bounds__(256) void k_column(TableView tv, const ColSeg *__re
           F = fmaf(c_ang.cw[nmu - 1][k], I[k], F);
       }
   } else {
-    sh_tau[wave][lane] = tau;
+    // layout: sh[(c * (MAXMU + 1) + k) * 64 + lane], k = MAXMU holds tau
+    sh[(chunk * (MAXMU + 1) + MAXMU) * 64 + lane] = tau;
 #pragma unroll
-    for (int k = 0; k < MAXMU; ++k) sh_B[wave][k][lane] = I[k];
+    for (int k = 0; k < MAXMU; ++k) sh[(chunk * (MAXMU + 1) + k) * 64 + lane] = I[k];
     __syncthreads();
     if (chunk == C - 1) {
-      const int w0 = sub * C;
 #pragma unroll
       for (int k = 0; k < MAXMU; ++k)
         if (k < nmu) {
-          Real acc = sh_B[w0][k][lane];
+          Real acc = sh[k * 64 + lane];
           for (int c = 1; c < C; ++c) {
+            const Real tc = sh[(c * (MAXMU + 1) + MAXMU) * 64 + lane];
             Real tr;
             if constexpr (kF64)
-              tr = exp(-sh_tau[w0 + c][lane] / c_ang.mu_d[nmu - 1][k]);
+              tr = exp(-tc / a_mud[k]);
             else
-              tr = fexp2(-sh_tau[w0 + c][lane] * c_ang.l2e_mu[nmu - 1][k]);
-            acc = tr * acc + sh_B[w0 + c][k][lane];
+              tr = fexp2(-tc * a_l2e[k]);
+            acc = tr * acc + sh[(c * (MAXMU + 1) + k) * 64 + lane];
           }
           if constexpr (kF64)
             F += c_ang.cw_d[nmu - 1][k] * acc;
@@ -570,84 +590,87 @@ __global__ __launch_bounds__(256) void k_column(TableView tv, const ColSeg *__re
   if (active && chunk == C - 1) out[d.out_offset + (int64_t)s * d.out_stride + j] = F;
 }
 
-int column_nu_per_wg(int chunks) { return (4 / chunks) * 64; }
+int column_nu_per_wg(int) { return 64; }
+
+using ColumnFn = void (*)(TableView, const ColSeg *, int, int64_t, const void *, const void *,
+                         void *);
+struct ColumnKernel {
+  ColumnFn fn;
+  int max_mu;
+  int real_bytes;
+};
 
 template <typename Real, typename TT, int NS, int MAXMU, bool FROM_CHI, bool BIG = false>
-static hipError_t launch_column_t(const TableView &tv, const ColSeg *segs, int n_segs,
-                                  int64_t total_wgs, const void *recs, const void *chi_in,
-                                  void *out, hipStream_t stream) {
-  hipLaunchKernelGGL((k_column<Real, TT, NS, MAXMU, FROM_CHI, BIG>), dim3((unsigned)total_wgs),
-                     dim3(256), 0, stream, tv, segs, n_segs, total_wgs,
-                     (const typename RecOf<Real>::type *)recs, (const Real *)chi_in, (Real *)out);
-  return hipGetLastError();
+static ColumnKernel ck() {
+  return ColumnKernel{&k_column<Real, TT, NS, MAXMU, FROM_CHI, BIG>, MAXMU, (int)sizeof(Real)};
 }
 
 template <typename Real, typename TT, bool FROM_CHI>
-static hipError_t launch_column_ns(const TableView &tv, const ColSeg *segs, int n_segs,
-                                   int64_t total_wgs, const void *recs, const void *chi_in,
-                                   void *out, int max_mu, hipStream_t stream) {
+static ColumnKernel pick_ns(const TableView &tv, int max_mu) {
   const int S = tv.S;
   if constexpr (FROM_CHI) {
-    if (max_mu <= 4)
-      return launch_column_t<Real, TT, 1, 4, true>(tv, segs, n_segs, total_wgs, recs, chi_in, out,
-                                                   stream);
-    return launch_column_t<Real, TT, 1, 8, true>(tv, segs, n_segs, total_wgs, recs, chi_in, out,
-                                                 stream);
+    if (max_mu <= 4) return ck<Real, TT, 1, 4, true>();
+    return ck<Real, TT, 1, 8, true>();
   } else {
     const int64_t table_bytes = (int64_t)tv.S * tv.nT * tv.nP * tv.pitch * (int64_t)sizeof(TT);
-    if (table_bytes >= 0xFFFFFFFFll)
-      return launch_column_t<Real, TT, kMaxSpecies, 8, false, true>(tv, segs, n_segs, total_wgs,
-                                                                    recs, chi_in, out, stream);
+    if (table_bytes >= 0xFFFFFFFFll) return ck<Real, TT, kMaxSpecies, 8, false, true>();
     if (max_mu <= 4) {
-      if (S <= 1)
-        return launch_column_t<Real, TT, -1, 4, false>(tv, segs, n_segs, total_wgs, recs, chi_in,
-                                                       out, stream);
-      if (S == 8)
-        return launch_column_t<Real, TT, -8, 4, false>(tv, segs, n_segs, total_wgs, recs, chi_in,
-                                                       out, stream);
-      if (S <= 8)
-        return launch_column_t<Real, TT, 8, 4, false>(tv, segs, n_segs, total_wgs, recs, chi_in,
-                                                      out, stream);
-      return launch_column_t<Real, TT, kMaxSpecies, 4, false>(tv, segs, n_segs, total_wgs, recs,
-                                                              chi_in, out, stream);
+      if (S <= 1) return ck<Real, TT, -1, 4, false>();
+      if (S == 8) return ck<Real, TT, -8, 4, false>();
+      if (S <= 8) return ck<Real, TT, 8, 4, false>();
+      return ck<Real, TT, kMaxSpecies, 4, false>();
     }
-    if (S <= 1)
-      return launch_column_t<Real, TT, -1, 8, false>(tv, segs, n_segs, total_wgs, recs, chi_in,
-                                                     out, stream);
-    if (S <= 8)
-      return launch_column_t<Real, TT, 8, 8, false>(tv, segs, n_segs, total_wgs, recs, chi_in,
-                                                    out, stream);
-    return launch_column_t<Real, TT, kMaxSpecies, 8, false>(tv, segs, n_segs, total_wgs, recs,
-                                                            chi_in, out, stream);
+    if (S <= 1) return ck<Real, TT, -1, 8, false>();
+    if (S <= 8) return ck<Real, TT, 8, 8, false>();
+    return ck<Real, TT, kMaxSpecies, 8, false>();
   }
 }
 
-hipError_t launch_column(const TableView &tv, const ColSeg *segs_dev, int n_segs,
-                         int64_t total_wgs, const void *recs, const void *chi_in, void *out,
-                         int max_mu, bool opacity_from_memory, hipStream_t stream) {
-  if (total_wgs <= 0) return hipSuccess;
-  if (opacity_from_memory) {
-    // stage 2 alone: the storage type is irrelevant
-    if (tv.dtype == HR2_TABLE_F64)
-      return launch_column_ns<double, double, true>(tv, segs_dev, n_segs, total_wgs, recs, chi_in,
-                                                    out, max_mu, stream);
-    return launch_column_ns<float, float, true>(tv, segs_dev, n_segs, total_wgs, recs, chi_in,
-                                                out, max_mu, stream);
+static ColumnKernel pick_column(const TableView &tv, int max_mu, bool from_chi) {
+  if (from_chi) {
+    if (tv.dtype == HR2_TABLE_F64) return pick_ns<double, double, true>(tv, max_mu);
+    return pick_ns<float, float, true>(tv, max_mu);
   }
   switch (tv.dtype) {
-    case HR2_TABLE_F64:
-      return launch_column_ns<double, double, false>(tv, segs_dev, n_segs, total_wgs, recs,
-                                                     chi_in, out, max_mu, stream);
-    case HR2_TABLE_F16:
-      return launch_column_ns<float, _Float16, false>(tv, segs_dev, n_segs, total_wgs, recs,
-                                                      chi_in, out, max_mu, stream);
-    case HR2_TABLE_BF16:
-      return launch_column_ns<float, uint16_t, false>(tv, segs_dev, n_segs, total_wgs, recs,
-                                                      chi_in, out, max_mu, stream);
-    default:
-      return launch_column_ns<float, float, false>(tv, segs_dev, n_segs, total_wgs, recs, chi_in,
-                                                   out, max_mu, stream);
+    case HR2_TABLE_F64: return pick_ns<double, double, false>(tv, max_mu);
+    case HR2_TABLE_F16: return pick_ns<float, _Float16, false>(tv, max_mu);
+    case HR2_TABLE_BF16: return pick_ns<float, uint16_t, false>(tv, max_mu);
+    default: return pick_ns<float, float, false>(tv, max_mu);
   }
+}
+
+static size_t column_shmem(const ColumnKernel &k, int chunks) {
+  return chunks > 1 ? (size_t)chunks * (k.max_mu + 1) * 64 * k.real_bytes : 0;
+}
+
+hipError_t launch_column(const TableView &tv, const ColSeg *segs_dev, int n_segs,
+                         int64_t total_wgs, int chunks, const void *recs, const void *chi_in,
+                         void *out, int max_mu, bool opacity_from_memory, hipStream_t stream) {
+  if (total_wgs <= 0) return hipSuccess;
+  const ColumnKernel k = pick_column(tv, max_mu, opacity_from_memory);
+  hipLaunchKernelGGL(k.fn, dim3((unsigned)total_wgs), dim3(64 * chunks),
+                     column_shmem(k, chunks), stream, tv, segs_dev, n_segs, total_wgs, recs,
+                     chi_in, out);
+  return hipGetLastError();
+}
+
+int column_wave_capacity(const TableView &tv, int max_mu, bool opacity_from_memory, int chunks) {
+  const ColumnKernel k = pick_column(tv, max_mu, opacity_from_memory);
+  int blocks = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, (const void *)k.fn, 64 * chunks,
+                                                   column_shmem(k, chunks)) != hipSuccess ||
+      blocks < 1) {
+    (void)hipGetLastError();
+    blocks = 1;
+  }
+  int dev = 0, n_cu = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      n_cu < 1) {
+    (void)hipGetLastError();
+    n_cu = 1;
+  }
+  return blocks * chunks * n_cu;
 }
 
 // ------------------------------------------------------- stage 1 on its own
@@ -784,7 +807,9 @@ template <typename Real>
 __global__ __launch_bounds__(256) void k_obs_norm(int64_t N, double nu_first, double dnu,
                                                   double R, const int32_t *h, int64_t i0,
                                                   int64_t n, Real *q_out, Real *invz_out) {
-  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  // one wave per window point: lanes split the 2h+1 taps, fixed butterfly sum
+  const int64_t t = (int64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
   if (t >= n) return;
   const int64_t i = i0 + t;
   const double sig = (nu_first + (double)i * dnu) / (R * 2.0 * sqrt(2.0 * log(2.0)));
@@ -792,81 +817,90 @@ __global__ __launch_bounds__(256) void k_obs_norm(int64_t N, double nu_first, do
   int64_t klo = -hi, khi = hi;
   if (i + klo < 0) klo = -i;
   if (i + khi > N - 1) khi = N - 1 - i;
+  Real z = (Real)0, q;
   if constexpr (std::is_same<Real, double>::value) {
-    double z = 0.0;
-    for (int64_t k = klo; k <= khi; ++k) {
+    for (int64_t k = klo + lane; k <= khi; k += 64) {
       const double dx = (double)(k < 0 ? -k : k) * dnu;
       z += exp(-dx * dx / (2.0 * sig * sig));
     }
-    q_out[t] = 1.0 / (2.0 * sig * sig);
-    invz_out[t] = 1.0 / z;
+    q = 1.0 / (2.0 * sig * sig);
   } else {
-    const float q = (float)(dnu * dnu * kLog2e / (2.0 * sig * sig));
-    float z = 0.0f;
-    for (int64_t k = klo; k <= khi; ++k) {
+    q = (float)(dnu * dnu * kLog2e / (2.0 * sig * sig));
+    for (int64_t k = klo + lane; k <= khi; k += 64) {
       const float kf = (float)k;
       z += fexp2(-(kf * kf) * q);
     }
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) z += __shfl_xor(z, off, 64);
+  if (lane == 0) {
     q_out[t] = q;
-    invz_out[t] = 1.0f / z;
+    invz_out[t] = (Real)1 / z;
   }
 }
 
 template <typename Real>
-__global__ __launch_bounds__(256) void k_obs_weights(const int64_t *edge_idx, const int32_t *h,
+__global__ __launch_bounds__(256) void k_obs_weights(int n_bins, int64_t nnz,
+                                                     const int64_t *edge_idx, const int32_t *h,
                                                      int64_t i0, const Real *q, const Real *invz,
                                                      double dnu, const int64_t *kstart,
-                                                     const int32_t *mlo, const int32_t *mlen,
-                                                     Real *K) {
-  const int jb = blockIdx.x;
-  const int64_t a = edge_idx[jb], b = edge_idx[jb + 1];
-  const int64_t lo = mlo[jb];
-  const int len = mlen[jb];
-  const int hmax = h[b - i0] > h[a - i0] ? h[b - i0] : h[a - i0];
-  const Real coef = (Real)(1.0 / (double)(b - a));
-  for (int xo = threadIdx.x; xo < len; xo += 256) {
-    const int64_t x = lo + xo;
-    int64_t ia = x - hmax, ib = x + hmax;
-    if (ia < a) ia = a;
-    if (ib > b) ib = b;
-    Real acc = (Real)0;
-    for (int64_t i = ia; i <= ib; ++i) {
-      const int64_t k = x - i;
-      const int64_t ak = k < 0 ? -k : k;
-      if (ak > h[i - i0]) continue;
-      const Real ci = (i == a || i == b) ? (Real)0.5 : (Real)1;
-      Real gk;
-      if constexpr (std::is_same<Real, double>::value) {
-        const double dx = (double)ak * dnu;
-        gk = exp(-dx * dx * q[i - i0]);
-      } else {
-        const float kf = (float)ak;
-        gk = fexp2(-(kf * kf) * q[i - i0]);
-      }
-      acc += ci * gk * invz[i - i0];
-    }
-    K[kstart[jb] + xo] = acc * coef;
+                                                     const int32_t *mlo, Real *K) {
+  // one thread per stored weight: find its bin, then sum the bin's
+  // Gaussians that reach this point
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= nnz) return;
+  int lo = 0, hi = n_bins;   // largest j with kstart[j] <= e
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (kstart[mid] <= e) lo = mid;
+    else hi = mid;
   }
+  const int jb = lo;
+  const int64_t a = edge_idx[jb], b = edge_idx[jb + 1];
+  const int64_t x = mlo[jb] + (e - kstart[jb]);
+  const int hmax = h[b - i0] > h[a - i0] ? h[b - i0] : h[a - i0];
+  int64_t ia = x - hmax, ib = x + hmax;
+  if (ia < a) ia = a;
+  if (ib > b) ib = b;
+  Real acc = (Real)0;
+  for (int64_t i = ia; i <= ib; ++i) {
+    const int64_t k = x - i;
+    const int64_t ak = k < 0 ? -k : k;
+    if (ak > h[i - i0]) continue;
+    const Real ci = (i == a || i == b) ? (Real)0.5 : (Real)1;
+    Real gk;
+    if constexpr (std::is_same<Real, double>::value) {
+      const double dx = (double)ak * dnu;
+      gk = exp(-dx * dx * q[i - i0]);
+    } else {
+      const float kf = (float)ak;
+      gk = fexp2(-(kf * kf) * q[i - i0]);
+    }
+    acc += ci * gk * invz[i - i0];
+  }
+  K[e] = acc * (Real)(1.0 / (double)(b - a));
 }
 
 hipError_t launch_obs_build(bool fp64, int64_t N, double nu_first, double dnu_eff, double R,
-                            int n_bins, const int64_t *edge_idx_dev, const int32_t *h_dev,
-                            int64_t i0, int64_t n_pts, void *q_scratch, void *invz_scratch,
-                            const int64_t *kstart_dev, const int32_t *mlo_dev,
-                            const int32_t *mlen_dev, void *K_dev, hipStream_t stream) {
-  const dim3 g1((unsigned)((n_pts + 255) / 256));
+                            int n_bins, int64_t nnz, const int64_t *edge_idx_dev,
+                            const int32_t *h_dev, int64_t i0, int64_t n_pts, void *q_scratch,
+                            void *invz_scratch, const int64_t *kstart_dev, const int32_t *mlo_dev,
+                            void *K_dev, hipStream_t stream) {
+  const dim3 g1((unsigned)((n_pts + 3) / 4));
+  const dim3 g2((unsigned)((nnz + 255) / 256));
   if (fp64) {
     hipLaunchKernelGGL(k_obs_norm<double>, g1, dim3(256), 0, stream, N, nu_first, dnu_eff, R,
                        h_dev, i0, n_pts, (double *)q_scratch, (double *)invz_scratch);
-    hipLaunchKernelGGL(k_obs_weights<double>, dim3(n_bins), dim3(256), 0, stream, edge_idx_dev,
-                       h_dev, i0, (const double *)q_scratch, (const double *)invz_scratch,
-                       dnu_eff, kstart_dev, mlo_dev, mlen_dev, (double *)K_dev);
+    hipLaunchKernelGGL(k_obs_weights<double>, g2, dim3(256), 0, stream, n_bins, nnz,
+                       edge_idx_dev, h_dev, i0, (const double *)q_scratch,
+                       (const double *)invz_scratch, dnu_eff, kstart_dev, mlo_dev,
+                       (double *)K_dev);
   } else {
     hipLaunchKernelGGL(k_obs_norm<float>, g1, dim3(256), 0, stream, N, nu_first, dnu_eff, R,
                        h_dev, i0, n_pts, (float *)q_scratch, (float *)invz_scratch);
-    hipLaunchKernelGGL(k_obs_weights<float>, dim3(n_bins), dim3(256), 0, stream, edge_idx_dev,
+    hipLaunchKernelGGL(k_obs_weights<float>, g2, dim3(256), 0, stream, n_bins, nnz, edge_idx_dev,
                        h_dev, i0, (const float *)q_scratch, (const float *)invz_scratch, dnu_eff,
-                       kstart_dev, mlo_dev, mlen_dev, (float *)K_dev);
+                       kstart_dev, mlo_dev, (float *)K_dev);
   }
   return hipGetLastError();
 }

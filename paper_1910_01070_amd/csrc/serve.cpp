@@ -217,22 +217,39 @@ bool hr2_server::launch_step(StepSlot &sl, std::vector<Req *> &reqs) {
   unsigned char *base = (unsigned char *)arena_dev;
   unsigned char *pbase = (unsigned char *)arena_pin;
   if (hipSetDevice(ctx->device) != hipSuccess) return false;
+  // column launches group the requests by chunk count (= workgroup size)
+  // and by angle class (kernel variant), so each request runs exactly the
+  // code it would run alone
+  std::stable_sort(reqs.begin(), reqs.end(), [](const Req *a, const Req *b) {
+    const int ka = a->chunks * 2 + (a->n_mu > 4), kb = b->chunks * 2 + (b->n_mu > 4);
+    return ka < kb;
+  });
   std::vector<ColSeg> cs(reqs.size());
   std::vector<ConvSeg> vs(reqs.size());
+  struct Group {
+    size_t first, count;
+    int64_t wgs;
+    int chunks, max_mu;
+  };
+  std::vector<Group> groups;
   int64_t wg = 0, waves = 0;
-  int max_mu = 1;
   for (size_t i = 0; i < reqs.size(); ++i) {
     Req &r = *reqs[i];
+    const int mu_class = r.n_mu > 4 ? 8 : 4;
+    if (groups.empty() || groups.back().chunks != r.chunks || groups.back().max_mu != mu_class) {
+      groups.push_back(Group{i, 0, 0, r.chunks, mu_class});
+      wg = 0;
+    }
     unsigned char *blk = base + r.dev_off;
     if (hipMemcpyAsync(blk, pbase + r.pin_off, r.upload, hipMemcpyHostToDevice, s) != hipSuccess)
       return false;
     const ColumnsView cv = columns_view(blk + r.o_cols, r.n_sets, r.L, tv.S);
     if (launch_levels(tv, cv, blk + r.o_recs, nullptr, fp64, s) != hipSuccess) return false;
     if (launch_obs_build(fp64, r.plan.N, r.plan.first, r.plan.dnu, r.plan.R, r.n_bins,
-                         (const int64_t *)(blk + r.o_edges), (const int32_t *)(blk + r.o_h),
-                         r.plan.i0, r.plan.n_pts, blk + r.o_q, blk + r.o_z,
-                         (const int64_t *)(blk + r.o_kstart), (const int32_t *)(blk + r.o_mlo),
-                         (const int32_t *)(blk + r.o_mlen), blk + r.o_K, s) != hipSuccess)
+                         r.plan.nnz, (const int64_t *)(blk + r.o_edges),
+                         (const int32_t *)(blk + r.o_h), r.plan.i0, r.plan.n_pts, blk + r.o_q,
+                         blk + r.o_z, (const int64_t *)(blk + r.o_kstart),
+                         (const int32_t *)(blk + r.o_mlo), blk + r.o_K, s) != hipSuccess)
       return false;
     ColSeg &c = cs[i];
     std::memset(&c, 0, sizeof(c));
@@ -250,7 +267,9 @@ bool hr2_server::launch_step(StepSlot &sl, std::vector<Req *> &reqs) {
     c.chunks = r.chunks;
     c.tiles_per_set = (int32_t)((r.window.nu_count + per_wg - 1) / per_wg);
     wg += (int64_t)r.n_sets * c.tiles_per_set;
-    max_mu = std::max(max_mu, r.n_mu);
+    groups.back().count += 1;
+    groups.back().wgs = wg;
+    if (wg > 0x7fffffff) return false;
     ConvSeg &v = vs[i];
     std::memset(&v, 0, sizeof(v));
     v.item_begin = waves;
@@ -266,7 +285,6 @@ bool hr2_server::launch_step(StepSlot &sl, std::vector<Req *> &reqs) {
     v.n_bins = r.n_bins;
     waves += (int64_t)r.n_sets * r.n_bins;
   }
-  if (wg > 0x7fffffff) return false;
   const size_t bytes_c = cs.size() * sizeof(ColSeg), bytes_v = vs.size() * sizeof(ConvSeg);
   const size_t total = round256(bytes_c) + bytes_v;
   if (sl.desc.ensure(total) != HR2_OK) return false;
@@ -282,9 +300,10 @@ bool hr2_server::launch_step(StepSlot &sl, std::vector<Req *> &reqs) {
     return false;
   const ColSeg *dcs = (const ColSeg *)sl.desc.ptr;
   const ConvSeg *dvs = (const ConvSeg *)((unsigned char *)sl.desc.ptr + round256(bytes_c));
-  if (launch_column(tv, dcs, (int)cs.size(), wg, base, nullptr, base, max_mu, false, s) !=
-      hipSuccess)
-    return false;
+  for (const Group &gq : groups)
+    if (launch_column(tv, dcs + gq.first, (int)gq.count, gq.wgs, gq.chunks, base, nullptr, base,
+                      gq.max_mu, false, s) != hipSuccess)
+      return false;
   if (launch_convolve_bin(fp64, dvs, (int)vs.size(), waves, base, base, s) != hipSuccess)
     return false;
   for (Req *r : reqs)
@@ -501,7 +520,12 @@ extern "C" hr2_status hr2_serve_submit(hr2_server *srv, const hr2_request *q, ui
   r->n_sets = q->n_sets;
   r->L = q->cols[0].n_levels;
   r->n_mu = q->n_mu;
-  r->chunks = auto_chunks((int64_t)r->n_sets * ((r->window.nu_count + 63) / 64), r->L);
+  {
+    // chunking depends on the request alone, so its result does not depend on the mix
+    (void)hipSetDevice(srv->ctx->device);
+    r->chunks = auto_chunks(t->view, (int64_t)r->n_sets * ((r->window.nu_count + 63) / 64), r->L,
+                            r->n_mu, false);
+  }
   pack_columns(t, q->n_sets, q->cols, r->cols);
   layout_request(t, *r);
   if (r->bytes > srv->budget)
@@ -523,6 +547,35 @@ extern "C" hr2_status hr2_serve_submit(hr2_server *srv, const hr2_request *q, ui
   }
   srv->cv_work.notify_one();
   return HR2_OK;
+}
+
+extern "C" hr2_status hr2_serve_submit_packed(hr2_server *srv, hr2_window window, double R,
+                                              int n_bins, const double *edges, int n_sets,
+                                              int n_levels, const double *p, const double *T,
+                                              const double *x, const double *log_g,
+                                              const double *scale, int n_mu, uint64_t *ticket) {
+  if (!srv || !p || !T || !x || !log_g || !scale || !ticket)
+    return set_error(HR2_E_INVALID_ARG, "NULL argument");
+  if (n_sets < 1) return set_error(HR2_E_INVALID_ARG, "n_sets must be >= 1");
+  const int S = srv->tables->view.S;
+  std::vector<hr2_column> cols(n_sets);
+  for (int i = 0; i < n_sets; ++i) {
+    cols[i].n_levels = n_levels;
+    cols[i].p_bar = p + (size_t)i * n_levels;
+    cols[i].T_K = T + (size_t)i * n_levels;
+    cols[i].x = x + (size_t)i * S;
+    cols[i].log_g_cgs = log_g[i];
+    cols[i].scale = scale[i];
+  }
+  hr2_request q;
+  q.window = window;
+  q.resolving_power = R;
+  q.n_bins = n_bins;
+  q.bin_edges_cm = edges;
+  q.n_sets = n_sets;
+  q.cols = cols.data();
+  q.n_mu = n_mu;
+  return hr2_serve_submit(srv, &q, ticket);
 }
 
 static hr2_status poll_locked(hr2_server *srv, uint64_t ticket, void *bins, size_t cap,

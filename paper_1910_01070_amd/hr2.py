@@ -74,7 +74,7 @@ EXPORTS = [
     "hr2_obs_create", "hr2_obs_destroy", "hr2_obs_n_bins", "hr2_convolve_bin",
     "hr2_forward_batch", "hr2_forward_batch_dev", "hr2_serve_create", "hr2_serve_submit",
     "hr2_serve_poll", "hr2_serve_wait", "hr2_serve_destroy", "hr2_serve_debug_fail_next_step",
-    "hr2_serve_get_stats", "hr2_ctx_collect_timing",
+    "hr2_serve_get_stats", "hr2_ctx_collect_timing", "hr2_serve_submit_packed",
 ]
 
 _lib = None
@@ -114,6 +114,8 @@ def load() -> ctypes.CDLL:
         "hr2_serve_debug_fail_next_step": ([vp], c_int),
         "hr2_serve_get_stats": ([vp, POINTER(ServeStats)], c_int),
         "hr2_ctx_collect_timing": ([vp, POINTER(c_double), POINTER(c_int64)], c_int),
+        "hr2_serve_submit_packed": ([vp, WindowC, c_double, c_int, _DP, c_int, c_int, _DP, _DP,
+                                     _DP, _DP, _DP, c_int, POINTER(c_uint64)], c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(L, name)
@@ -337,6 +339,19 @@ class Server:
                        ctypes.cast(cc.arr, POINTER(ColumnC)), int(n_mu))
         t = c_uint64()
         _check(load().hr2_serve_submit(self.handle, ctypes.byref(req), ctypes.byref(t)))
+        return t.value
+
+    def submit_packed(self, window, resolving_power: float, edges_cm, p, T, x, log_g, scale,
+                      n_mu: int = 3) -> int:
+        """Columns as packed float64 arrays p, T [B][L], x [B][S], log_g, scale [B]."""
+        e, p, T, x = _f64(edges_cm), _f64(p), _f64(T), _f64(x)
+        lg, sc = _f64(log_g), _f64(scale)
+        B, L = p.shape
+        t = c_uint64()
+        _check(load().hr2_serve_submit_packed(self.handle, window_c(window),
+                                              float(resolving_power), len(e) - 1, _ptr(e), B, L,
+                                              _ptr(p), _ptr(T), _ptr(x), _ptr(lg), _ptr(sc),
+                                              int(n_mu), ctypes.byref(t)))
         return t.value
 
     def poll(self, ticket: int, n_elems: int, wait_s: Optional[float] = None):

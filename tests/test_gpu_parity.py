@@ -53,7 +53,7 @@ def test_c1_full_chain(ctx, dtype, tol):
     say(f"C1 {dtype}: tables + layout")
     T = hr2.Tables(ctx, tab, dtype)
     obs = hr2.Obs(ctx, T, spec.window, spec.resolving_power, spec.edges_cm)
-    for chunks in (0, 1, 2, 4):
+    for chunks in (0, 1, 2, 3, 4, 8):
         say(f"C1 {dtype}: forward, chunks={chunks}")
         bins, fplus = run_forward(ctx, T, obs, cols, 3, chunks)
         for s, col in enumerate(cols):
@@ -127,7 +127,7 @@ def test_multispecies_cia_windows(ctx, dtype, tol):
         hi = nu_first + 0.8 * (w.count - 1) * dnu
         edges = wl.snapped_edges(tab, w, wl.log_edges(lo, hi, 9))
         obs = hr2.Obs(ctx, T, w, 400.0, edges)
-        for chunks in (1, 2, 4):
+        for chunks in (1, 2, 3, 5, 8):
             say(f"window {w} L={L} {dtype} chunks={chunks}")
             bins, fplus = run_forward(ctx, T, obs, cols, 3, chunks)
             for s, col in enumerate(cols):
@@ -301,3 +301,46 @@ def test_c4_reduced_precision_errors(ctx, c2, dtype):
                                          1e-3 if dtype == "f16" else 1.0, None)
     say(f"  {dtype}: bins vs source {e_b_src:.2e}, F+ vs source {e_f_src:.2e}")
     T.close()
+
+
+def test_c3_graph_replay(ctx):
+    """C3 as a HIP graph: the 512-set batch captured once and replayed, with
+    eager work and synchronisations between replays, equals the eager launch."""
+    tab = tu.c1_table()
+    T = hr2.Tables(ctx, tab, "f32")
+    spec = wl.c1_obs(tab)
+    obs = hr2.Obs(ctx, T, spec.window, spec.resolving_power, spec.edges_cm)
+    cols = wl.c3_columns()
+    B = len(cols)
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+    p = dev(np.stack([c.p_bar for c in cols]))
+    Tk = dev(np.stack([c.T_K for c in cols]))
+    x = dev(np.stack([c.x for c in cols]))
+    lg = dev([c.log_g for c in cols])
+    sc = dev([c.scale for c in cols])
+    bins = torch.empty(B * obs.n_bins, dtype=torch.float32, device="cuda")
+    fplus = torch.empty(B * spec.window.count, dtype=torch.float32, device="cuda")
+    ctx.set_option(hr2.OPT_CHUNKS, 0)
+    say("C3 eager")
+    hr2.forward_batch_dev(ctx, T, obs, p, Tk, x, lg, sc, 3, bins, fplus)
+    torch.cuda.synchronize()
+    ref = bins.clone()
+    say("C3 capture")
+    g = torch.cuda.CUDAGraph()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(g, stream=s):
+            hr2.forward_batch_dev(ctx, T, obs, p, Tk, x, lg, sc, 3, bins, fplus, None, s)
+    torch.cuda.synchronize()
+    for rep in range(3):
+        bins.zero_()
+        junk = torch.randn(1 << 16, device="cuda").sum()
+        torch.cuda.synchronize()
+        say(f"C3 replay {rep}")
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(bins, ref), rep
+        del junk
+    del g
+    torch.cuda.synchronize()

@@ -362,8 +362,14 @@ def c5_request(rng, table: Table, t_arrival=0.0, max_sets=64, span_range=(20_000
     c = 5.0 / (R * 2.0 * np.sqrt(2.0 * np.log(2.0)))
     lo = nu_first * (1.0 + c) + 2 * stride * table.dnu_cm
     hi = nu_last / (1.0 + c) - 2 * stride * table.dnu_cm
+    if not hi > lo * (1.0 + 2.0 / R):
+        # window narrower than the profile's margins: bins span the window
+        lo = nu_first + 2 * stride * table.dnu_cm
+        hi = nu_last - 2 * stride * table.dnu_cm
     n_bins = max(1, int(np.floor(R * np.log(hi / lo))))
     edges = snapped_edges(table, w, log_edges(lo, hi, n_bins))
+    if len(edges) < 2:
+        edges = snapped_edges(table, w, [nu_first, nu_last])
     n_sets = int(rng.integers(1, max_sets + 1))
     cols = [c2_like_column(rng, layers + 1, table.n_species) for _ in range(n_sets)]
     return TraceRequest(t_arrival, ObsSpec(w, R, edges), cols)
@@ -379,4 +385,62 @@ def c5_trace(table: Table, rate_hz=2000.0, duration_s=10.0, seed=505, max_reques
         if t > duration_s or (max_requests is not None and len(out) >= max_requests):
             break
         out.append(c5_request(rng, table, t, max_sets=max_sets, span_range=span_range))
+    return out
+
+
+# Packed form of the serving trace (one array per column field), as a
+# sampler hands its live points over.
+
+
+@dataclass
+class PackedRequest:
+    t_arrival: float
+    obs: ObsSpec
+    p: np.ndarray       # [B][L]
+    T: np.ndarray       # [B][L]
+    x: np.ndarray       # [B][S]
+    log_g: np.ndarray   # [B]
+    scale: np.ndarray   # [B]
+    n_mu: int = 3
+
+    @property
+    def n_sets(self) -> int:
+        return int(self.p.shape[0])
+
+    @property
+    def layer_nu(self) -> int:
+        return (self.p.shape[1] - 1) * self.obs.window.count * self.n_sets
+
+
+def packed_c2_like_columns(rng, n_sets, n_levels, n_species):
+    p = levels(n_levels, 3.0, -6.0)
+    lp = np.log10(p)
+    T1 = rng.uniform(1500.0, 3000.0, n_sets)
+    b = rng.uniform(0.6, 0.95, (n_sets, 5))
+    knots_T = np.concatenate([T1[:, None], T1[:, None] * np.cumprod(b, axis=1)], axis=1)
+    knots_lp = np.linspace(lp[0], lp[-1], 6)
+    # element index and weight of each level (knots decrease in log p)
+    e = np.clip(np.searchsorted(-knots_lp, -lp, side="right") - 1, 0, 4)
+    w = (lp - knots_lp[e]) / (knots_lp[e + 1] - knots_lp[e])
+    T = knots_T[:, e] + w[None, :] * (knots_T[:, e + 1] - knots_T[:, e])
+    x = log_uniform(rng, 1e-8, 1e-2, (n_sets, n_species))
+    lg = rng.uniform(3.5, 6.0, n_sets)
+    sc = np.array([scale_factor(f) for f in rng.uniform(0.1, 5.0, n_sets)])
+    return np.tile(p, (n_sets, 1)), T, x, lg, sc
+
+
+def c5_trace_packed(table: Table, rate_hz=2000.0, duration_s=10.0, seed=505, max_sets=64,
+                    span_range=(20_000, 150_000)):
+    rng = np.random.default_rng(seed)
+    t = 0.0
+    out = []
+    while True:
+        t += rng.exponential(1.0 / rate_hz)
+        if t > duration_s:
+            break
+        r = c5_request(rng, table, t, max_sets=1, span_range=span_range)
+        n_sets = int(rng.integers(1, max_sets + 1))
+        L = r.cols[0].n_levels
+        p, T, x, lg, sc = packed_c2_like_columns(rng, n_sets, L, table.n_species)
+        out.append(PackedRequest(t, r.obs, p, T, x, lg, sc))
     return out
