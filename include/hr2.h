@@ -126,7 +126,8 @@ const char *hr2_last_error(void);
 typedef enum {
   HR2_OPT_CHUNKS = 0,      /* layer chunks per wavenumber tile: 0 = auto, 1, 2, 4 */
   HR2_OPT_NU_PER_LANE = 1, /* wavenumbers per lane: 0 = auto, 1 (only 1 is built) */
-  HR2_OPT_TIMING = 2       /* 1: bracket each forward-batch kernel with HIP events */
+  HR2_OPT_TIMING = 2       /* n > 0: bracket the kernels of every n-th forward-batch
+                              call with HIP events (0 = off)                        */
 } hr2_option;
 hr2_status hr2_ctx_set_option(hr2_ctx *ctx, hr2_option opt, int value);
 
@@ -327,9 +328,14 @@ void hr2_serve_destroy(hr2_server *srv);
  * normally.  Nothing is enqueued for the failed step. */
 hr2_status hr2_serve_debug_fail_next_step(hr2_server *srv);
 
-/* Counters of a server: steps launched, requests done, peak admitted bytes. */
+/* Test hook: while hold != 0 the scheduler admits requests but launches no
+ * step; hold = 0 releases it (the held requests then share steps). */
+hr2_status hr2_serve_debug_hold(hr2_server *srv, int hold);
+
+/* Counters of a server: steps launched, requests done / failed, most
+ * requests admitted at once, most requests in one step, peak admitted bytes. */
 typedef struct {
-  uint64_t steps, requests_done, requests_failed, max_inflight;
+  uint64_t steps, requests_done, requests_failed, max_inflight, max_step_requests;
   size_t peak_bytes;
 } hr2_serve_stats;
 hr2_status hr2_serve_get_stats(hr2_server *srv, hr2_serve_stats *out);

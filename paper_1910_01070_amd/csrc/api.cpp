@@ -246,7 +246,9 @@ extern "C" hr2_status hr2_ctx_set_option(hr2_ctx *ctx, hr2_option opt, int value
         return set_error(HR2_E_UNSUPPORTED, "only one wavenumber per lane is built");
       return HR2_OK;
     case HR2_OPT_TIMING:
-      ctx->timing = value != 0;
+      if (value < 0) return set_error(HR2_E_INVALID_ARG, "timing period must be >= 0");
+      ctx->timing_every = value;
+      ctx->timing_calls = 0;
       return HR2_OK;
   }
   return set_error(HR2_E_INVALID_ARG, "unknown option");
@@ -824,7 +826,7 @@ constexpr size_t kMaxTimedCalls = 65536;
 
 // Event slot k of the current timed call (nullptr when not timing).
 static hipEvent_t timing_event(hr2_ctx *ctx, int k) {
-  if (!ctx->timing || ctx->tev_used + 4 > 4 * kMaxTimedCalls) return nullptr;
+  if (ctx->timing_every <= 0 || ctx->tev_used + 4 > 4 * kMaxTimedCalls) return nullptr;
   const size_t at = ctx->tev_used + k;
   while (ctx->tev.size() <= at) {
     hipEvent_t ev;
@@ -849,8 +851,11 @@ hr2_status run_forward(hr2_ctx *ctx, const hr2_tables *t, const hr2_obs *o, cons
     if ((st = ctx->fplus.ensure(fp_bytes)) != HR2_OK) return st;
     fplus = ctx->fplus.ptr;
   }
-  hipEvent_t ev[4] = {timing_event(ctx, 0), timing_event(ctx, 1), timing_event(ctx, 2),
-                      timing_event(ctx, 3)};
+  const bool this_call = ctx->timing_every > 0 && !capturing(s) &&
+                         (ctx->timing_calls++ % ctx->timing_every) == 0;
+  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+  if (this_call)
+    for (int k = 0; k < 4; ++k) ev[k] = timing_event(ctx, k);
   const bool timed = ev[0] && ev[1] && ev[2] && ev[3];
   if (timed) HIP_TRY(hipEventRecord(ev[0], s));
   HIP_TRY(launch_levels(t->view, cv, ctx->recs.ptr, status, t->view.dtype == HR2_TABLE_F64, s));

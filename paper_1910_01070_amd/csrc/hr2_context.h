@@ -34,7 +34,8 @@ struct hr2_ctx {
   void *pinned = nullptr;
   size_t pinned_cap = 0;
   int opt_chunks = 0;
-  bool timing = false;
+  int timing_every = 0;            // time every n-th forward call (0 = off)
+  int64_t timing_calls = 0;
   std::vector<hipEvent_t> tev;     // 4 events per timed call
   size_t tev_used = 0;             // events recorded since the last collection
   hr2::DevBuf recs, fplus, cols, segs, convsegs;

@@ -135,7 +135,7 @@ __device__ __forceinline__ void locate_lds(const double *a, int n, double v, int
 }
 
 template <typename Real>
-__global__ __launch_bounds__(128) void k_levels(TableView tv, ColumnsView cv,
+__global__ __launch_bounds__(256) void k_levels(TableView tv, ColumnsView cv,
                                                 typename RecOf<Real>::type *recs, int *status) {
   using Rec = typename RecOf<Real>::type;
   __shared__ double s_T[kMaxAxis], s_lp[kMaxAxis];
@@ -187,15 +187,11 @@ __global__ __launch_bounds__(128) void k_levels(TableView tv, ColumnsView cv,
     const bool has_prev = l > 0;
     const CellW cp = has_prev ? s_cell[l - 1] : c;
     int mask = 0;
-    double wsl[4];
-    int rowsl[4];
     for (int k = 0; k < 4; ++k) {
       int row, rowp;
       double w, wp;
       slot_corner(c, k, tv.nP, row, w);
       slot_corner(cp, k, tv.nP, rowp, wp);
-      wsl[k] = w;
-      rowsl[k] = row;
       r.w[k] = (Real)w;
       r.rowb[k] = (uint32_t)row * row_bytes;
       const bool nz = w != 0.0;
@@ -217,40 +213,8 @@ __global__ __launch_bounds__(128) void k_levels(TableView tv, ColumnsView cv,
     }
     r.mask = mask;
 
-    // n_s 2^{interpolated row offset}: the kernel exponentiates only the
-    // stored (offset-free) part, keeping its exp2 argument small.  All
-    // offsets are fetched before any arithmetic so their latencies overlap.
-    double offv[kMaxSpecies][4];
-#pragma unroll
-    for (int q = 0; q < kMaxSpecies; ++q)
-#pragma unroll
-      for (int k = 0; k < 4; ++k)
-        offv[q][k] = q < S ? tv.off[q * rows_per_species + rowsl[k]] : 0.0;
-#pragma unroll
-    for (int q = 0; q < kMaxSpecies; ++q) {
-      double a = 0.0;
-      if (q < S) {
-        const double cq = wsl[0] * offv[q][0] + wsl[1] * offv[q][1] + wsl[2] * offv[q][2] +
-                          wsl[3] * offv[q][3];
-        a = x[q] * n * exp2(cq);
-      }
-      r.a_s[q] = (Real)a;
-    }
-    for (int q = 0; q < 2; ++q) {
-      double a = 0.0;
-      if (q < tv.n_cia) {
-        double cq = 0.0;
-        for (int k = 0; k < 2; ++k) {
-          int row;
-          double w;
-          cia_slot(c, k, row, w);
-          cq += w * tv.off_cia[q * tv.nT + row];
-        }
-        const double nh2 = h2 * n, nhe = he * n;
-        a = (q == 0 ? nh2 * nh2 : nh2 * nhe) * exp2(cq);
-      }
-      r.a_cia[q] = (Real)a;
-    }
+    for (int q = 0; q < kMaxSpecies; ++q) r.a_s[q] = (Real)0;
+    r.a_cia[0] = r.a_cia[1] = (Real)0;
     double hdz = 0.0;
     if (l + 1 < L) {
       const double tbar = 0.5 * (T[l] + T[l + 1]);
@@ -271,16 +235,49 @@ __global__ __launch_bounds__(128) void k_levels(TableView tv, ColumnsView cv,
     }
     recs[(int64_t)s * L + l] = r;
   }
+  __syncthreads();
+
+  // n_s 2^{interpolated row offset} (and the CIA pairs' n_a n_b 2^{...}),
+  // one (level, species) per thread: the kernel exponentiates only the
+  // stored offset-free part, keeping its exp2 argument small.
+  const int per_level = S + tv.n_cia;
+  for (int t = threadIdx.x; t < L * per_level; t += blockDim.x) {
+    const int l = t / per_level, q = t - l * per_level;
+    const CellW c = s_cell[l];
+    const double n = p[l] * 1.0e6 / (kKB * T[l]);
+    Rec *r = recs + (int64_t)s * L + l;
+    if (q < S) {
+      double off[4], w[4];
+      for (int k = 0; k < 4; ++k) {
+        int row;
+        slot_corner(c, k, tv.nP, row, w[k]);
+        off[k] = tv.off[q * rows_per_species + row];
+      }
+      const double cq = w[0] * off[0] + w[1] * off[1] + w[2] * off[2] + w[3] * off[3];
+      r->a_s[q] = (Real)(x[q] * n * exp2(cq));
+    } else {
+      const int qc = q - S;
+      double cq = 0.0;
+      for (int k = 0; k < 2; ++k) {
+        int row;
+        double w;
+        cia_slot(c, k, row, w);
+        cq += w * tv.off_cia[qc * tv.nT + row];
+      }
+      const double nh2 = h2 * n, nhe = he * n;
+      r->a_cia[qc] = (Real)((qc == 0 ? nh2 * nh2 : nh2 * nhe) * exp2(cq));
+    }
+  }
 }
 
 hipError_t launch_levels(const TableView &tv, const ColumnsView &cv, void *recs, int *status,
                          bool fp64, hipStream_t stream) {
   const dim3 grid((unsigned)cv.B);
   if (fp64)
-    hipLaunchKernelGGL(k_levels<double>, grid, dim3(128), 0, stream, tv, cv,
+    hipLaunchKernelGGL(k_levels<double>, grid, dim3(256), 0, stream, tv, cv,
                        (LevelRecD *)recs, status);
   else
-    hipLaunchKernelGGL(k_levels<float>, grid, dim3(128), 0, stream, tv, cv,
+    hipLaunchKernelGGL(k_levels<float>, grid, dim3(256), 0, stream, tv, cv,
                        (LevelRecF *)recs, status);
   return hipGetLastError();
 }
@@ -462,42 +459,48 @@ __global__ __launch_bounds__(512) void k_column(TableView tv, const ColSeg *__re
   }
   Real tau = (Real)0, chi_prev = (Real)0, S_prev = (Real)0, hdz_prev = (Real)0;
 
+  // Fetch the rows a level needs that the slots do not hold yet.  The rows
+  // of level l+1 are requested right after level l's opacity is formed (its
+  // slot values are no longer needed), so the loads are in flight while
+  // level l's Planck function and RT update run.
+  auto fetch = [&](const Rec &rr, int mask) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      if (mask & (1 << k)) {
+        const uint32_t off = rr.rowb[k] + kb;
+#pragma unroll
+        for (int q = 0; q < NS; ++q) {
+          if (q < S) {
+            const TT v = BIG ? buf_load<TT>(rs[BIG ? q : 0], off, 0)
+                             : buf_load<TT>(rs[0], off, (uint32_t)(q * sp_bytes));
+            if constexpr (kF64)
+              slot[q][k] = (Real)v;
+            else
+              slot[q][k] = to_float<TT>(v);
+          }
+        }
+      }
+    }
+    if (has_cia) {
+#pragma unroll
+      for (int k = 0; k < 2; ++k) {
+        if (mask & (16 << k)) {
+          const uint32_t off = rr.cia_rowb[k] + kbc;
+          cslot[0][k] = buf_load<Real>(rc, off, 0);
+          cslot[1][k] = buf_load<Real>(rc, off, (uint32_t)pair_bytes);
+        }
+      }
+    }
+  };
+
   if (l0 < nlay) {
+    if constexpr (!FROM_CHI) fetch(rec[l0], rec[l0].mask >> 8);
     for (int l = l0; l <= l1; ++l) {
       const Rec r = rec[l];
       Real chi;
       if constexpr (FROM_CHI) {
         chi = chi_in[d.chi_offset + (int64_t)l * nu_count + jj];
       } else {
-        const int mask = (l == l0) ? (r.mask >> 8) : r.mask;
-        // fetch the rows new to this level, slot by slot
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-          if (mask & (1 << k)) {
-            const uint32_t off = r.rowb[k] + kb;
-#pragma unroll
-            for (int q = 0; q < NS; ++q) {
-              if (q < S) {
-                const TT v = BIG ? buf_load<TT>(rs[BIG ? q : 0], off, 0)
-                                 : buf_load<TT>(rs[0], off, (uint32_t)(q * sp_bytes));
-                if constexpr (kF64)
-                  slot[q][k] = (Real)v;
-                else
-                  slot[q][k] = to_float<TT>(v);
-              }
-            }
-          }
-        }
-        if (has_cia) {
-#pragma unroll
-          for (int k = 0; k < 2; ++k) {
-            if (mask & (16 << k)) {
-              const uint32_t off = r.cia_rowb[k] + kbc;
-              cslot[0][k] = buf_load<Real>(rc, off, 0);
-              cslot[1][k] = buf_load<Real>(rc, off, (uint32_t)pair_bytes);
-            }
-          }
-        }
         chi = (Real)0;
 #pragma unroll
         for (int q = 0; q < NS; ++q) {
@@ -519,6 +522,13 @@ __global__ __launch_bounds__(512) void k_column(TableView tv, const ColSeg *__re
             else
               chi = fmaf(r.a_cia[q], fexp2(y), chi);
           }
+        }
+        if (l < l1) {
+          const Rec &rn = rec[l + 1];
+          // keeps this fetch here, after the opacity, instead of being merged
+          // with the chunk's first fetch at the top of the loop
+          asm volatile("" ::: "memory");
+          fetch(rn, rn.mask);
         }
       }
       Real S;

@@ -141,6 +141,7 @@ struct hr2_server {
   int n_admitted = 0;                // admitted and not finished
   bool stop = false;
   bool fail_next = false;
+  bool hold = false;
   hr2_serve_stats stats{};
   std::thread thr;
 
@@ -395,7 +396,7 @@ void hr2_server::run() {
     StepSlot *free_slot = nullptr;
     for (auto &sl : slots)
       if (!sl.busy) free_slot = &sl;
-    if (!stop && !admitted.empty() && free_slot) {
+    if (!stop && !hold && !admitted.empty() && free_slot) {
       std::vector<Req *> reqs;
       reqs.swap(admitted);
       StepSlot &sl = *free_slot;
@@ -403,6 +404,7 @@ void hr2_server::run() {
       sl.seq = ++step_seq;
       sl.reqs = reqs;
       ++stats.steps;
+      stats.max_step_requests = std::max<uint64_t>(stats.max_step_requests, reqs.size());
       if (fail_next) {
         // injected failure: nothing is enqueued for this step
         fail_next = false;
@@ -457,8 +459,10 @@ void hr2_server::run() {
       } else {
         cv_work.wait_for(lk, std::chrono::microseconds(50));
       }
+    } else if (hold && !stop) {
+      cv_work.wait_for(lk, std::chrono::milliseconds(1));
     } else if (!stop) {
-      cv_work.wait(lk, [this] { return stop || !pending.empty(); });
+      cv_work.wait(lk, [this] { return stop || hold || !pending.empty() || !admitted.empty(); });
     }
   }
 }
@@ -629,6 +633,16 @@ extern "C" hr2_status hr2_serve_debug_fail_next_step(hr2_server *srv) {
   if (!srv) return set_error(HR2_E_INVALID_ARG, "NULL server");
   std::lock_guard<std::mutex> lk(srv->mu);
   srv->fail_next = true;
+  return HR2_OK;
+}
+
+extern "C" hr2_status hr2_serve_debug_hold(hr2_server *srv, int hold) {
+  if (!srv) return set_error(HR2_E_INVALID_ARG, "NULL server");
+  {
+    std::lock_guard<std::mutex> lk(srv->mu);
+    srv->hold = hold != 0;
+  }
+  srv->cv_work.notify_all();
   return HR2_OK;
 }
 

@@ -65,7 +65,8 @@ class RequestInfo(ctypes.Structure):
 
 class ServeStats(ctypes.Structure):
     _fields_ = [("steps", c_uint64), ("requests_done", c_uint64), ("requests_failed", c_uint64),
-                ("max_inflight", c_uint64), ("peak_bytes", c_size_t)]
+                ("max_inflight", c_uint64), ("max_step_requests", c_uint64),
+                ("peak_bytes", c_size_t)]
 
 
 EXPORTS = [
@@ -75,6 +76,7 @@ EXPORTS = [
     "hr2_forward_batch", "hr2_forward_batch_dev", "hr2_serve_create", "hr2_serve_submit",
     "hr2_serve_poll", "hr2_serve_wait", "hr2_serve_destroy", "hr2_serve_debug_fail_next_step",
     "hr2_serve_get_stats", "hr2_ctx_collect_timing", "hr2_serve_submit_packed",
+    "hr2_serve_debug_hold",
 ]
 
 _lib = None
@@ -116,6 +118,7 @@ def load() -> ctypes.CDLL:
         "hr2_ctx_collect_timing": ([vp, POINTER(c_double), POINTER(c_int64)], c_int),
         "hr2_serve_submit_packed": ([vp, WindowC, c_double, c_int, _DP, c_int, c_int, _DP, _DP,
                                      _DP, _DP, _DP, c_int, POINTER(c_uint64)], c_int),
+        "hr2_serve_debug_hold": ([vp, c_int], c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(L, name)
@@ -366,6 +369,9 @@ class Server:
             st = L.hr2_serve_wait(self.handle, int(ticket), float(wait_s),
                                   out.ctypes.data_as(c_void_p), n_elems, ctypes.byref(info))
         return st, (out if st == OK else None), info
+
+    def hold(self, on: bool):
+        _check(load().hr2_serve_debug_hold(self.handle, 1 if on else 0))
 
     def fail_next_step(self):
         _check(load().hr2_serve_debug_fail_next_step(self.handle))

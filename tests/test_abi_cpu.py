@@ -77,7 +77,7 @@ def test_struct_layouts_match_the_header():
     assert ctypes.sizeof(hr2.WindowC) == 24
     assert ctypes.sizeof(hr2.ColumnC) == 48
     assert ctypes.sizeof(hr2.TablesDesc) == 104
-    assert ctypes.sizeof(hr2.ServeStats) == 40
+    assert ctypes.sizeof(hr2.ServeStats) == 48
 
 
 def test_serving_trace_inputs_are_valid():

@@ -53,19 +53,22 @@ def test_mix_equals_solo_equals_batch(env):
     srv = hr2.Server(ctx, T, 8 << 30, 64)
     say("solo")
     solo = [run_solo(srv, r) for r in reqs]
-    say("mix: submit all, then collect")
+    say("mix: submit all while the scheduler is held, release, then collect")
+    srv.hold(True)
     tickets = [srv.submit(r.obs.window, r.obs.resolving_power, r.obs.edges_cm, r.cols, r.n_mu)
                for r in reqs]
+    srv.hold(False)
     mixed = []
     for r, t in zip(reqs, tickets):
         st, out, info = srv.poll(t, n_out(r), wait_s=60.0)
         assert st == hr2.OK and info.state == hr2.REQ_DONE
         mixed.append(out)
     stats = srv.stats()
-    say(f"  steps {stats.steps}, done {stats.requests_done}, max in flight {stats.max_inflight}")
+    say(f"  steps {stats.steps}, done {stats.requests_done}, max in flight {stats.max_inflight}, "
+        f"max requests per step {stats.max_step_requests}")
     for a, b in zip(solo, mixed):
         assert np.array_equal(a, b)
-    assert stats.max_inflight > 1, "the burst should have been batched"
+    assert stats.max_step_requests == len(reqs), "the held burst should share one step"
     say("batch entry point")
     for r, a in zip(reqs[:4], solo[:4]):
         obs = hr2.Obs(ctx, T, r.obs.window, r.obs.resolving_power, r.obs.edges_cm)
