@@ -71,6 +71,8 @@ def lib():
         L.or_snap_edges.restype = _I
         L.or_bin.argtypes = [_D, _D, _DP, _I, _I64P, _D, _DP]
         L.or_bin.restype = None
+        L.or_lnl.argtypes = [_I, _DP, _DP, _DP, _I, _D]
+        L.or_lnl.restype = _D
         _handle = L
     return _handle
 
@@ -185,6 +187,13 @@ def bin_spectrum(Fd, edge_idx, nu_first, dnu_eff, scale):
     out = np.empty(nb)
     lib().or_bin(float(nu_first), float(dnu_eff), _p(Fd), nb, _p(edge_idx), float(scale), _p(out))
     return out
+
+
+def log_likelihood(model, D, sigma, log10_eps=None):
+    """Eq. 19, or Eq. 22-23 with s^2 = sigma^2 + 10^eps when log10_eps is given."""
+    m, D, sg = _f64(model), _f64(D), _f64(sigma)
+    return lib().or_lnl(len(m), _p(m), _p(D), _p(sg), 0 if log10_eps is None else 1,
+                        0.0 if log10_eps is None else float(log10_eps))
 
 
 # ------------------------------------------------------------- composition

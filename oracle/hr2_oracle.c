@@ -323,3 +323,22 @@ void or_bin(double nu_first, double dnu_eff, const double *Fd, int n_bins,
     bins[j] = scale * s / (nu_b - nu_a);
   }
 }
+
+/* ------------------------------------------------------------------------
+ * Gaussian log-likelihood of binned data (Sect. 3.1, Eq. 19):
+ *   ln L = sum_j ( -(D_j - m_j)^2 / (2 s_j^2) - 1/2 ln(2 pi s_j^2) ),
+ * with s_j^2 = sigma_j^2, or with error inflation (Sect. 3.3, Eq. 22-23)
+ * s_j^2 = sigma_j^2 + 10^eps when with_eps != 0.  Reading of Eq. 23: its
+ * second term belongs inside the sum, as in Eq. 19.
+ * ---------------------------------------------------------------------- */
+double or_lnl(int n_bins, const double *model, const double *D, const double *sigma,
+              int with_eps, double log10_eps) {
+  double lnl = 0.0;
+  for (int j = 0; j < n_bins; ++j) {
+    double s2 = sigma[j] * sigma[j];
+    if (with_eps) s2 += pow(10.0, log10_eps);
+    const double r = D[j] - model[j];
+    lnl += -r * r / (2.0 * s2) - 0.5 * log(2.0 * OR_PI * s2);
+  }
+  return lnl;
+}

@@ -480,3 +480,24 @@ def test_hydrostatic_thickness_exact_for_t_linear_in_log_p():
     integral = T0 * s + (T1 - T0) * s * s / (2 * (lnp[0] - lnp[-1]))
     want = KB * integral / (st["mubar"] * AMU * g)
     np.testing.assert_allclose(height, want, rtol=AMU_RTOL)
+
+
+# ------------------------------------------------------------ Eq. 19, 22-23
+
+
+def test_likelihood_matches_the_gaussian_density():
+    """Eq. 19 is the log of a product of normal densities: it equals the sum of
+    scipy's norm.logpdf; with error inflation (Eq. 22-23) the scale becomes
+    sqrt(sigma^2 + 10^eps)."""
+    from scipy import stats
+    rng = np.random.default_rng(31)
+    m = rng.uniform(1.0, 5.0, 57)
+    sg = rng.uniform(0.05, 0.5, 57)
+    D = m + sg * rng.normal(size=57)
+    want = np.sum(stats.norm.logpdf(D, loc=m, scale=sg))
+    assert abs(oracle.log_likelihood(m, D, sg) - want) < 1e-12 * abs(want)
+    eps = -1.7
+    want = np.sum(stats.norm.logpdf(D, loc=m, scale=np.sqrt(sg ** 2 + 10.0 ** eps)))
+    assert abs(oracle.log_likelihood(m, D, sg, eps) - want) < 1e-12 * abs(want)
+    # a perfect model leaves only the normalisation
+    assert abs(oracle.log_likelihood(m, m, sg) + 0.5 * np.sum(np.log(2 * np.pi * sg ** 2))) < 1e-12
