@@ -103,11 +103,12 @@ def gauss_legendre01(n):
 
 
 def planck(nu_cm, T_K):
-    nu_cm, T_K = np.broadcast_arrays(_f64(nu_cm), _f64(T_K))
-    nu_cm, T_K = _f64(nu_cm), _f64(T_K)
-    out = np.empty(nu_cm.shape)
-    lib().or_planck_n(nu_cm.size, _p(nu_cm), _p(T_K), _p(out))
-    return out
+    shape = np.broadcast_shapes(np.shape(nu_cm), np.shape(T_K))
+    nu = _f64(np.broadcast_to(np.asarray(nu_cm, dtype=np.float64), shape).ravel())
+    T = _f64(np.broadcast_to(np.asarray(T_K, dtype=np.float64), shape).ravel())
+    out = np.empty(nu.size)
+    lib().or_planck_n(nu.size, _p(nu), _p(T), _p(out))
+    return out.reshape(shape)
 
 
 def column_state(table, col):

@@ -444,3 +444,78 @@ def c5_trace_packed(table: Table, rate_hz=2000.0, duration_s=10.0, seed=505, max
         p, T, x, lg, sc = packed_c2_like_columns(rng, n_sets, L, table.n_species)
         out.append(PackedRequest(t, r.obs, p, T, x, lg, sc))
     return out
+
+
+# ------------------------------------------------- observed data for ln L
+
+
+def noisy_data(model_bins, seed, noise_frac=0.2):
+    """Synthetic observation of a model spectrum: one error bar for every bin,
+    sigma = noise_frac x the median |model|, and D = model + sigma x N(0, 1)
+    (the recipe of the paper's synthetic retrieval tests: 20% of the median
+    flux).  Returns (D, sigma)."""
+    m = np.asarray(model_bins, dtype=np.float64)
+    rng = np.random.default_rng(seed)
+    sigma = np.full(m.shape, noise_frac * float(np.median(np.abs(m))))
+    return m + sigma * rng.standard_normal(m.shape), sigma
+
+
+# ------------------------------------------ parameter vectors (Theta -> column)
+
+
+@dataclass
+class ParamLayout:
+    """How a parameter vector maps onto a column (mirrors hr2_param_layout):
+    n_elements elements of order `order` for the temperature, n_levels levels
+    from log10_p_bottom to log10_p_top, the radius of Eq. 9, and for every
+    table species the free ratio it copies (species_src, -1 = absent) times
+    species_factor."""
+    n_elements: int
+    order: int
+    n_levels: int
+    log10_p_bottom: float
+    log10_p_top: float
+    radius_cm: float
+    n_free: int
+    with_eps: bool
+    species_src: np.ndarray      # int32 [n_species]
+    species_factor: np.ndarray   # float64 [n_species]
+
+
+# solar Na/K number ratio from the photospheric abundances log eps(Na) = 6.24
+# and log eps(K) = 5.03 (Asplund et al. 2009)
+SOLAR_NA_K = 10.0 ** (6.24 - 5.03)
+
+
+def c2_param_layout(n_elements=3, order=2, with_eps=True):
+    """The paper's brown-dwarf set-up on the C2 table: seven free mixing
+    ratios (H2O, CH4, CO, CO2, NH3, H2S, K; the eighth table species stands
+    for Na, a fixed multiple of K), 101 levels from 1e3 to 1e-6 bar."""
+    src = np.array([0, 1, 2, 3, 4, 5, 6, 6], dtype=np.int32)
+    fac = np.array([1, 1, 1, 1, 1, 1, 1, SOLAR_NA_K], dtype=np.float64)
+    return ParamLayout(n_elements, order, 101, 3.0, -6.0, R_JUP_CM, 7, with_eps, src, fac)
+
+
+def c1_param_layout(n_elements=2, order=2, with_eps=False, n_levels=20):
+    """One absorber (the C1 table), levels as the C1 columns."""
+    return ParamLayout(n_elements, order, n_levels, 2.0, -4.0, R_JUP_CM, 1, with_eps,
+                       np.array([0], dtype=np.int32), np.array([1.0]))
+
+
+def draw_theta(layout: ParamLayout, n_sets, seed, log10_eps_range=(-30.0, -28.0)):
+    """Parameter vectors [log g, f, d_pc, T1, b_1..b_{N_T-1}, x_free..., (log10 eps)]
+    from boxes inside the paper's priors (b kept in 0.6-0.95 and x in
+    1e-8-1e-2 so that the temperatures stay on typical table grids and the
+    filler gas stays positive)."""
+    rng = np.random.default_rng(seed)
+    NT = layout.n_elements * layout.order + 1
+    rows = []
+    for _ in range(n_sets):
+        th = [rng.uniform(3.5, 6.0), rng.uniform(0.1, 5.0), rng.normal(10.0, 0.05),
+              rng.uniform(1000.0, 3000.0)]
+        th += list(rng.uniform(0.6, 0.95, NT - 1))
+        th += list(log_uniform(rng, 1e-8, 1e-2, layout.n_free))
+        if layout.with_eps:
+            th.append(rng.uniform(*log10_eps_range))
+        rows.append(th)
+    return np.array(rows, dtype=np.float64)
