@@ -104,13 +104,16 @@ enum {
   HR2_MAX_SPECIES = 12,
   HR2_MAX_CIA = 2,
   HR2_MAX_LEVELS = 1024,
-  HR2_MAX_MU = 8
+  HR2_MAX_MU = 8,
+  HR2_MAX_ORDER = 8,          /* finite-element order q */
+  HR2_MAX_TNODES = 128        /* temperature nodes K_e q + 1 */
 };
 
 typedef struct hr2_ctx hr2_ctx;
 typedef struct hr2_tables hr2_tables;
 typedef struct hr2_obs hr2_obs;
 typedef struct hr2_server hr2_server;
+typedef struct hr2_params hr2_params;
 
 /* Create a context on HIP device `hip_device`.  Allocates the angular
  * quadrature constants and grow-only scratch.  Errors: HR2_E_INVALID_ARG
@@ -183,7 +186,15 @@ void hr2_tables_destroy(hr2_tables *tables);
  *   T_K[L]     > 0; table lookups clamp to the T axis, Planck uses T as given
  *   x[n_species]  isoprofile mixing ratios, >= 0, sum < 1 (Sect. 5.2)
  *   log_g_cgs  log10 of surface gravity in cm s^-2
- *   scale      f (R/d)^2 (Eq. 9), finite */
+ *   scale      f (R/d)^2 (Eq. 9), finite
+ *   tau_cloud, p_cloud_top_bar, cloud_bottom_frac
+ *              optional gray cloud layer (App. B): total optical depth
+ *              tau_cloud >= 0 (0 = clear sky, the other two ignored),
+ *              independent of wavenumber, between p_cloud_top_bar > 0 and
+ *              p_cloud_top_bar * cloud_bottom_frac (cloud_bottom_frac > 1).
+ *              Reading (the appendix is silent): the optical depth is spread
+ *              uniformly in ln p over that range and each layer adds its
+ *              share to its optical depth.  Zero-initialise for clear sky. */
 typedef struct {
   int n_levels;
   const double *p_bar;
@@ -191,6 +202,9 @@ typedef struct {
   const double *x;
   double log_g_cgs;
   double scale;
+  double tau_cloud;
+  double p_cloud_top_bar;
+  double cloud_bottom_frac;
 } hr2_column;
 
 /* Wavenumber window: table points nu_begin + j * nu_stride, j < nu_count.
@@ -245,7 +259,9 @@ hr2_status hr2_forward_batch(hr2_ctx *ctx, const hr2_tables *tables, const hr2_o
 
 /* Same, with the columns already resident in device memory (FP64):
  *   p_dev[n_sets][n_levels], T_dev[n_sets][n_levels],
- *   x_dev[n_sets][n_species], log_g_dev[n_sets], scale_dev[n_sets].
+ *   x_dev[n_sets][n_species], log_g_dev[n_sets], scale_dev[n_sets],
+ *   cloud_dev: NULL (clear sky) or [n_sets][3] = (tau_cloud,
+ *   p_cloud_top_bar, cloud_bottom_frac) as in hr2_column.
  * Nothing is validated on the host (that would need a device read); the
  * level kernel checks every set and writes its status to set_status_dev
  * (device int[n_sets], may be NULL): 0 = valid, HR2_E_INVALID_ARG otherwise.
@@ -256,9 +272,118 @@ hr2_status hr2_forward_batch(hr2_ctx *ctx, const hr2_tables *tables, const hr2_o
 hr2_status hr2_forward_batch_dev(hr2_ctx *ctx, const hr2_tables *tables, const hr2_obs *obs,
                                  int n_sets, int n_levels, const double *p_dev,
                                  const double *T_dev, const double *x_dev,
-                                 const double *log_g_dev, const double *scale_dev, int n_mu,
-                                 void *bins_dev, void *fplus_dev, int *set_status_dev,
+                                 const double *log_g_dev, const double *scale_dev,
+                                 const double *cloud_dev, int n_mu, void *bins_dev,
+                                 void *fplus_dev, int *set_status_dev, void *stream);
+
+/* ---- likelihood: the forward model fused with ln L (Sect. 3.1, Eq. 19;
+ * error inflation of Sect. 3.3, Eq. 22-23) ----
+ * ln L = sum_j [ -(D_j - m_j)^2 / (2 s_j^2) - 1/2 ln(2 pi s_j^2) ], where m_j
+ * is the model's bin j (exactly what hr2_forward_batch returns, in
+ * hr2_real) and s_j^2 = sigma_j^2, or sigma_j^2 + 10^eps with inflation.
+ * Reading of Eq. 23: its normalisation term belongs inside the sum, as in
+ * Eq. 19.  The per-bin terms are formed in FP64 and summed per set in a
+ * fixed order, so repeated calls give identical results.
+ *
+ * hr2_obs_set_data attaches observed data to a layout: D[n_bins] (finite)
+ * and sigma[n_bins] (finite, > 0), host FP64, copied (the caller keeps its
+ * arrays).  It may be called again to replace the data; it waits for the
+ * device first.  Errors: HR2_E_INVALID_ARG (NULL, non-finite, sigma <= 0),
+ * HR2_E_NO_MEMORY. */
+hr2_status hr2_obs_set_data(hr2_obs *obs, const double *D, const double *sigma);
+
+/* ln L of n_sets host columns (as hr2_forward_batch): lnl_dev is device
+ * double[n_sets].  log10_eps: NULL (Eq. 19) or host double[n_sets], the
+ * exponent of Eq. 22 per set.  bins_dev: NULL, or device
+ * hr2_real[n_sets][n_bins] that also receives the model bins.  Enqueued on
+ * stream; only n_sets doubles need to come back to the host.  Errors: as
+ * hr2_forward_batch, plus HR2_E_INVALID_ARG when the layout has no data or
+ * a log10_eps is not finite. */
+hr2_status hr2_loglike_batch(hr2_ctx *ctx, const hr2_tables *tables, const hr2_obs *obs,
+                             int n_sets, const hr2_column *cols, int n_mu,
+                             const double *log10_eps, double *lnl_dev, void *bins_dev,
+                             void *stream);
+
+/* Same with device-resident FP64 columns and optional clouds (as
+ * hr2_forward_batch_dev); log10_eps_dev: NULL or device double[n_sets].  An invalid set's ln L is
+ * NaN and its set_status_dev entry HR2_E_INVALID_ARG.  Capturable into a HIP
+ * graph under the same condition as hr2_forward_batch_dev. */
+hr2_status hr2_loglike_batch_dev(hr2_ctx *ctx, const hr2_tables *tables, const hr2_obs *obs,
+                                 int n_sets, int n_levels, const double *p_dev,
+                                 const double *T_dev, const double *x_dev,
+                                 const double *log_g_dev, const double *scale_dev,
+                                 const double *cloud_dev, const double *log10_eps_dev, int n_mu,
+                                 double *lnl_dev, void *bins_dev, int *set_status_dev,
                                  void *stream);
+
+/* ---- parameter vectors: Theta -> column on the device ----
+ * Temperature (Sect. 2.5.1, Eq. 12-16): n_elements elements of order q
+ * split [log10_p_top, log10_p_bottom] into equal parts; on each the
+ * temperature is the Lagrange interpolant (Eq. 13) through q + 1 nodes at
+ * the Gauss-Lobatto points of the reference element [0, 1]; elements share
+ * boundary nodes, so there are N_T = n_elements q + 1 node temperatures
+ * (Eq. 16).  The bottom node's temperature T1 is a parameter; node n (from
+ * the bottom) is b_n times node n - 1.  Readings: element 1 and local
+ * coordinate 0 are at the bottom; a level on an element boundary takes the
+ * element above (the same value, the profile being continuous).
+ * Levels: n_levels, equidistant in log p, level 0 at log10_p_bottom.
+ * Free chemistry (Sect. 5.2): height-independent mixing ratios; table
+ * species s gets species_factor[s] * xfree[species_src[s]], or 0 when
+ * species_src[s] < 0 (sodium from potassium with the solar ratio, say).
+ * Scale (Eq. 9): f (radius_cm / (d_pc * 3.0856775814913673e18 cm))^2.
+ *
+ * One parameter vector (FP64, row of theta_dev[n_sets][n_theta]):
+ *   log g (cgs), f, d (parsec), T1 (K), b_1 .. b_{N_T - 1},
+ *   xfree[0 .. n_free - 1], then tau_cloud, p_cloud_top_bar,
+ *   cloud_bottom_frac (as in hr2_column) when with_cloud, then log10 eps
+ *   (Eq. 22) when with_eps.
+ * An invalid vector (T1, b, f or d not > 0, x < 0, a cloud outside the
+ * hr2_column ranges, anything not finite) yields NaN temperatures, which the forward model reports as an invalid
+ * set (status HR2_E_INVALID_ARG, NaN bins and ln L). */
+typedef struct {
+  int n_elements;                 /* K_e >= 1 */
+  int order;                      /* q in [1, HR2_MAX_ORDER]; K_e q + 1 <= HR2_MAX_TNODES */
+  int n_levels;                   /* [2, HR2_MAX_LEVELS] */
+  double log10_p_bottom;          /* bar */
+  double log10_p_top;             /* bar, < log10_p_bottom */
+  double radius_cm;               /* R_* of Eq. 9, > 0 */
+  int n_free;                     /* free mixing ratios in theta, [0, HR2_MAX_SPECIES] */
+  int with_cloud;                 /* 0 or 1: theta carries a gray cloud (App. B) */
+  int with_eps;                   /* 0 or 1 */
+  const int *species_src;         /* [n_species of the tables], each in [-1, n_free) */
+  const double *species_factor;   /* [n_species], finite, >= 0 */
+} hr2_param_layout;
+
+/* Validate and keep a layout for these tables (copied; host arrays may be
+ * freed afterwards).  Errors: HR2_E_INVALID_ARG (NULL, out-of-range field). */
+hr2_status hr2_params_create(hr2_ctx *ctx, const hr2_tables *tables,
+                             const hr2_param_layout *layout, hr2_params **out);
+void hr2_params_destroy(hr2_params *params);
+/* Parameters per set: 3 + N_T + n_free + 3 with_cloud + with_eps (0 for NULL). */
+int hr2_params_n_theta(const hr2_params *params);
+
+/* Unpack n_sets device parameter vectors into device FP64 columns in the
+ * layout hr2_forward_batch_dev reads: p_dev, T_dev [n_sets][n_levels],
+ * x_dev [n_sets][n_species], log_g_dev, scale_dev [n_sets]; cloud_dev
+ * [n_sets][3] or NULL (zeros without with_cloud); log10_eps_dev [n_sets] or
+ * NULL (0 without with_eps).  Enqueued on stream. */
+hr2_status hr2_params_unpack_dev(hr2_ctx *ctx, const hr2_params *params, int n_sets,
+                                 const double *theta_dev, double *p_dev, double *T_dev,
+                                 double *x_dev, double *log_g_dev, double *scale_dev,
+                                 double *cloud_dev, double *log10_eps_dev, void *stream);
+
+/* Parameter vectors straight to spectra and/or ln L: unpack (above) into
+ * context scratch, then the forward model, then (lnl_dev non-NULL) the
+ * likelihood of Eq. 19, or Eq. 22-23 with the vector's own eps when the
+ * layout has with_eps.  bins_dev: NULL or device hr2_real[n_sets][n_bins];
+ * lnl_dev: NULL or device double[n_sets]; at least one of the two.
+ * set_status_dev as in hr2_forward_batch_dev.  Capturable into a HIP graph
+ * after one eager call with the same sizes.  Errors: as
+ * hr2_loglike_batch_dev; HR2_E_INVALID_ARG when the layout's tables differ. */
+hr2_status hr2_forward_params_dev(hr2_ctx *ctx, const hr2_tables *tables, const hr2_obs *obs,
+                                  const hr2_params *params, int n_sets,
+                                  const double *theta_dev, int n_mu, void *bins_dev,
+                                  double *lnl_dev, int *set_status_dev, void *stream);
 
 /* ---- serving: continuous batching of uneven forward-model requests ----
  * A scheduler thread owns one stream.  Requests (each n_sets columns sharing

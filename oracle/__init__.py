@@ -8,7 +8,8 @@ Thin ctypes wrapper around ``hr2_oracle.c`` plus the composition of its
 stages (opacity -> RT -> convolution -> binning) for a column.  Inputs are
 duck-typed: a table needs ``T_K, log10_p_bar, nu0_cm, dnu_cm, n_nu,
 log10_sigma, molar_mass, log10_k_cia, he_h2_ratio``; a column ``p_bar, T_K,
-x, log_g, scale``; a window ``begin, count, stride``.
+x, log_g, scale`` and optionally ``cloud`` = (tau_c, p_top_bar, bottom_frac)
+or None (App. B); a window ``begin, count, stride``.
 """
 from __future__ import annotations
 
@@ -43,7 +44,8 @@ _handle = None
 def lib():
     global _handle
     if _handle is None:
-        if not os.path.exists(LIB_PATH):
+        src = os.path.join(HERE, "hr2_oracle.c")
+        if not os.path.exists(LIB_PATH) or os.path.getmtime(src) > os.path.getmtime(LIB_PATH):
             build(force=True)
         L = ctypes.CDLL(LIB_PATH)
         L.or_gauss_legendre01.argtypes = [_I, _DP, _DP]
@@ -63,6 +65,10 @@ def lib():
         L.or_sc_flux.restype = _D
         L.or_rt_emission.argtypes = [_I, _I64, _DP, _DP, _DP, _DP, _I, _DP]
         L.or_rt_emission.restype = None
+        L.or_rt_emission_x.argtypes = [_I, _I64, _DP, _DP, _DP, _DP, _I, _DP, _DP]
+        L.or_rt_emission_x.restype = None
+        L.or_cloud_dtau.argtypes = [_I, _DP, _D, _D, _D, _DP]
+        L.or_cloud_dtau.restype = None
         for name in ("or_convolve", "or_convolve_banded"):
             fn = getattr(L, name)
             fn.argtypes = [_I64, _D, _D, _DP, _D, _I64, _I64P, _DP]
@@ -155,12 +161,25 @@ def sc_flux(dtau, S, n_mu):
     return lib().or_sc_flux(len(S), _p(dtau), _p(S), int(n_mu))
 
 
-def rt_emission(chi, dz, T_K, nu, n_mu):
+def cloud_dtau(p_bar, cloud):
+    """Per-layer optical depth of a gray cloud (tau_c, p_top_bar, bottom_frac), App. B."""
+    p = _f64(p_bar)
+    out = np.empty(max(len(p) - 1, 1))
+    tau_c, p_top, frac = cloud
+    lib().or_cloud_dtau(len(p), _p(p), float(tau_c), float(p_top), float(frac), _p(out))
+    return out[:len(p) - 1]
+
+
+def rt_emission(chi, dz, T_K, nu, n_mu, dtau_extra=None):
     chi = _f64(chi)
     L, n = chi.shape
     out = np.empty(n)
-    lib().or_rt_emission(L, n, _p(chi), _p(_f64(dz)), _p(_f64(T_K)), _p(_f64(nu)), int(n_mu),
-                         _p(out))
+    if dtau_extra is None:
+        lib().or_rt_emission(L, n, _p(chi), _p(_f64(dz)), _p(_f64(T_K)), _p(_f64(nu)), int(n_mu),
+                             _p(out))
+    else:
+        lib().or_rt_emission_x(L, n, _p(chi), _p(_f64(dz)), _p(_f64(T_K)), _p(_f64(nu)),
+                               int(n_mu), _p(_f64(dtau_extra)), _p(out))
     return out
 
 
@@ -213,7 +232,9 @@ def fplus(table, col, window, n_mu, sub=None):
     chi = opacity(table, col, tab_idx)
     st = column_state(table, col)
     nu = table.nu0_cm + tab_idx * table.dnu_cm
-    return rt_emission(chi, st["dz"], col.T_K, nu, n_mu)
+    cloud = getattr(col, "cloud", None)
+    extra = None if cloud is None else cloud_dtau(col.p_bar, cloud)
+    return rt_emission(chi, st["dz"], col.T_K, nu, n_mu, extra)
 
 
 def forward(table, col, window, R, edges_cm, n_mu):

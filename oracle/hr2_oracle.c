@@ -217,25 +217,52 @@ double or_sc_flux(int L, const double *dtau, const double *S, int n_mu) {
 }
 
 /* ------------------------------------------------------------------------
- * Stage 2 (Eq. 2-8) for one column: dtau_l = (chi_l + chi_{l+1})/2 dz_l,
+ * Gray cloud layer (App. B): total optical depth tau_c, wavenumber
+ * independent, between the cloud top p_top and the cloud bottom
+ * p_top * bottom_frac (bottom_frac > 1).  The appendix does not say how the
+ * optical depth is spread; reading: uniformly in ln p, so layer l (levels l
+ * and l+1, p_l > p_{l+1}) receives tau_c times the share of
+ * [ln p_top, ln(p_top bottom_frac)] that [ln p_{l+1}, ln p_l] covers.
+ * ---------------------------------------------------------------------- */
+void or_cloud_dtau(int L, const double *p_bar, double tau_c, double p_top_bar,
+                   double bottom_frac, double *dtau_c) {
+  const double a = log(p_top_bar), b = log(p_top_bar * bottom_frac);
+  for (int l = 0; l + 1 < L; ++l) {
+    const double lo = log(p_bar[l + 1]), hi = log(p_bar[l]);
+    double ov = (hi < b ? hi : b) - (lo > a ? lo : a);
+    if (ov < 0.0) ov = 0.0;
+    dtau_c[l] = tau_c * ov / (b - a);
+  }
+}
+
+/* ------------------------------------------------------------------------
+ * Stage 2 (Eq. 2-8) for one column: dtau_l = (chi_l + chi_{l+1})/2 dz_l
+ * (+ dtau_extra[l], a gray cloud's share, when dtau_extra is not NULL),
  * S_l = B(nu, T_l), F+ per wavenumber.  chi[L][n], dz[L-1], T[L], nu[n].
  * ---------------------------------------------------------------------- */
-void or_rt_emission(int L, int64_t n, const double *chi, const double *dz, const double *T_K,
-                    const double *nu, int n_mu, double *fplus) {
+void or_rt_emission_x(int L, int64_t n, const double *chi, const double *dz, const double *T_K,
+                      const double *nu, int n_mu, const double *dtau_extra, double *fplus) {
 #pragma omp parallel
   {
     double *dtau = (double *)malloc(sizeof(double) * (L > 1 ? L - 1 : 1));
     double *S = (double *)malloc(sizeof(double) * L);
 #pragma omp for schedule(static)
     for (int64_t j = 0; j < n; ++j) {
-      for (int l = 0; l + 1 < L; ++l)
+      for (int l = 0; l + 1 < L; ++l) {
         dtau[l] = 0.5 * (chi[(size_t)l * n + j] + chi[(size_t)(l + 1) * n + j]) * dz[l];
+        if (dtau_extra) dtau[l] += dtau_extra[l];
+      }
       for (int l = 0; l < L; ++l) S[l] = or_planck(nu[j], T_K[l]);
       fplus[j] = or_sc_flux(L, dtau, S, n_mu);
     }
     free(dtau);
     free(S);
   }
+}
+
+void or_rt_emission(int L, int64_t n, const double *chi, const double *dz, const double *T_K,
+                    const double *nu, int n_mu, double *fplus) {
+  or_rt_emission_x(L, n, chi, dz, T_K, nu, n_mu, NULL, fplus);
 }
 
 /* ------------------------------------------------------------------------

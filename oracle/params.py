@@ -16,6 +16,9 @@ potassium); H2 and He fill the rest, which the forward model already does.
 
 Radius-distance factor (Eq. 9): scale = f (R_* / d)^2.
 
+Gray cloud (App. B), optional: optical depth, top pressure and the bottom as
+a multiple of the top, passed on with the column.
+
 Readings taken where the paper is silent:
 * elements and levels span the same log-pressure range, element 1 at the
   bottom, local coordinate 0 at each element's bottom boundary;
@@ -82,14 +85,21 @@ def level_pressures(n_levels, log10_p_bottom, log10_p_top):
     return 10.0 ** np.linspace(log10_p_bottom, log10_p_top, n_levels)
 
 
+def _with_cloud(layout) -> bool:
+    return bool(getattr(layout, "with_cloud", False))
+
+
 def n_theta(layout) -> int:
     """Parameters per set: log g, f, d, T1, the N_T - 1 b's, the free mixing
-    ratios, and log10 eps when the layout carries it."""
-    return 3 + layout.n_elements * layout.order + 1 + layout.n_free + int(layout.with_eps)
+    ratios, the three gray-cloud parameters (App. B) when the layout has a
+    cloud, and log10 eps when it carries one."""
+    return (3 + layout.n_elements * layout.order + 1 + layout.n_free + 3 * _with_cloud(layout)
+            + int(layout.with_eps))
 
 
 def unpack(layout, theta):
-    """One parameter vector -> (p_bar, T_K, x, log_g, scale, log10_eps or None)."""
+    """One parameter vector -> (p_bar, T_K, x, log_g, scale, cloud or None,
+    log10_eps or None); cloud = (tau_c, p_top_bar, bottom_frac)."""
     th = np.asarray(theta, dtype=np.float64)
     if len(th) != n_theta(layout):
         raise ValueError("wrong parameter count")
@@ -97,7 +107,10 @@ def unpack(layout, theta):
     NT = layout.n_elements * layout.order + 1
     b = th[4:3 + NT]
     xf = th[3 + NT:3 + NT + layout.n_free]
-    eps = float(th[3 + NT + layout.n_free]) if layout.with_eps else None
+    k = 3 + NT + layout.n_free
+    cloud = tuple(float(v) for v in th[k:k + 3]) if _with_cloud(layout) else None
+    k += 3 * _with_cloud(layout)
+    eps = float(th[k]) if layout.with_eps else None
     p = level_pressures(layout.n_levels, layout.log10_p_bottom, layout.log10_p_top)
     T = fe_temperature(np.log10(p), layout.log10_p_bottom, layout.log10_p_top,
                        layout.n_elements, layout.order, node_temperatures(T1, b))
@@ -105,4 +118,4 @@ def unpack(layout, theta):
     fac = np.asarray(layout.species_factor, dtype=np.float64)
     x = np.array([fac[s] * xf[src[s]] if src[s] >= 0 else 0.0 for s in range(len(src))])
     scale = f * (layout.radius_cm / (d_pc * PARSEC_CM)) ** 2
-    return p, T, x, float(log_g), float(scale), eps
+    return p, T, x, float(log_g), float(scale), cloud, eps

@@ -226,6 +226,8 @@ extern "C" void hr2_ctx_destroy(hr2_ctx *ctx) {
   ctx->cols.release();
   ctx->segs.release();
   ctx->convsegs.release();
+  ctx->terms.release();
+  ctx->unpacked.release();
   if (ctx->pinned) (void)hipHostFree(ctx->pinned);
   for (hipEvent_t ev : ctx->tev) (void)hipEventDestroy(ev);
   if (ctx->scratch_event) (void)hipEventDestroy(ctx->scratch_event);
@@ -499,6 +501,12 @@ hr2_status check_column(const hr2_tables *t, const hr2_column &c, int want_level
   if (!(xs < 1.0)) return set_error(HR2_E_INVALID_ARG, "mixing ratios must sum below 1");
   if (!std::isfinite(c.log_g_cgs) || !std::isfinite(c.scale))
     return set_error(HR2_E_INVALID_ARG, "log g and scale must be finite");
+  if (!(c.tau_cloud >= 0.0) || !std::isfinite(c.tau_cloud))
+    return set_error(HR2_E_INVALID_ARG, "tau_cloud must be finite and >= 0");
+  if (c.tau_cloud > 0.0 &&
+      (!(c.p_cloud_top_bar > 0.0) || !std::isfinite(c.p_cloud_top_bar) ||
+       !(c.cloud_bottom_frac > 1.0) || !std::isfinite(c.cloud_bottom_frac)))
+    return set_error(HR2_E_INVALID_ARG, "a cloud needs p_cloud_top_bar > 0 and bottom_frac > 1");
   return HR2_OK;
 }
 
@@ -509,15 +517,18 @@ hr2_status check_n_mu(int n_mu) {
 
 void pack_columns(const hr2_tables *t, int n_sets, const hr2_column *cols, std::vector<double> &buf) {
   const int L = cols[0].n_levels, S = t->view.S;
-  buf.resize((size_t)n_sets * (2 * L + S + 2));
+  buf.resize((size_t)n_sets * (2 * L + S + 5));
   double *p = buf.data(), *T = p + (size_t)n_sets * L, *x = T + (size_t)n_sets * L;
-  double *lg = x + (size_t)n_sets * S, *sc = lg + n_sets;
+  double *lg = x + (size_t)n_sets * S, *sc = lg + n_sets, *cl = sc + n_sets;
   for (int s = 0; s < n_sets; ++s) {
     std::memcpy(p + (size_t)s * L, cols[s].p_bar, sizeof(double) * L);
     std::memcpy(T + (size_t)s * L, cols[s].T_K, sizeof(double) * L);
     std::memcpy(x + (size_t)s * S, cols[s].x, sizeof(double) * S);
     lg[s] = cols[s].log_g_cgs;
     sc[s] = cols[s].scale;
+    cl[3 * s] = cols[s].tau_cloud;
+    cl[3 * s + 1] = cols[s].p_cloud_top_bar;
+    cl[3 * s + 2] = cols[s].cloud_bottom_frac;
   }
 }
 
@@ -529,6 +540,7 @@ ColumnsView columns_view(const void *dev, int n_sets, int L, int S) {
   v.x = v.T + (size_t)n_sets * L;
   v.logg = v.x + (size_t)n_sets * S;
   v.scale = v.logg + n_sets;
+  v.cloud = v.scale + n_sets;
   v.B = n_sets;
   v.L = L;
   return v;
@@ -710,10 +722,34 @@ extern "C" void hr2_obs_destroy(hr2_obs *o) {
   if (o->d_kstart) (void)hipFree(o->d_kstart);
   if (o->d_mlo) (void)hipFree(o->d_mlo);
   if (o->d_mlen) (void)hipFree(o->d_mlen);
+  if (o->d_D) (void)hipFree(o->d_D);   // d_s2 lives in the same allocation
   delete o;
 }
 
 extern "C" int hr2_obs_n_bins(const hr2_obs *o) { return o ? o->n_bins : 0; }
+
+extern "C" hr2_status hr2_obs_set_data(hr2_obs *o, const double *D, const double *sigma) {
+  if (!o || !D || !sigma) return set_error(HR2_E_INVALID_ARG, "NULL argument");
+  const int nb = o->n_bins;
+  std::vector<double> buf(2 * (size_t)nb);
+  for (int j = 0; j < nb; ++j) {
+    if (!std::isfinite(D[j]) || !std::isfinite(sigma[j]) || !(sigma[j] > 0.0))
+      return set_error(HR2_E_INVALID_ARG, "data must be finite and sigma > 0 in every bin");
+    buf[j] = D[j];
+    buf[nb + j] = sigma[j] * sigma[j];
+  }
+  HIP_TRY(hipSetDevice(o->ctx->device));
+  if (o->d_D == nullptr) {
+    void *p = nullptr;
+    HIP_TRY(hipMalloc(&p, buf.size() * sizeof(double)));
+    o->d_D = (double *)p;
+    o->d_s2 = o->d_D + nb;
+  }
+  // the previous data may still be read by queued work on any stream
+  HIP_TRY(hipDeviceSynchronize());
+  HIP_TRY(hipMemcpy(o->d_D, buf.data(), buf.size() * sizeof(double), hipMemcpyHostToDevice));
+  return HR2_OK;
+}
 
 // ------------------------------------------------------------ stage calls
 namespace {
@@ -836,17 +872,27 @@ static hipEvent_t timing_event(hr2_ctx *ctx, int k) {
   return ctx->tev[at];
 }
 
+// Likelihood outputs of a forward call (NULL: bins only).
+struct LikeArgs {
+  const double *log10_eps;   // device [B] or NULL
+  double *lnl;               // device [B]
+};
+
 hr2_status run_forward(hr2_ctx *ctx, const hr2_tables *t, const hr2_obs *o, const ColumnsView &cv,
-                       int n_mu, void *bins, void *fplus, int *status, hipStream_t s) {
+                       int n_mu, void *bins, void *fplus, int *status, hipStream_t s,
+                       const LikeArgs *like = nullptr) {
   const hr2_window &w = o->window;
   const int B = cv.B, L = cv.L;
   const size_t rec_bytes = (size_t)B * L * rec_size(t);
   const size_t fp_bytes = fplus == nullptr ? (size_t)B * w.nu_count * real_size(t) : 0;
-  if ((rec_bytes > ctx->recs.cap || fp_bytes > ctx->fplus.cap) && capturing(s))
+  const size_t term_bytes = like ? (size_t)B * o->n_bins * sizeof(double) : 0;
+  if ((rec_bytes > ctx->recs.cap || fp_bytes > ctx->fplus.cap || term_bytes > ctx->terms.cap) &&
+      capturing(s))
     return set_error(HR2_E_UNSUPPORTED,
                      "scratch would grow under stream capture: make the same call once first");
   hr2_status st = ctx->recs.ensure(rec_bytes);
   if (st != HR2_OK) return st;
+  if (like && (st = ctx->terms.ensure(term_bytes)) != HR2_OK) return st;
   if (fplus == nullptr) {
     if ((st = ctx->fplus.ensure(fp_bytes)) != HR2_OK) return st;
     fplus = ctx->fplus.ptr;
@@ -897,11 +943,18 @@ hr2_status run_forward(hr2_ctx *ctx, const hr2_tables *t, const hr2_obs *o, cons
   cs.scale_const = 0.0;
   cs.n_sets = B;
   cs.n_bins = o->n_bins;
+  if (like) {
+    cs.D = o->d_D;
+    cs.s2 = o->d_s2;
+    cs.log10_eps = like->log10_eps;
+    cs.terms = (double *)ctx->terms.ptr;
+  }
   if ((st = upload_cached(ctx, ctx->convsegs, ctx->convsegs_shadow, &cs, sizeof(cs), s)) != HR2_OK)
     return st;
   if (timed) HIP_TRY(hipEventRecord(ev[2], s));
   HIP_TRY(launch_convolve_bin(o->fp64, (const ConvSeg *)ctx->convsegs.ptr, 1,
                               (int64_t)B * o->n_bins, fplus, bins, s));
+  if (like) HIP_TRY(launch_lnl_reduce(cs.terms, B, o->n_bins, like->lnl, s));
   if (timed) {
     HIP_TRY(hipEventRecord(ev[3], s));
     ctx->tev_used += 4;
@@ -936,8 +989,8 @@ extern "C" hr2_status hr2_forward_batch_dev(hr2_ctx *ctx, const hr2_tables *t, c
                                             int n_sets, int n_levels, const double *p_dev,
                                             const double *T_dev, const double *x_dev,
                                             const double *logg_dev, const double *scale_dev,
-                                            int n_mu, void *bins, void *fplus, int *status_dev,
-                                            void *stream) {
+                                            const double *cloud_dev, int n_mu, void *bins,
+                                            void *fplus, int *status_dev, void *stream) {
   if (!ctx || !t || !o || !p_dev || !T_dev || !x_dev || !logg_dev || !scale_dev || !bins)
     return set_error(HR2_E_INVALID_ARG, "NULL argument");
   if (o->tables != t) return set_error(HR2_E_INVALID_ARG, "layout was made for other tables");
@@ -954,9 +1007,226 @@ extern "C" hr2_status hr2_forward_batch_dev(hr2_ctx *ctx, const hr2_tables *t, c
   cv.x = x_dev;
   cv.logg = logg_dev;
   cv.scale = scale_dev;
+  cv.cloud = cloud_dev;
   cv.B = n_sets;
   cv.L = n_levels;
   if ((st = run_forward(ctx, t, o, cv, n_mu, bins, fplus, status_dev, s)) != HR2_OK) return st;
+  return ctx_end(ctx, s);
+}
+
+namespace {
+
+hr2_status check_like(const hr2_tables *t, const hr2_obs *o, int n_sets, int n_mu) {
+  if (o->tables != t) return set_error(HR2_E_INVALID_ARG, "layout was made for other tables");
+  if (o->d_D == nullptr)
+    return set_error(HR2_E_INVALID_ARG, "no data on this layout: call hr2_obs_set_data first");
+  if (n_sets < 1) return set_error(HR2_E_INVALID_ARG, "n_sets must be >= 1");
+  return check_n_mu(n_mu);
+}
+
+}  // namespace
+
+extern "C" hr2_status hr2_loglike_batch(hr2_ctx *ctx, const hr2_tables *t, const hr2_obs *o,
+                                        int n_sets, const hr2_column *cols, int n_mu,
+                                        const double *log10_eps, double *lnl, void *bins,
+                                        void *stream) {
+  if (!ctx || !t || !o || !cols || !lnl) return set_error(HR2_E_INVALID_ARG, "NULL argument");
+  hr2_status st = check_like(t, o, n_sets, n_mu);
+  if (st != HR2_OK) return st;
+  for (int i = 0; i < n_sets; ++i)
+    if ((st = check_column(t, cols[i], cols[0].n_levels)) != HR2_OK) return st;
+  if (log10_eps)
+    for (int i = 0; i < n_sets; ++i)
+      if (!std::isfinite(log10_eps[i]))
+        return set_error(HR2_E_INVALID_ARG, "log10_eps must be finite");
+  hipStream_t s = (hipStream_t)stream;
+  if ((st = ctx_begin(ctx, s)) != HR2_OK) return st;
+  std::vector<double> buf;
+  pack_columns(t, n_sets, cols, buf);
+  const size_t n_col = buf.size();
+  if (log10_eps) buf.insert(buf.end(), log10_eps, log10_eps + n_sets);
+  if ((st = stage_upload(ctx, ctx->cols, buf.data(), buf.size() * sizeof(double), s)) != HR2_OK)
+    return st;
+  const ColumnsView cv = columns_view(ctx->cols.ptr, n_sets, cols[0].n_levels, t->view.S);
+  LikeArgs like{log10_eps ? (const double *)ctx->cols.ptr + n_col : nullptr, lnl};
+  if ((st = run_forward(ctx, t, o, cv, n_mu, bins, nullptr, nullptr, s, &like)) != HR2_OK)
+    return st;
+  return ctx_end(ctx, s);
+}
+
+extern "C" hr2_status hr2_loglike_batch_dev(hr2_ctx *ctx, const hr2_tables *t, const hr2_obs *o,
+                                            int n_sets, int n_levels, const double *p_dev,
+                                            const double *T_dev, const double *x_dev,
+                                            const double *logg_dev, const double *scale_dev,
+                                            const double *cloud_dev, const double *log10_eps_dev,
+                                            int n_mu, double *lnl, void *bins, int *status_dev,
+                                            void *stream) {
+  if (!ctx || !t || !o || !p_dev || !T_dev || !x_dev || !logg_dev || !scale_dev || !lnl)
+    return set_error(HR2_E_INVALID_ARG, "NULL argument");
+  hr2_status st = check_like(t, o, n_sets, n_mu);
+  if (st != HR2_OK) return st;
+  if (n_levels < 2 || n_levels > HR2_MAX_LEVELS)
+    return set_error(HR2_E_INVALID_ARG, "n_levels must be in [2, 1024]");
+  hipStream_t s = (hipStream_t)stream;
+  if ((st = ctx_begin(ctx, s)) != HR2_OK) return st;
+  ColumnsView cv;
+  cv.p = p_dev;
+  cv.T = T_dev;
+  cv.x = x_dev;
+  cv.logg = logg_dev;
+  cv.scale = scale_dev;
+  cv.cloud = cloud_dev;
+  cv.B = n_sets;
+  cv.L = n_levels;
+  LikeArgs like{log10_eps_dev, lnl};
+  if ((st = run_forward(ctx, t, o, cv, n_mu, bins, nullptr, status_dev, s, &like)) != HR2_OK)
+    return st;
+  return ctx_end(ctx, s);
+}
+
+// ------------------------------------------------------ parameter vectors
+namespace {
+
+// Gauss-Lobatto points of [0, 1] for n = q + 1 points: the ends and the
+// roots of P'_q, found by Newton steps with P''_q from Legendre's equation
+// (1 - x^2) P'' = 2 x P' - q (q + 1) P, started at the Chebyshev-Lobatto
+// points.
+void gauss_lobatto_01(int q, double *x01) {
+  x01[0] = 0.0;
+  x01[q] = 1.0;
+  const double pi = 3.14159265358979323846;
+  for (int i = 1; i < q; ++i) {
+    double z = -std::cos(pi * i / q);
+    for (int it = 0; it < 100; ++it) {
+      double pa = 1.0, pb = 0.0, da = 0.0, db = 0.0;   // P_k, P_{k-1} and derivatives
+      for (int k = 1; k <= q; ++k) {
+        const double pc = pb, dc = db;
+        pb = pa;
+        db = da;
+        pa = ((2.0 * k - 1.0) * z * pb - (k - 1.0) * pc) / k;
+        da = ((2.0 * k - 1.0) * (pb + z * db) - (k - 1.0) * dc) / k;
+      }
+      const double d2 = (2.0 * z * da - q * (q + 1.0) * pa) / (1.0 - z * z);
+      const double step = da / d2;
+      z -= step;
+      if (std::fabs(step) <= 1e-16) break;
+    }
+    x01[i] = 0.5 * (z + 1.0);
+  }
+}
+
+}  // namespace
+
+extern "C" hr2_status hr2_params_create(hr2_ctx *ctx, const hr2_tables *t,
+                                        const hr2_param_layout *lay, hr2_params **out) {
+  if (!ctx || !t || !lay || !out) return set_error(HR2_E_INVALID_ARG, "NULL argument");
+  *out = nullptr;
+  const int S = t->view.S;
+  if (lay->n_elements < 1 || lay->order < 1 || lay->order > HR2_MAX_ORDER ||
+      (int64_t)lay->n_elements * lay->order + 1 > HR2_MAX_TNODES)
+    return set_error(HR2_E_INVALID_ARG, "need K_e >= 1, 1 <= q <= 8 and K_e q + 1 <= 128");
+  if (lay->n_levels < 2 || lay->n_levels > HR2_MAX_LEVELS)
+    return set_error(HR2_E_INVALID_ARG, "n_levels must be in [2, 1024]");
+  if (!std::isfinite(lay->log10_p_bottom) || !std::isfinite(lay->log10_p_top) ||
+      !(lay->log10_p_top < lay->log10_p_bottom))
+    return set_error(HR2_E_INVALID_ARG, "need finite log10_p_top < log10_p_bottom");
+  if (!(lay->radius_cm > 0.0) || !std::isfinite(lay->radius_cm))
+    return set_error(HR2_E_INVALID_ARG, "radius_cm must be finite and > 0");
+  if (lay->n_free < 0 || lay->n_free > HR2_MAX_SPECIES || (lay->with_eps != 0 && lay->with_eps != 1) ||
+      (lay->with_cloud != 0 && lay->with_cloud != 1))
+    return set_error(HR2_E_INVALID_ARG,
+                     "n_free must be in [0, 12], with_cloud and with_eps 0 or 1");
+  if (S > 0 && (!lay->species_src || !lay->species_factor))
+    return set_error(HR2_E_INVALID_ARG, "NULL species map");
+  auto *pp = new hr2_params();
+  pp->ctx = ctx;
+  pp->tables = t;
+  ParamView &v = pp->view;
+  for (int s = 0; s < S; ++s) {
+    const int src = lay->species_src[s];
+    const double f = lay->species_factor[s];
+    if (src < -1 || src >= lay->n_free || !std::isfinite(f) || f < 0.0) {
+      delete pp;
+      return set_error(HR2_E_INVALID_ARG,
+                       "species_src must be in [-1, n_free) and species_factor finite, >= 0");
+    }
+    v.src[s] = src;
+    v.fac[s] = f;
+  }
+  const int q = lay->order;
+  gauss_lobatto_01(q, v.nodes);
+  for (int i = 0; i <= q; ++i) {
+    double den = 1.0;
+    for (int j = 0; j <= q; ++j)
+      if (j != i) den *= v.nodes[i] - v.nodes[j];
+    v.inv_den[i] = 1.0 / den;
+  }
+  v.lp_bottom = lay->log10_p_bottom;
+  v.lp_top = lay->log10_p_top;
+  v.radius_cm = lay->radius_cm;
+  v.K = lay->n_elements;
+  v.q = q;
+  v.L = lay->n_levels;
+  v.S = S;
+  v.n_free = lay->n_free;
+  v.with_cloud = lay->with_cloud;
+  v.with_eps = lay->with_eps;
+  v.n_theta = 3 + v.K * q + 1 + v.n_free + 3 * v.with_cloud + v.with_eps;
+  *out = pp;
+  return HR2_OK;
+}
+
+extern "C" void hr2_params_destroy(hr2_params *p) { delete p; }
+
+extern "C" int hr2_params_n_theta(const hr2_params *p) { return p ? p->view.n_theta : 0; }
+
+extern "C" hr2_status hr2_params_unpack_dev(hr2_ctx *ctx, const hr2_params *pp, int n_sets,
+                                            const double *theta, double *p_dev, double *T_dev,
+                                            double *x_dev, double *logg_dev, double *scale_dev,
+                                            double *cloud_dev, double *eps_dev, void *stream) {
+  if (!ctx || !pp || !theta || !p_dev || !T_dev || !logg_dev || !scale_dev ||
+      (!x_dev && pp->view.S > 0))
+    return set_error(HR2_E_INVALID_ARG, "NULL argument");
+  if (n_sets < 1) return set_error(HR2_E_INVALID_ARG, "n_sets must be >= 1");
+  hipStream_t s = (hipStream_t)stream;
+  hr2_status st;
+  if ((st = ctx_begin(ctx, s)) != HR2_OK) return st;
+  HIP_TRY(launch_unpack(pp->view, n_sets, theta, p_dev, T_dev, x_dev, logg_dev, scale_dev,
+                        cloud_dev, eps_dev, s));
+  return ctx_end(ctx, s);
+}
+
+extern "C" hr2_status hr2_forward_params_dev(hr2_ctx *ctx, const hr2_tables *t, const hr2_obs *o,
+                                             const hr2_params *pp, int n_sets,
+                                             const double *theta, int n_mu, void *bins,
+                                             double *lnl, int *status_dev, void *stream) {
+  if (!ctx || !t || !o || !pp || !theta || (!bins && !lnl))
+    return set_error(HR2_E_INVALID_ARG, "NULL argument");
+  if (pp->tables != t) return set_error(HR2_E_INVALID_ARG, "parameter layout is for other tables");
+  if (o->tables != t) return set_error(HR2_E_INVALID_ARG, "layout was made for other tables");
+  if (n_sets < 1) return set_error(HR2_E_INVALID_ARG, "n_sets must be >= 1");
+  hr2_status st = lnl ? check_like(t, o, n_sets, n_mu) : check_n_mu(n_mu);
+  if (st != HR2_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  const ParamView &v = pp->view;
+  const int B = n_sets, L = v.L, S = v.S;
+  const size_t n_dbl = (size_t)B * (2 * (size_t)L + S + 6);   // columns, clouds, eps
+  if (n_dbl * sizeof(double) > ctx->unpacked.cap && capturing(s))
+    return set_error(HR2_E_UNSUPPORTED,
+                     "scratch would grow under stream capture: make the same call once first");
+  if ((st = ctx_begin(ctx, s)) != HR2_OK) return st;
+  if ((st = ctx->unpacked.ensure(n_dbl * sizeof(double))) != HR2_OK) return st;
+  ColumnsView cv = columns_view(ctx->unpacked.ptr, B, L, S);
+  double *cloud = const_cast<double *>(cv.cloud);
+  double *eps = cloud + (size_t)3 * B;
+  HIP_TRY(launch_unpack(v, B, theta, const_cast<double *>(cv.p), const_cast<double *>(cv.T),
+                        const_cast<double *>(cv.x), const_cast<double *>(cv.logg),
+                        const_cast<double *>(cv.scale), cloud, eps, s));
+  if (!v.with_cloud) cv.cloud = nullptr;
+  LikeArgs like{v.with_eps ? eps : nullptr, lnl};
+  if ((st = run_forward(ctx, t, o, cv, n_mu, bins, nullptr, status_dev, s, lnl ? &like : nullptr)) !=
+      HR2_OK)
+    return st;
   return ctx_end(ctx, s);
 }
 

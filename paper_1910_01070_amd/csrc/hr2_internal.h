@@ -34,7 +34,8 @@ struct alignas(16) LevelRecF {
   float hdz;             // dz_l / 2 of layer l -> l+1 (0 at the top level)
   float pl_hi, pl_lo;    // c2 log2(e) / T_l as an unevaluated float sum
   float a_s[kMaxSpecies];  // n_s 2^{c_s}
-  float pad[2];
+  float dtc;             // gray-cloud optical depth of layer l -> l+1
+  float pad;
 };
 static_assert(sizeof(LevelRecF) == 128, "LevelRecF must be 128 bytes");
 
@@ -49,7 +50,8 @@ struct alignas(16) LevelRecD {
   double hdz;
   double T;               // level temperature (Planck in FP64)
   double a_s[kMaxSpecies];
-  double pad[6];
+  double dtc;             // gray-cloud optical depth of layer l -> l+1
+  double pad[5];
 };
 static_assert(sizeof(LevelRecD) == 256, "LevelRecD must be 256 bytes");
 
@@ -81,6 +83,7 @@ struct ColumnsView {
   const double *x;      // [B][S]
   const double *logg;   // [B]
   const double *scale;  // [B]
+  const double *cloud = nullptr;  // [B][3] (tau_c, p_top_bar, bottom_frac) or NULL: clear sky
   int B, L;
 };
 
@@ -110,6 +113,11 @@ struct ConvSeg {
   const double *scale;      // [n_sets] or NULL
   double scale_const;       // used when scale == NULL
   int32_t n_sets, n_bins;
+  // Likelihood (Eq. 19, Eq. 22-23); all NULL when only the bins are wanted.
+  const double *D;          // [n_bins] observed binned flux
+  const double *s2;         // [n_bins] sigma_j^2
+  const double *log10_eps;  // [n_sets] error inflation exponent, or NULL
+  double *terms;            // [n_sets][n_bins] per-bin terms of ln L
 };
 
 // Angular quadrature constants for n_mu = 1..8 (Eq. 8): row n-1.
@@ -121,6 +129,19 @@ struct AngleTable {
   double mu_d[kMaxMu][kMaxMu];
   double inv_mu_d[kMaxMu][kMaxMu];
   double cw_d[kMaxMu][kMaxMu];
+};
+
+// Parameter-vector layout (finite-element temperature, free chemistry,
+// Eq. 9 scale), passed to the unpack kernel by value.
+constexpr int kMaxOrder = HR2_MAX_ORDER;
+constexpr int kMaxTNodes = HR2_MAX_TNODES;
+struct ParamView {
+  double nodes[kMaxOrder + 1];     // Gauss-Lobatto points on [0, 1]
+  double inv_den[kMaxOrder + 1];   // 1 / prod_{j != i} (x_i - x_j)
+  double fac[kMaxSpecies];
+  int32_t src[kMaxSpecies];
+  double lp_bottom, lp_top, radius_cm;
+  int32_t K, q, L, S, n_free, with_cloud, with_eps, n_theta;
 };
 
 // ----------------------------------------------------------------- launchers
@@ -146,6 +167,15 @@ hipError_t launch_opacity_only(const TableView &tv, const void *recs, int n_leve
 hipError_t launch_convolve_bin(bool fp64, const ConvSeg *segs_dev, int n_segs,
                                int64_t total_items, const void *in, void *out,
                                hipStream_t stream);
+// ln L per set: the sum over bins of the terms k_convolve_bin wrote.
+hipError_t launch_lnl_reduce(const double *terms, int n_sets, int n_bins, double *lnl,
+                             hipStream_t stream);
+
+// Parameter vectors -> FP64 columns (p, T [B][L], x [B][S], log g, scale
+// [B], cloud [B][3], eps [B]; cloud and eps may be NULL).
+hipError_t launch_unpack(const ParamView &pv, int n_sets, const double *theta, double *p,
+                         double *T, double *x, double *logg, double *scale, double *cloud,
+                         double *eps, hipStream_t stream);
 
 // Observation layout build: Z_i and q_i for window points [i0, i0 + n_pts),
 // then the nnz banded per-bin weights.
@@ -180,4 +210,11 @@ struct hr2_obs {
   int64_t *d_kstart = nullptr;       // [n_bins]
   int32_t *d_mlo = nullptr, *d_mlen = nullptr;
   size_t bytes = 0;
+  double *d_D = nullptr, *d_s2 = nullptr;   // [n_bins] data and sigma^2 (hr2_obs_set_data)
+};
+
+struct hr2_params {
+  hr2_ctx *ctx = nullptr;
+  const hr2_tables *tables = nullptr;
+  hr2::ParamView view{};
 };

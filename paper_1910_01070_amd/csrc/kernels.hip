@@ -29,6 +29,8 @@ constexpr double kMHe = 4.0026;
 constexpr double kC2 = kH * kC / kKB;          // second radiation constant, cm K
 constexpr double kC1 = 2.0 * kH * kC * kC;     // 2 h c^2
 constexpr double kLog2e = 1.4426950408889634074;
+constexpr double kTwoPi = 6.283185307179586477;
+constexpr double kParsecCm = 3.0856775814913673e18;   // IAU 2015 parsec
 constexpr float kLn2f = 0.69314718055994530942f;
 
 __constant__ AngleTable c_ang;
@@ -158,6 +160,19 @@ __global__ __launch_bounds__(256) void k_levels(TableView tv, ColumnsView cv,
     mm += x[q] * tv.mass[q];
   }
   bad |= !(xs < 1.0) || !isfinite(cv.logg[s]) || !isfinite(cv.scale[s]);
+  // gray cloud (App. B): tau_c >= 0; with tau_c > 0 a top pressure > 0 and a
+  // bottom at bottom_frac > 1 times the top
+  double tau_c = 0.0, lc_top = 0.0, lc_bot = 1.0;
+  if (cv.cloud) {
+    const double *cl = cv.cloud + (int64_t)s * 3;
+    tau_c = cl[0];
+    bad |= !(tau_c >= 0.0) || !isfinite(tau_c);
+    if (tau_c > 0.0) {
+      bad |= !(cl[1] > 0.0) || !isfinite(cl[1]) || !(cl[2] > 1.0) || !isfinite(cl[2]);
+      lc_top = log(cl[1]);
+      lc_bot = log(cl[1] * cl[2]);
+    }
+  }
   for (int l = threadIdx.x; l < L; l += blockDim.x) {
     bad |= !(p[l] > 0.0) || !isfinite(p[l]) || !(T[l] > 0.0) || !isfinite(T[l]);
     if (l + 1 < L) bad |= !(p[l] > p[l + 1]);
@@ -222,16 +237,24 @@ __global__ __launch_bounds__(256) void k_levels(TableView tv, ColumnsView cv,
     }
     if (bad) hdz = __builtin_nan("");
     r.hdz = (Real)hdz;
+    // the cloud's optical depth, spread uniformly in ln p over
+    // [p_top, p_top bottom_frac]: this layer's share of that range
+    double dtc = 0.0;
+    if (tau_c > 0.0 && l + 1 < L) {
+      const double hi = fmin(log(p[l]), lc_bot), lo = fmax(log(p[l + 1]), lc_top);
+      if (hi > lo) dtc = tau_c * (hi - lo) / (lc_bot - lc_top);
+    }
+    r.dtc = (Real)dtc;
     if constexpr (std::is_same<Real, float>::value) {
       const double pl = kC2 * kLog2e / T[l];
       const float hi = (float)pl;
       r.pl_hi = hi;
       r.pl_lo = (float)(pl - (double)hi);
-      r.pad[0] = r.pad[1] = 0.0f;
+      r.pad = 0.0f;
     } else {
       r.T = T[l];
       r.pad0 = 0;
-      for (int q = 0; q < 6; ++q) r.pad[q] = 0.0;
+      for (int q = 0; q < 5; ++q) r.pad[q] = 0.0;
     }
     recs[(int64_t)s * L + l] = r;
   }
@@ -457,7 +480,8 @@ __global__ __launch_bounds__(512) void k_column(TableView tv, const ColSeg *__re
     a_l2e[k] = c_ang.l2e_mu[nmu - 1][k];
     a_mud[k] = kF64 ? c_ang.mu_d[nmu - 1][k] : 0.0;
   }
-  Real tau = (Real)0, chi_prev = (Real)0, S_prev = (Real)0, hdz_prev = (Real)0;
+  Real tau = (Real)0, chi_prev = (Real)0, S_prev = (Real)0, hdz_prev = (Real)0,
+       dtc_prev = (Real)0;
 
   // Fetch the rows a level needs that the slots do not hold yet.  The rows
   // of level l+1 are requested right after level l's opacity is formed (its
@@ -540,7 +564,8 @@ __global__ __launch_bounds__(512) void k_column(TableView tv, const ColSeg *__re
 #pragma unroll
         for (int k = 0; k < MAXMU; ++k) I[k] = (chunk == 0) ? S : (Real)0;
       } else {
-        const Real dtau = (chi_prev + chi) * hdz_prev;
+        // trapezoid of chi over the layer, plus its share of a gray cloud
+        const Real dtau = (chi_prev + chi) * hdz_prev + dtc_prev;
         tau += dtau;
         if constexpr (kF64) {
 #pragma unroll
@@ -557,6 +582,7 @@ __global__ __launch_bounds__(512) void k_column(TableView tv, const ColSeg *__re
       chi_prev = chi;
       S_prev = S;
       hdz_prev = r.hdz;
+      dtc_prev = r.dtc;
     }
   }
 
@@ -788,7 +814,15 @@ __global__ __launch_bounds__(256) void k_convolve_bin(const ConvSeg *__restrict_
   if (threadIdx.x == 0) {
     const Real tot = (part[0] + part[1]) + (part[2] + part[3]);
     const double sc = d.scale ? d.scale[s] : d.scale_const;
-    out[d.out_offset + (int64_t)s * d.n_bins + jb] = tot * (Real)sc;
+    const Real v = tot * (Real)sc;
+    if (out) out[d.out_offset + (int64_t)s * d.n_bins + jb] = v;
+    if (d.terms) {
+      // Eq. 19 term of bin j in FP64; with Eq. 22 the variance gains 10^eps
+      double s2 = d.s2[jb];
+      if (d.log10_eps) s2 += exp10(d.log10_eps[s]);
+      const double r = d.D[jb] - (double)v;
+      d.terms[(int64_t)s * d.n_bins + jb] = -r * r / (2.0 * s2) - 0.5 * log(kTwoPi * s2);
+    }
   }
 }
 
@@ -803,6 +837,117 @@ hipError_t launch_convolve_bin(bool fp64, const ConvSeg *segs_dev, int n_segs,
   else
     hipLaunchKernelGGL(k_convolve_bin<float>, grid, dim3(256), 0, stream, segs_dev, n_segs,
                        total_items, (const float *)in, (float *)out);
+  return hipGetLastError();
+}
+
+// ln L of set s = the sum of its n_bins terms, in a fixed order (strided
+// per-thread sums, wave butterfly, then the four waves), so repeated calls
+// give identical results.
+__global__ __launch_bounds__(256) void k_lnl_reduce(const double *__restrict__ terms,
+                                                    int n_bins, double *__restrict__ lnl) {
+  __shared__ double part[4];
+  const int s = blockIdx.x;
+  const double *t = terms + (int64_t)s * n_bins;
+  double acc = 0.0;
+  for (int j = threadIdx.x; j < n_bins; j += 256) acc += t[j];
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) lnl[s] = (part[0] + part[1]) + (part[2] + part[3]);
+}
+
+hipError_t launch_lnl_reduce(const double *terms, int n_sets, int n_bins, double *lnl,
+                             hipStream_t stream) {
+  if (n_sets <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_lnl_reduce, dim3((unsigned)n_sets), dim3(256), 0, stream, terms, n_bins,
+                     lnl);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------ parameter unpack
+// One workgroup per parameter vector.  Node temperatures T_0 = T1,
+// T_n = b_n T_{n-1} (Sect. 2.5.1); level l sits at u = l K / (L - 1) element
+// widths above the bottom (levels and elements both equidistant in log p
+// over the same range), in element k = min(floor(u), K - 1) at local
+// coordinate xi = u - k, where T = sum_i T_{kq+i} l_i(xi) (Eq. 12-13).
+__global__ __launch_bounds__(256) void k_unpack(ParamView pv, const double *__restrict__ theta,
+                                                double *__restrict__ p, double *__restrict__ T,
+                                                double *__restrict__ x, double *__restrict__ logg,
+                                                double *__restrict__ scale,
+                                                double *__restrict__ cloud,
+                                                double *__restrict__ eps) {
+  __shared__ double Tn[kMaxTNodes];
+  __shared__ int bad_s;
+  const int s = blockIdx.x;
+  const double *th = theta + (int64_t)s * pv.n_theta;
+  const int NT = pv.K * pv.q + 1;
+  if (threadIdx.x == 0) {
+    bool bad = !isfinite(th[0]) || !(th[1] > 0.0) || !isfinite(th[1]) || !(th[2] > 0.0) ||
+               !isfinite(th[2]);
+    double t = th[3];
+    bad |= !(t > 0.0) || !isfinite(t);
+    Tn[0] = t;
+    for (int n = 1; n < NT; ++n) {
+      const double b = th[3 + n];
+      bad |= !(b > 0.0) || !isfinite(b);
+      t *= b;
+      Tn[n] = t;
+    }
+    for (int k = 0; k < pv.n_free; ++k) {
+      const double xf = th[3 + NT + k];
+      bad |= !(xf >= 0.0) || !isfinite(xf);
+    }
+    if (pv.with_cloud) {
+      const double *c = th + 3 + NT + pv.n_free;
+      bad |= !(c[0] >= 0.0) || !isfinite(c[0]);
+      if (c[0] > 0.0)
+        bad |= !(c[1] > 0.0) || !isfinite(c[1]) || !(c[2] > 1.0) || !isfinite(c[2]);
+    }
+    if (pv.with_eps) bad |= !isfinite(th[3 + NT + pv.n_free + 3 * pv.with_cloud]);
+    bad_s = bad ? 1 : 0;
+  }
+  __syncthreads();
+  const bool bad = bad_s != 0;
+  const int L = pv.L;
+  const double step = (pv.lp_top - pv.lp_bottom) / (double)(L - 1);
+  for (int l = threadIdx.x; l < L; l += blockDim.x) {
+    const double lp = l == L - 1 ? pv.lp_top : pv.lp_bottom + (double)l * step;
+    p[(int64_t)s * L + l] = exp10(lp);
+    const double u = (double)l * (double)pv.K / (double)(L - 1);
+    int k = (int)floor(u);
+    k = k < 0 ? 0 : (k > pv.K - 1 ? pv.K - 1 : k);
+    const double xi = u - (double)k;
+    double acc = 0.0;
+    for (int i = 0; i <= pv.q; ++i) {
+      double li = pv.inv_den[i];
+      for (int j = 0; j <= pv.q; ++j)
+        if (j != i) li *= xi - pv.nodes[j];
+      acc += Tn[k * pv.q + i] * li;
+    }
+    T[(int64_t)s * L + l] = bad ? __builtin_nan("") : acc;
+  }
+  for (int sp = threadIdx.x; sp < pv.S; sp += blockDim.x) {
+    const int src = pv.src[sp];
+    x[(int64_t)s * pv.S + sp] = src >= 0 ? pv.fac[sp] * th[3 + NT + src] : 0.0;
+  }
+  if (threadIdx.x == 0) {
+    logg[s] = th[0];
+    const double rd = pv.radius_cm / (th[2] * kParsecCm);
+    scale[s] = th[1] * rd * rd;
+    const double *c = th + 3 + NT + pv.n_free;
+    if (cloud)
+      for (int k = 0; k < 3; ++k) cloud[(int64_t)s * 3 + k] = pv.with_cloud ? c[k] : 0.0;
+    if (eps) eps[s] = pv.with_eps ? c[3 * pv.with_cloud] : 0.0;
+  }
+}
+
+hipError_t launch_unpack(const ParamView &pv, int n_sets, const double *theta, double *p,
+                         double *T, double *x, double *logg, double *scale, double *cloud,
+                         double *eps, hipStream_t stream) {
+  if (n_sets <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_unpack, dim3((unsigned)n_sets), dim3(256), 0, stream, pv, theta, p, T, x,
+                     logg, scale, cloud, eps);
   return hipGetLastError();
 }
 

@@ -45,11 +45,20 @@ class TablesDesc(ctypes.Structure):
 
 class ColumnC(ctypes.Structure):
     _fields_ = [("n_levels", c_int), ("p_bar", _DP), ("T_K", _DP), ("x", _DP),
-                ("log_g_cgs", c_double), ("scale", c_double)]
+                ("log_g_cgs", c_double), ("scale", c_double), ("tau_cloud", c_double),
+                ("p_cloud_top_bar", c_double), ("cloud_bottom_frac", c_double)]
 
 
 class WindowC(ctypes.Structure):
     _fields_ = [("nu_begin", c_int64), ("nu_count", c_int64), ("nu_stride", c_int64)]
+
+
+class ParamLayoutC(ctypes.Structure):
+    _fields_ = [("n_elements", c_int), ("order", c_int), ("n_levels", c_int),
+                ("log10_p_bottom", c_double), ("log10_p_top", c_double), ("radius_cm", c_double),
+                ("n_free", c_int), ("with_cloud", c_int), ("with_eps", c_int),
+                ("species_src", POINTER(c_int)),
+                ("species_factor", _DP)]
 
 
 class RequestC(ctypes.Structure):
@@ -76,7 +85,9 @@ EXPORTS = [
     "hr2_forward_batch", "hr2_forward_batch_dev", "hr2_serve_create", "hr2_serve_submit",
     "hr2_serve_poll", "hr2_serve_wait", "hr2_serve_destroy", "hr2_serve_debug_fail_next_step",
     "hr2_serve_get_stats", "hr2_ctx_collect_timing", "hr2_serve_submit_packed",
-    "hr2_serve_debug_hold",
+    "hr2_serve_debug_hold", "hr2_obs_set_data", "hr2_loglike_batch", "hr2_loglike_batch_dev",
+    "hr2_params_create", "hr2_params_destroy", "hr2_params_n_theta", "hr2_params_unpack_dev",
+    "hr2_forward_params_dev",
 ]
 
 _lib = None
@@ -106,8 +117,8 @@ def load() -> ctypes.CDLL:
         "hr2_obs_n_bins": ([vp], c_int),
         "hr2_convolve_bin": ([vp, vp, vp, c_double, vp, vp], c_int),
         "hr2_forward_batch": ([vp, vp, vp, c_int, POINTER(ColumnC), c_int, vp, vp, vp], c_int),
-        "hr2_forward_batch_dev": ([vp, vp, vp, c_int, c_int, vp, vp, vp, vp, vp, c_int, vp, vp,
-                                   vp, vp], c_int),
+        "hr2_forward_batch_dev": ([vp, vp, vp, c_int, c_int, vp, vp, vp, vp, vp, vp, c_int, vp,
+                                   vp, vp, vp], c_int),
         "hr2_serve_create": ([vp, vp, c_size_t, c_int, POINTER(vp)], c_int),
         "hr2_serve_submit": ([vp, POINTER(RequestC), POINTER(c_uint64)], c_int),
         "hr2_serve_poll": ([vp, c_uint64, vp, c_size_t, POINTER(RequestInfo)], c_int),
@@ -119,6 +130,16 @@ def load() -> ctypes.CDLL:
         "hr2_serve_submit_packed": ([vp, WindowC, c_double, c_int, _DP, c_int, c_int, _DP, _DP,
                                      _DP, _DP, _DP, c_int, POINTER(c_uint64)], c_int),
         "hr2_serve_debug_hold": ([vp, c_int], c_int),
+        "hr2_obs_set_data": ([vp, _DP, _DP], c_int),
+        "hr2_loglike_batch": ([vp, vp, vp, c_int, POINTER(ColumnC), c_int, _DP, vp, vp, vp],
+                              c_int),
+        "hr2_loglike_batch_dev": ([vp, vp, vp, c_int, c_int, vp, vp, vp, vp, vp, vp, vp, c_int,
+                                   vp, vp, vp, vp], c_int),
+        "hr2_params_create": ([vp, vp, POINTER(ParamLayoutC), POINTER(vp)], c_int),
+        "hr2_params_destroy": ([vp], None),
+        "hr2_params_n_theta": ([vp], c_int),
+        "hr2_params_unpack_dev": ([vp, vp, c_int, vp, vp, vp, vp, vp, vp, vp, vp, vp], c_int),
+        "hr2_forward_params_dev": ([vp, vp, vp, vp, c_int, vp, c_int, vp, vp, vp, vp], c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(L, name)
@@ -174,7 +195,10 @@ class _Columns:
         for i, c in enumerate(cols):
             p, T, x = _f64(c.p_bar), _f64(c.T_K), _f64(c.x)
             self.keep += [p, T, x]
-            self.arr[i] = ColumnC(len(p), _ptr(p), _ptr(T), _ptr(x), float(c.log_g), float(c.scale))
+            cl = getattr(c, "cloud", None)
+            tau, ptop, frac = (0.0, 0.0, 0.0) if cl is None else (float(v) for v in cl)
+            self.arr[i] = ColumnC(len(p), _ptr(p), _ptr(T), _ptr(x), float(c.log_g), float(c.scale),
+                                  tau, ptop, frac)
 
 
 def window_c(window) -> WindowC:
@@ -261,6 +285,13 @@ class Obs:
         self.handle = h
         self.n_bins = len(e) - 1
 
+    def set_data(self, D, sigma):
+        """Observed binned flux and its 1-sigma errors (host, n_bins each), for ln L."""
+        D, sg = _f64(D), _f64(sigma)
+        if D.shape != (self.n_bins,) or sg.shape != (self.n_bins,):
+            raise ValueError("D and sigma need n_bins values each")
+        _check(load().hr2_obs_set_data(self.handle, _ptr(D), _ptr(sg)))
+
     def close(self):
         if self.handle:
             load().hr2_obs_destroy(self.handle)
@@ -309,19 +340,118 @@ def forward_batch(ctx: Context, tables: Tables, obs: Obs, cols: Sequence, n_mu: 
 
 
 def forward_batch_dev(ctx: Context, tables: Tables, obs: Obs, p, T, x, log_g, scale, n_mu: int,
-                      bins, fplus=None, status=None, stream=None):
-    """Columns already in device memory: p, T [B][L], x [B][S], log_g, scale [B] (float64)."""
+                      bins, fplus=None, status=None, stream=None, cloud=None):
+    """Columns already in device memory: p, T [B][L], x [B][S], log_g, scale [B],
+    cloud None or [B][3] (float64)."""
     import torch
     B, L = p.shape
     f64 = torch.float64
     real = tables.real
     fp = None if fplus is None else _dev_ptr(fplus, real, B * int(obs.window.count), "fplus")
     sp = None if status is None else _dev_ptr(status, torch.int32, B, "status")
+    cp = None if cloud is None else _dev_ptr(cloud, f64, 3 * B, "cloud")
     _check(load().hr2_forward_batch_dev(
         ctx.handle, tables.handle, obs.handle, B, L, _dev_ptr(p, f64, B * L, "p"),
         _dev_ptr(T, f64, B * L, "T"), _dev_ptr(x, f64, B * tables.n_species, "x"),
-        _dev_ptr(log_g, f64, B, "log_g"), _dev_ptr(scale, f64, B, "scale"), int(n_mu),
+        _dev_ptr(log_g, f64, B, "log_g"), _dev_ptr(scale, f64, B, "scale"), cp, int(n_mu),
         _dev_ptr(bins, real, B * obs.n_bins, "bins"), fp, sp, _stream(stream)))
+
+
+def loglike_batch(ctx: Context, tables: Tables, obs: Obs, cols: Sequence, n_mu: int, lnl,
+                  log10_eps=None, bins=None, stream=None):
+    """ln L per set (Eq. 19, or Eq. 22-23 with log10_eps) into device float64 lnl[B]."""
+    import torch
+    cc = _Columns(cols)
+    B = len(cols)
+    eps = None
+    if log10_eps is not None:
+        eps = _f64(log10_eps)
+        if eps.shape != (B,):
+            raise ValueError("log10_eps needs one value per set")
+    bp = None if bins is None else _dev_ptr(bins, tables.real, B * obs.n_bins, "bins")
+    _check(load().hr2_loglike_batch(ctx.handle, tables.handle, obs.handle, B, cc.arr, int(n_mu),
+                                    None if eps is None else _ptr(eps),
+                                    _dev_ptr(lnl, torch.float64, B, "lnl"), bp, _stream(stream)))
+
+
+def loglike_batch_dev(ctx: Context, tables: Tables, obs: Obs, p, T, x, log_g, scale, n_mu: int,
+                      lnl, log10_eps=None, bins=None, status=None, stream=None, cloud=None):
+    """Device-resident float64 columns (as forward_batch_dev); log10_eps a device [B] or None."""
+    import torch
+    B, L = p.shape
+    f64 = torch.float64
+    ep = None if log10_eps is None else _dev_ptr(log10_eps, f64, B, "log10_eps")
+    bp = None if bins is None else _dev_ptr(bins, tables.real, B * obs.n_bins, "bins")
+    sp = None if status is None else _dev_ptr(status, torch.int32, B, "status")
+    cp = None if cloud is None else _dev_ptr(cloud, f64, 3 * B, "cloud")
+    _check(load().hr2_loglike_batch_dev(
+        ctx.handle, tables.handle, obs.handle, B, L, _dev_ptr(p, f64, B * L, "p"),
+        _dev_ptr(T, f64, B * L, "T"), _dev_ptr(x, f64, B * tables.n_species, "x"),
+        _dev_ptr(log_g, f64, B, "log_g"), _dev_ptr(scale, f64, B, "scale"), cp, ep, int(n_mu),
+        _dev_ptr(lnl, f64, B, "lnl"), bp, sp, _stream(stream)))
+
+
+class Params:
+    """Parameter-vector layout (finite-element temperature, free chemistry,
+    Eq. 9 scale): duck-typed `layout` with the fields of hr2_param_layout."""
+
+    def __init__(self, ctx: Context, tables: Tables, layout):
+        self.ctx, self.tables = ctx, tables
+        self._src = np.ascontiguousarray(layout.species_src, dtype=np.int32)
+        self._fac = _f64(layout.species_factor)
+        if self._src.shape != (tables.n_species,) or self._fac.shape != (tables.n_species,):
+            raise ValueError("species_src and species_factor need one entry per table species")
+        c = ParamLayoutC(int(layout.n_elements), int(layout.order), int(layout.n_levels),
+                         float(layout.log10_p_bottom), float(layout.log10_p_top),
+                         float(layout.radius_cm), int(layout.n_free),
+                         int(bool(getattr(layout, "with_cloud", False))), int(bool(layout.with_eps)),
+                         self._src.ctypes.data_as(POINTER(c_int)), _ptr(self._fac))
+        h = c_void_p()
+        _check(load().hr2_params_create(ctx.handle, tables.handle, ctypes.byref(c),
+                                        ctypes.byref(h)))
+        self.handle = h
+        self.n_theta = load().hr2_params_n_theta(h)
+        self.n_levels = int(layout.n_levels)
+
+    def unpack(self, theta, p, T, x, log_g, scale, log10_eps=None, stream=None, cloud=None):
+        import torch
+        f64 = torch.float64
+        B = theta.shape[0]
+        L, S = self.n_levels, self.tables.n_species
+        _check(load().hr2_params_unpack_dev(
+            self.ctx.handle, self.handle, B, _dev_ptr(theta, f64, B * self.n_theta, "theta"),
+            _dev_ptr(p, f64, B * L, "p"), _dev_ptr(T, f64, B * L, "T"),
+            _dev_ptr(x, f64, B * S, "x"), _dev_ptr(log_g, f64, B, "log_g"),
+            _dev_ptr(scale, f64, B, "scale"),
+            None if cloud is None else _dev_ptr(cloud, f64, 3 * B, "cloud"),
+            None if log10_eps is None else _dev_ptr(log10_eps, f64, B, "log10_eps"),
+            _stream(stream)))
+
+    def close(self):
+        if self.handle:
+            load().hr2_params_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def forward_params_dev(ctx: Context, tables: Tables, obs: Obs, params: Params, theta, n_mu: int,
+                       bins=None, lnl=None, status=None, stream=None):
+    """Device parameter vectors theta[B][n_theta] (float64) -> bins and/or ln L."""
+    import torch
+    B = theta.shape[0]
+    f64 = torch.float64
+    bp = None if bins is None else _dev_ptr(bins, tables.real, B * obs.n_bins, "bins")
+    lp = None if lnl is None else _dev_ptr(lnl, f64, B, "lnl")
+    sp = None if status is None else _dev_ptr(status, torch.int32, B, "status")
+    _check(load().hr2_forward_params_dev(
+        ctx.handle, tables.handle, obs.handle, params.handle, B,
+        _dev_ptr(theta, f64, B * params.n_theta, "theta"), int(n_mu), bp, lp, sp,
+        _stream(stream)))
 
 
 class Server:

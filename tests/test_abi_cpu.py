@@ -50,6 +50,16 @@ def test_null_arguments_without_a_device():
     assert lib.hr2_ctx_set_option(None, 0, 0) == hr2.E_INVALID_ARG
     ms = (ctypes.c_double * 3)()
     assert lib.hr2_ctx_collect_timing(None, ms, None) == hr2.E_INVALID_ARG
+    assert lib.hr2_obs_set_data(None, None, None) == hr2.E_INVALID_ARG
+    assert lib.hr2_loglike_batch(None, None, None, 1, None, 3, None, None, None,
+                                 None) == hr2.E_INVALID_ARG
+    assert lib.hr2_loglike_batch_dev(None, None, None, 1, 2, None, None, None, None, None, None,
+                                     None, 3, None, None, None, None) == hr2.E_INVALID_ARG
+    assert lib.hr2_params_create(None, None, None, None) == hr2.E_INVALID_ARG
+    assert lib.hr2_params_n_theta(None) == 0
+    lib.hr2_params_destroy(None)
+    assert lib.hr2_forward_params_dev(None, None, None, None, 1, None, 3, None, None, None,
+                                      None) == hr2.E_INVALID_ARG
 
 
 def test_context_without_a_device_reports_device_error():
@@ -75,9 +85,10 @@ def test_binding_fails_loudly_without_the_library(monkeypatch, tmp_path):
 def test_struct_layouts_match_the_header():
     # sizes of the by-value / pointed-to structs on x86-64
     assert ctypes.sizeof(hr2.WindowC) == 24
-    assert ctypes.sizeof(hr2.ColumnC) == 48
+    assert ctypes.sizeof(hr2.ColumnC) == 72
     assert ctypes.sizeof(hr2.TablesDesc) == 104
     assert ctypes.sizeof(hr2.ServeStats) == 48
+    assert ctypes.sizeof(hr2.ParamLayoutC) == 72
 
 
 def test_serving_trace_inputs_are_valid():

@@ -108,7 +108,7 @@ def test_unpack_scale_mixing_ratios_and_levels():
     lay = wl.c2_param_layout(3, 2, with_eps=True)
     th = wl.draw_theta(lay, 1, seed=4)[0]
     th[1], th[2] = 2.0, 10.0                      # f = 2, d = 10 pc
-    p, T, x, lg, scale, eps = op.unpack(lay, th)
+    p, T, x, lg, scale, cloud, eps = op.unpack(lay, th)
     # f (R_J / 10 pc)^2 by hand: 7.1492e9 / 3.0856775814913673e19 = 2.31690...e-10
     assert abs(scale - 2.0 * (7.1492e9 / 3.0856775814913673e19) ** 2) < 1e-28
     assert abs(scale / 1.0736e-19 - 1.0) < 1e-3

@@ -19,7 +19,7 @@ import ctypes
 import os
 import subprocess
 from dataclasses import dataclass, field
-from typing import List, Optional
+from typing import List, Optional, Tuple
 
 import numpy as np
 
@@ -108,6 +108,7 @@ class Column:
     x: np.ndarray        # [S]
     log_g: float
     scale: float
+    cloud: Optional[Tuple[float, float, float]] = None   # (tau_c, p_top_bar, bottom_frac)
 
     @property
     def n_levels(self) -> int:
@@ -450,10 +451,10 @@ def c5_trace_packed(table: Table, rate_hz=2000.0, duration_s=10.0, seed=505, max
 
 
 def noisy_data(model_bins, seed, noise_frac=0.2):
-    """Synthetic observation of a model spectrum: one error bar for every bin,
-    sigma = noise_frac x the median |model|, and D = model + sigma x N(0, 1)
-    (the recipe of the paper's synthetic retrieval tests: 20% of the median
-    flux).  Returns (D, sigma)."""
+    """Synthetic observation of a model spectrum: D = model + sigma x N(0, 1)
+    with sigma = noise_frac x the median |model| (the noise of the paper's
+    synthetic retrieval tests, Sect. 4.1), and the same sigma as every bin's
+    error bar.  Returns (D, sigma)."""
     m = np.asarray(model_bins, dtype=np.float64)
     rng = np.random.default_rng(seed)
     sigma = np.full(m.shape, noise_frac * float(np.median(np.abs(m))))
@@ -480,6 +481,7 @@ class ParamLayout:
     with_eps: bool
     species_src: np.ndarray      # int32 [n_species]
     species_factor: np.ndarray   # float64 [n_species]
+    with_cloud: bool = False     # theta carries (tau_c, p_top_bar, bottom_frac)
 
 
 # solar Na/K number ratio from the photospheric abundances log eps(Na) = 6.24
@@ -503,7 +505,7 @@ def c1_param_layout(n_elements=2, order=2, with_eps=False, n_levels=20):
 
 
 def draw_theta(layout: ParamLayout, n_sets, seed, log10_eps_range=(-30.0, -28.0)):
-    """Parameter vectors [log g, f, d_pc, T1, b_1..b_{N_T-1}, x_free..., (log10 eps)]
+    """Parameter vectors [log g, f, d_pc, T1, b_1..b_{N_T-1}, x_free..., (cloud), (log10 eps)]
     from boxes inside the paper's priors (b kept in 0.6-0.95 and x in
     1e-8-1e-2 so that the temperatures stay on typical table grids and the
     filler gas stays positive)."""
@@ -515,6 +517,10 @@ def draw_theta(layout: ParamLayout, n_sets, seed, log10_eps_range=(-30.0, -28.0)
               rng.uniform(1000.0, 3000.0)]
         th += list(rng.uniform(0.6, 0.95, NT - 1))
         th += list(log_uniform(rng, 1e-8, 1e-2, layout.n_free))
+        if layout.with_cloud:
+            # log-uniform draws (App. B states the priors' kind, not their ranges)
+            th += [log_uniform(rng, 1e-2, 1e2), log_uniform(rng, 1e-3, 10.0),
+                   log_uniform(rng, 1.5, 10.0)]
         if layout.with_eps:
             th.append(rng.uniform(*log10_eps_range))
         rows.append(th)
