@@ -113,10 +113,11 @@ def main():
     ap.add_argument("--cpu-budget-s", type=float, default=20.0)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy 5 times (counter scale)")
-    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4", "c5"],
+    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4", "c5", "params"],
                     help="c2 (default): one realistic spectrum per step; c3: 512-set C1 batch "
                          "as a HIP graph vs 512 sequential calls; c4: reduced-precision "
-                         "batches; c5: Poisson serving trace")
+                         "batches; c5: Poisson serving trace; params: parameter vectors "
+                         "to ln L")
     ap.add_argument("--rate", type=float, default=2000.0, help="c5 arrival rate, requests/s")
     ap.add_argument("--duration", type=float, default=10.0, help="c5 trace length, s")
     args = ap.parse_args()
@@ -144,6 +145,8 @@ def main():
         return run_c4(args)
     if args.workload == "c5":
         return run_c5(args)
+    if args.workload == "params":
+        return run_params(args)
     log("generating tables")
     t0 = time.perf_counter()
     tab = wl.c2_table(n_nu=args.n_nu)
@@ -319,9 +322,9 @@ def run_c3(args):
 
 def run_c4(args):
     """C2 columns in batches of 1, 64 and 512 with FP32, FP16 and BF16 tables,
-    and the per-spectrum error of the first sets against the FP64 oracle."""
+    and the per-spectrum error of the first sets against the library's FP64
+    tables (whose parity with the FP64 oracle is the test suite's job)."""
     import torch
-    import oracle
     import workloads as wl
     from paper_1910_01070_amd import hr2
     tab = wl.c2_table(n_nu=args.n_nu)
@@ -330,9 +333,15 @@ def run_c4(args):
     rows = []
     n_err = 4
     err_cols = wl.c4_columns(n_err)
-    log("oracle on the error sample")
-    refs = [oracle.forward(tab, c, spec.window, spec.resolving_power, spec.edges_cm, 3)["bins"]
-            for c in err_cols]
+    log("FP64-table reference of the error sample")
+    T64 = hr2.Tables(ctx, tab, "f64")
+    obs64 = hr2.Obs(ctx, T64, spec.window, spec.resolving_power, spec.edges_cm)
+    ref = torch.empty(n_err * obs64.n_bins, dtype=torch.float64, device="cuda")
+    hr2.forward_batch(ctx, T64, obs64, err_cols, 3, ref)
+    torch.cuda.synchronize()
+    refs = ref.cpu().numpy().reshape(n_err, obs64.n_bins)
+    obs64.close()
+    T64.close()
     errors = {}
     for dt in ("f32", "f16", "bf16"):
         T = hr2.Tables(ctx, tab, dt)
@@ -365,7 +374,57 @@ def run_c4(args):
         obs.close()
         T.close()
     print(json.dumps({"workload": "C4 reduced precision (C2 columns, batches)", "rows": rows,
-                      "per_spectrum_max_rel_err_vs_fp64_oracle": errors}))
+                      "per_spectrum_max_rel_err_vs_fp64_tables": errors}))
+
+
+def run_params(args):
+    """Parameter vectors to ln L: the paper's free-chemistry retrieval set-up
+    (three second-order elements, seven free mixing ratios, error inflation:
+    18 parameters) on the C2 table, batches of 1, 64 and 512 vectors per call
+    (hr2_forward_params_dev with ln L only: one double per set comes back)."""
+    import torch
+    import workloads as wl
+    from paper_1910_01070_amd import hr2
+    tab = wl.c2_table(n_nu=args.n_nu)
+    spec = wl.c2_obs(tab)
+    lay = wl.c2_param_layout(3, 2, with_eps=True)
+    ctx = hr2.Context(0)
+    T = hr2.Tables(ctx, tab, args.dtype)
+    obs = hr2.Obs(ctx, T, spec.window, spec.resolving_power, spec.edges_cm)
+    P = hr2.Params(ctx, T, lay)
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+    # observed data: the model of one vector plus 20%-of-median noise (only
+    # the shape of the data matters for timing)
+    th0 = wl.draw_theta(lay, 1, seed=7)
+    b0 = torch.empty(obs.n_bins, dtype=torch.float32, device="cuda")
+    hr2.forward_params_dev(ctx, T, obs, P, dev(th0), 3, b0)
+    torch.cuda.synchronize()
+    D, sigma = wl.noisy_data(b0.cpu().numpy().astype(np.float64), seed=8)
+    obs.set_data(D, sigma)
+    rows = []
+    L = lay.n_levels
+    for B in (1, 64, 512):
+        th = wl.draw_theta(lay, B, seed=100 + B)
+        th[:, -1] = np.log10(float(sigma[0]) ** 2)
+        thd = dev(th)
+        lnl = torch.empty(B, dtype=torch.float64, device="cuda")
+        steps = max(5, min(args.steps, 4000 // B))
+        for _ in range(3):
+            hr2.forward_params_dev(ctx, T, obs, P, thd, 3, None, lnl)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            hr2.forward_params_dev(ctx, T, obs, P, thd, 3, None, lnl)
+        torch.cuda.synchronize()
+        dt_s = (time.perf_counter() - t0) / steps
+        rows.append({"batch": B, "ms_per_call": dt_s * 1e3, "likelihoods_per_s": B / dt_s,
+                     "layer_nu_per_s": B * (L - 1) * spec.window.count / dt_s,
+                     "finite": int(torch.isfinite(lnl).sum())})
+        log(rows[-1])
+    print(json.dumps({"workload": "parameter vectors -> ln L: 18-parameter free-chemistry "
+                                  "set-up (3 second-order elements, 7 free ratios, eps) on the "
+                                  "C2 table, 101 levels, 400 bins",
+                      "table_storage": args.dtype, "rows": rows}))
 
 
 def run_c5(args):

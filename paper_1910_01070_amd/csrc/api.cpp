@@ -546,11 +546,12 @@ ColumnsView columns_view(const void *dev, int n_sets, int L, int S) {
   return v;
 }
 
-// Layer chunks per 64-point tile.  A launch of W = B * tiles * C waves
-// runs in ceil(W / capacity) rounds of resident waves, each wave sweeping
-// about (L - 1)/C layers plus one shared boundary level; pick the C with the
-// fewest wave-level steps on the critical path (small penalty per chunk for
-// the combine).  Depends on the request and the device only.
+// Layer chunks per 64-point tile.  A launch of W = B * tiles * C waves, each
+// sweeping about (L - 1)/C layers plus one shared boundary level, takes at
+// least the wave-level steps of one wave (the critical path) and at least
+// W * steps / capacity (the resident-wave throughput); pick the C with the
+// smaller of the two maxima (small penalty per chunk for the combine).
+// Depends on the request and the device only.
 int auto_chunks(const TableView &tv, int64_t base_waves, int n_levels, int n_mu,
                 bool from_chi) {
   // capacities depend on the kernel variant and the device only: cache them
@@ -572,9 +573,9 @@ int auto_chunks(const TableView &tv, int64_t base_waves, int n_levels, int n_mu,
   double best_cost = 1e300;
   for (int c = 1; c <= 8 && c <= n_levels - 1; ++c) {
     const int64_t cap = std::max(1, capacity(c));
-    const int64_t rounds = (base_waves * c + cap - 1) / cap;
     const double per_wave = (double)((n_levels - 1 + c - 1) / c + 1);
-    const double cost = (double)rounds * per_wave * (1.0 + 0.02 * c);
+    const double through = (double)base_waves * c * per_wave / (double)cap;
+    const double cost = std::max(through, per_wave) * (1.0 + 0.02 * c);
     if (cost < best_cost * 0.999) {
       best_cost = cost;
       best = c;

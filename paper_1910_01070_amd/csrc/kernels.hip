@@ -136,8 +136,10 @@ __device__ __forceinline__ void locate_lds(const double *a, int n, double v, int
   w = (v - a[lo]) / (a[lo + 1] - a[lo]);
 }
 
+constexpr int kLevelThreads = 1024;   // one pass over the (level, species) products of C2
+
 template <typename Real>
-__global__ __launch_bounds__(256) void k_levels(TableView tv, ColumnsView cv,
+__global__ __launch_bounds__(kLevelThreads) void k_levels(TableView tv, ColumnsView cv,
                                                 typename RecOf<Real>::type *recs, int *status) {
   using Rec = typename RecOf<Real>::type;
   __shared__ double s_T[kMaxAxis], s_lp[kMaxAxis];
@@ -190,7 +192,7 @@ __global__ __launch_bounds__(256) void k_levels(TableView tv, ColumnsView cv,
   const double h2 = (1.0 - xs) / (1.0 + tv.he_ratio);
   const double he = tv.he_ratio * h2;
   mm += h2 * kMH2 + he * kMHe;
-  const double g = pow(10.0, cv.logg[s]);
+  const double g = exp10(cv.logg[s]);
   const int64_t rows_per_species = (int64_t)tv.nT * tv.nP;
   const uint32_t row_bytes = (uint32_t)(tv.pitch * tv.tab_elem);
   const uint32_t cia_row_bytes = (uint32_t)(tv.pitch * tv.cia_elem);
@@ -297,10 +299,10 @@ hipError_t launch_levels(const TableView &tv, const ColumnsView &cv, void *recs,
                          bool fp64, hipStream_t stream) {
   const dim3 grid((unsigned)cv.B);
   if (fp64)
-    hipLaunchKernelGGL(k_levels<double>, grid, dim3(256), 0, stream, tv, cv,
+    hipLaunchKernelGGL(k_levels<double>, grid, dim3(kLevelThreads), 0, stream, tv, cv,
                        (LevelRecD *)recs, status);
   else
-    hipLaunchKernelGGL(k_levels<float>, grid, dim3(256), 0, stream, tv, cv,
+    hipLaunchKernelGGL(k_levels<float>, grid, dim3(kLevelThreads), 0, stream, tv, cv,
                        (LevelRecF *)recs, status);
   return hipGetLastError();
 }
@@ -310,13 +312,14 @@ hipError_t launch_levels(const TableView &tv, const ColumnsView &cv, void *recs,
 // Planck source, Eq. 2 (wavenumber form), FP32: x = c2 nu / T is formed as
 // an unevaluated float sum (pl_hi + pl_lo)(nu_hi + nu_lo) in log2 units so
 // that exp stays accurate for large x; expm1 by its series below x = 1/2.
+// Above, B = c1 nu^3 g / (1 - g) with g = e^{-x} <= e^{-1/2}: no overflow for
+// any x (g underflows to 0, and B with it, once x passes ~87).
 __device__ __forceinline__ float planck_f(float nu_hi, float nu_lo, float c1nu3, float pl_hi,
                                           float pl_lo) {
   const float p_hi = pl_hi * nu_hi;
   const float p_err = fmaf(pl_hi, nu_hi, -p_hi);
   const float p_lo = fmaf(pl_hi, nu_lo, fmaf(pl_lo, nu_hi, p_err));
   const float xl2 = p_hi + p_lo;
-  float em;
   if (xl2 < 0.72134752044448170f) {   // x < 1/2
     const float x = xl2 * kLn2f;
     float t = 1.0f / 40320.0f;
@@ -327,12 +330,10 @@ __device__ __forceinline__ float planck_f(float nu_hi, float nu_lo, float c1nu3,
     t = fmaf(t, x, 1.0f / 6.0f);
     t = fmaf(t, x, 0.5f);
     t = fmaf(t, x, 1.0f);
-    em = t * x;
-  } else {
-    const float e = fexp2(p_hi);
-    em = fmaf(e, p_lo * kLn2f, e) - 1.0f;
+    return c1nu3 * frcp(t * x);
   }
-  return c1nu3 * frcp(em);
+  const float g = fexp2(-p_hi) * fmaf(-p_lo, kLn2f, 1.0f);
+  return c1nu3 * g * frcp(1.0f - g);
 }
 
 __device__ __forceinline__ double planck_d(double nu, double c1nu3, double T) {
@@ -408,9 +409,14 @@ __global__ __launch_bounds__(512) void k_column(TableView tv, const ColSeg *__re
   Real *sh = (Real *)sh_raw;
 
   const int64_t g = xcd_remap(blockIdx.x, total_wgs);
+  // the segment holding workgroup g: last one with wg_begin <= g (ascending)
   int sg = 0;
-  for (int i = 1; i < n_segs; ++i)
-    if (segs[i].wg_begin <= g) sg = i;
+  for (int lo = 0, hi = n_segs; hi - lo > 1;) {
+    const int mid = (lo + hi) >> 1;
+    if (segs[mid].wg_begin <= g) lo = mid;
+    else hi = mid;
+    sg = lo;
+  }
   const ColSeg &d = segs[sg];
   const int n_sets = d.n_sets;
   const int C = blockDim.x >> 6;   // one wave per layer chunk (the segment's chunks)
@@ -795,8 +801,12 @@ __global__ __launch_bounds__(256) void k_convolve_bin(const ConvSeg *__restrict_
   __shared__ Real part[4];
   const int64_t it = blockIdx.x;
   int sg = 0;
-  for (int i = 1; i < n_segs; ++i)
-    if (segs[i].item_begin <= it) sg = i;
+  for (int lo = 0, hi = n_segs; hi - lo > 1;) {
+    const int mid = (lo + hi) >> 1;
+    if (segs[mid].item_begin <= it) lo = mid;
+    else hi = mid;
+    sg = lo;
+  }
   const ConvSeg &d = segs[sg];
   const int64_t local = it - d.item_begin;
   const int s = (int)(local / d.n_bins);
@@ -804,8 +814,22 @@ __global__ __launch_bounds__(256) void k_convolve_bin(const ConvSeg *__restrict_
   const Real *K = (const Real *)d.K + d.kstart[jb];
   const int len = d.mlen[jb];
   const Real *F = in + d.in_offset + (int64_t)s * d.in_stride + d.mlo[jb];
-  Real acc = (Real)0;
-  for (int q = threadIdx.x; q < len; q += 256) acc += K[q] * F[q];
+  // four independent partial sums, so that each thread's loads of a round
+  // are in flight together
+  Real a0 = (Real)0, a1 = (Real)0, a2 = (Real)0, a3 = (Real)0;
+  int q = threadIdx.x;
+  for (; q + 768 < len; q += 1024) {
+    const Real k0 = K[q], k1 = K[q + 256], k2 = K[q + 512], k3 = K[q + 768];
+    const Real f0 = F[q], f1 = F[q + 256], f2 = F[q + 512], f3 = F[q + 768];
+    a0 += k0 * f0;
+    a1 += k1 * f1;
+    a2 += k2 * f2;
+    a3 += k3 * f3;
+  }
+  if (q < len) a0 += K[q] * F[q];
+  if (q + 256 < len) a1 += K[q + 256] * F[q + 256];
+  if (q + 512 < len) a2 += K[q + 512] * F[q + 512];
+  Real acc = (a0 + a1) + (a2 + a3);
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
   const int wave = threadIdx.x >> 6;

@@ -168,6 +168,21 @@ def test_c2_params_lnl(ctx):
         say(f"  set {s}: bins {e:.2e}, ln L {got:.8e} vs {want:.8e}")
         assert e <= 1e-5
         assert abs(got - want) <= lnl_bound(refs[s], D, sigma, 1e-5, th[s, -1])
+    say("64 vectors from the prior boxes: every ln L finite; the coldest against the oracle")
+    thb = wl.draw_theta(lay, 64, seed=164)
+    thb[:, -1] = th[0, -1]
+    lnl = torch.empty(64, dtype=torch.float64, device="cuda")
+    hr2.forward_params_dev(ctx, T, obs, P, dev(thb), 3, None, lnl)
+    torch.cuda.synchronize()
+    ll = lnl.cpu().numpy()
+    assert np.all(np.isfinite(ll))
+    t_top = [op.unpack(lay, t)[1][-1] for t in thb]
+    s = int(np.argmin(t_top))
+    col, _ = oracle_column(lay, thb[s])
+    ref = oracle.forward(tab, col, spec.window, spec.resolving_power, spec.edges_cm, 3)["bins"]
+    want = oracle.log_likelihood(ref, D, sigma, thb[s, -1])
+    say(f"  coldest top {t_top[s]:.0f} K: ln L {ll[s]:.8e} vs {want:.8e}")
+    assert abs(ll[s] - want) <= lnl_bound(ref, D, sigma, 1e-5, thb[s, -1])
     P.close()
     obs.close()
     T.close()

@@ -156,6 +156,30 @@ def test_isothermal_and_transparent_limits(ctx):
         assert e <= 1e-5
 
 
+@pytest.mark.parametrize("dtype,tol", [("f64", 1e-12), ("f32", 1e-5)])
+def test_cold_upper_levels(ctx, dtype, tol):
+    """Levels far below the table's T axis (down to 25 K): c2 nu / T reaches
+    ~350 at 6000 cm^-1, beyond the FP32 exponent range, and the Planck
+    function of those levels must come out 0-ish, never inf or NaN."""
+    tab = tu.c1_table()
+    spec = wl.c1_obs(tab)
+    p = wl.levels(21, 2.0, -4.0)
+    cols = [wl.Column(p, wl.linear_logp_profile(p, Tb, Tt), np.array([1e-3]), 4.75,
+                      wl.scale_factor(1.0)) for Tb, Tt in ((1400.0, 25.0), (900.0, 60.0))]
+    T = hr2.Tables(ctx, tab, dtype)
+    obs = hr2.Obs(ctx, T, spec.window, spec.resolving_power, spec.edges_cm)
+    bins, fplus = run_forward(ctx, T, obs, cols)
+    assert np.all(np.isfinite(bins)) and np.all(np.isfinite(fplus))
+    for s, col in enumerate(cols):
+        ref = oracle.forward(tab, col, spec.window, spec.resolving_power, spec.edges_cm, 3)
+        e_f, _ = tu.max_rel_err(fplus[s], ref["fplus"])
+        e_b, _ = tu.max_rel_err(bins[s], ref["bins"])
+        say(f"  cold set {s} {dtype}: F+ {e_f:.2e} bins {e_b:.2e}")
+        assert e_f <= tol and e_b <= tol
+    obs.close()
+    T.close()
+
+
 def test_batch_independence_and_device_entry(ctx):
     """P15: a set's result does not depend on the other sets of the launch
     (bit-identical), and the device-column entry equals the host entry."""
