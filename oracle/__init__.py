@@ -69,6 +69,14 @@ def lib():
         L.or_rt_emission_x.restype = None
         L.or_cloud_dtau.argtypes = [_I, _DP, _D, _D, _D, _DP]
         L.or_cloud_dtau.restype = None
+        L.or_rt_emission_o.argtypes = [_I, _I64, _DP, _DP, _DP, _DP, _I, _DP, _I, _DP]
+        L.or_rt_emission_o.restype = None
+        L.or_sc_para_coeffs.argtypes = [_D, _D, _DP, _DP, _DP]
+        L.or_sc_para_coeffs.restype = None
+        L.or_sc_intensity_para.argtypes = [_I, _DP, _DP, _D]
+        L.or_sc_intensity_para.restype = _D
+        L.or_sc_flux_o.argtypes = [_I, _DP, _DP, _I, _I]
+        L.or_sc_flux_o.restype = _D
         for name in ("or_convolve", "or_convolve_banded"):
             fn = getattr(L, name)
             fn.argtypes = [_I64, _D, _D, _DP, _D, _I64, _I64P, _DP]
@@ -156,9 +164,22 @@ def sc_intensity(dtau, S, mu):
     return lib().or_sc_intensity(len(S), _p(dtau), _p(S), float(mu))
 
 
-def sc_flux(dtau, S, n_mu):
+def sc_flux(dtau, S, n_mu, order=1):
     dtau, S = _f64(dtau), _f64(S)
-    return lib().or_sc_flux(len(S), _p(dtau), _p(S), int(n_mu))
+    return lib().or_sc_flux_o(len(S), _p(dtau), _p(S), int(n_mu), int(order))
+
+
+def sc_para_coeffs(du, dd):
+    """(alpha, beta, gamma) of the parabolic step for path lengths du, dd."""
+    a, b, g = _D(), _D(), _D()
+    lib().or_sc_para_coeffs(float(du), float(dd), ctypes.byref(a), ctypes.byref(b),
+                            ctypes.byref(g))
+    return a.value, b.value, g.value
+
+
+def sc_intensity_para(dtau, S, mu):
+    dtau, S = _f64(dtau), _f64(S)
+    return lib().or_sc_intensity_para(len(S), _p(dtau), _p(S), float(mu))
 
 
 def cloud_dtau(p_bar, cloud):
@@ -170,16 +191,18 @@ def cloud_dtau(p_bar, cloud):
     return out[:len(p) - 1]
 
 
-def rt_emission(chi, dz, T_K, nu, n_mu, dtau_extra=None):
+def rt_emission(chi, dz, T_K, nu, n_mu, dtau_extra=None, order=1):
+    """F+ (Eq. 2-8); order 1: linear source, order 2: parabolic source."""
     chi = _f64(chi)
     L, n = chi.shape
     out = np.empty(n)
-    if dtau_extra is None:
+    if dtau_extra is None and order == 1:
         lib().or_rt_emission(L, n, _p(chi), _p(_f64(dz)), _p(_f64(T_K)), _p(_f64(nu)), int(n_mu),
                              _p(out))
     else:
-        lib().or_rt_emission_x(L, n, _p(chi), _p(_f64(dz)), _p(_f64(T_K)), _p(_f64(nu)),
-                               int(n_mu), _p(_f64(dtau_extra)), _p(out))
+        ex = None if dtau_extra is None else _f64(dtau_extra)
+        lib().or_rt_emission_o(L, n, _p(chi), _p(_f64(dz)), _p(_f64(T_K)), _p(_f64(nu)),
+                               int(n_mu), None if ex is None else _p(ex), int(order), _p(out))
     return out
 
 
@@ -225,7 +248,7 @@ def window_grid(table, window):
     return nu_first, dnu_eff
 
 
-def fplus(table, col, window, n_mu, sub=None):
+def fplus(table, col, window, n_mu, sub=None, order=1):
     """F+ at window points ``sub`` (all when None): opacity then RT."""
     idx_w = np.arange(window.count, dtype=np.int64) if sub is None else _i64(sub)
     tab_idx = window.begin + window.stride * idx_w
@@ -234,13 +257,13 @@ def fplus(table, col, window, n_mu, sub=None):
     nu = table.nu0_cm + tab_idx * table.dnu_cm
     cloud = getattr(col, "cloud", None)
     extra = None if cloud is None else cloud_dtau(col.p_bar, cloud)
-    return rt_emission(chi, st["dz"], col.T_K, nu, n_mu, extra)
+    return rt_emission(chi, st["dz"], col.T_K, nu, n_mu, extra, order)
 
 
-def forward(table, col, window, R, edges_cm, n_mu):
+def forward(table, col, window, R, edges_cm, n_mu, order=1):
     """Whole chain on the full window: dict with fplus, fd and bins."""
     nu_first, dnu_eff = window_grid(table, window)
-    fp = fplus(table, col, window, n_mu)
+    fp = fplus(table, col, window, n_mu, order=order)
     edge_idx = snap_edges(edges_cm, nu_first, dnu_eff, window.count)
     a, b = int(edge_idx[0]), int(edge_idx[-1])
     fd = np.full(window.count, np.nan)
@@ -258,7 +281,7 @@ def half_width(nu_first, dnu_eff, R, i):
     return h
 
 
-def forward_bins_subset(table, col, window, R, edges_cm, n_mu, bin_ids):
+def forward_bins_subset(table, col, window, R, edges_cm, n_mu, bin_ids, order=1):
     """Selected bins only: F+ on each bin's support, convolution on the bin's points."""
     nu_first, dnu_eff = window_grid(table, window)
     edge_idx = snap_edges(edges_cm, nu_first, dnu_eff, window.count)
@@ -268,7 +291,7 @@ def forward_bins_subset(table, col, window, R, edges_cm, n_mu, bin_ids):
         lo = max(0, a - half_width(nu_first, dnu_eff, R, a) - 1)
         hi = min(window.count - 1, b + half_width(nu_first, dnu_eff, R, b) + 1)
         sub = np.arange(lo, hi + 1, dtype=np.int64)
-        fp_sub = fplus(table, col, window, n_mu, sub)
+        fp_sub = fplus(table, col, window, n_mu, sub, order)
         fp_full = np.zeros(window.count)
         fp_full[lo:hi + 1] = fp_sub
         fd = np.zeros(window.count)

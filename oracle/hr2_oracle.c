@@ -206,14 +206,67 @@ double or_sc_intensity(int L, const double *dtau, const double *S, double mu) {
   return I;
 }
 
-/* Eq. 8 with the n_mu-point rule: F+ = 2 pi sum_k w_k mu_k I(mu_k). */
-double or_sc_flux(int L, const double *dtau, const double *S, int n_mu) {
+/* ------------------------------------------------------------------------
+ * Parabolic short characteristics (the higher-order interpolant the paper
+ * mentions with Eq. 4-7, coefficients after Olson & Kunasz 1987): on the
+ * step from level i-1 (upwind) to level i the source is the quadratic
+ * through S_{i-1}, S_i and S_{i+1} (the downwind level).  With optical
+ * path lengths du (layer i-1 -> i) and dd (layer i -> i+1) along the ray and
+ * x the optical distance back from level i, S(0) = S_i, S(du) = S_{i-1},
+ * S(-dd) = S_{i+1}, and
+ *   Delta I_i = int_0^du S(x) e^{-x} dx = alpha S_{i+1} + beta S_i + gamma S_{i-1}
+ * with the moments w_n = int_0^du x^n e^{-x} dx:
+ *   w0 = 1 - e^{-du},  w1 = w0 - du e^{-du},  w2 = 2 w1 - du^2 e^{-du},
+ *   gamma = (w2 + dd w1) / (du (du + dd)),
+ *   beta  = (du dd w0 - w2 - (dd - du) w1) / (du dd),
+ *   alpha = (w2 - du w1) / (dd (du + dd)).
+ * Readings (the paper gives no formulas): the top step, which has no
+ * downwind level, and a step whose downwind layer has zero optical depth
+ * use the linear coefficients (alpha = 0); a step with du = 0 adds nothing.
+ * ---------------------------------------------------------------------- */
+void or_sc_para_coeffs(double du, double dd, double *alpha, double *beta, double *gamma) {
+  const double e = exp(-du);
+  const double w0 = -expm1(-du);
+  const double w1 = w0 - du * e;
+  const double w2 = 2.0 * w1 - du * du * e;
+  *gamma = (w2 + dd * w1) / (du * (du + dd));
+  *beta = (du * dd * w0 - w2 - (dd - du) * w1) / (du * dd);
+  *alpha = (w2 - du * w1) / (dd * (du + dd));
+}
+
+double or_sc_intensity_para(int L, const double *dtau, const double *S, double mu) {
+  double I = S[0];
+  for (int l = 0; l + 1 < L; ++l) {
+    const double du = dtau[l] / mu;
+    if (du == 0.0) continue;
+    const double e = exp(-du);
+    if (l + 2 < L && dtau[l + 1] > 0.0) {
+      double a, b, g;
+      or_sc_para_coeffs(du, dtau[l + 1] / mu, &a, &b, &g);
+      I = e * I + a * S[l + 2] + b * S[l + 1] + g * S[l];
+    } else {
+      const double u = -expm1(-du) / du;
+      I = e * I + (1.0 - u) * S[l + 1] + (u - e) * S[l];
+    }
+  }
+  return I;
+}
+
+/* Eq. 8 with the n_mu-point rule: F+ = 2 pi sum_k w_k mu_k I(mu_k); order 1
+ * is the linear source of Eq. 5-6, order 2 the parabolic one. */
+double or_sc_flux_o(int L, const double *dtau, const double *S, int n_mu, int order) {
   double mu[64], w[64];
   if (n_mu < 1 || n_mu > 64) return NAN;
   or_gauss_legendre01(n_mu, mu, w);
   double f = 0.0;
-  for (int k = 0; k < n_mu; ++k) f += w[k] * mu[k] * or_sc_intensity(L, dtau, S, mu[k]);
+  for (int k = 0; k < n_mu; ++k)
+    f += w[k] * mu[k] *
+         (order == 2 ? or_sc_intensity_para(L, dtau, S, mu[k]) : or_sc_intensity(L, dtau, S, mu[k]));
   return 2.0 * OR_PI * f;
+}
+
+double or_sc_flux(int L, const double *dtau, const double *S, int n_mu) {
+  return or_sc_flux_o(L, dtau, S, n_mu, 1);
 }
 
 /* ------------------------------------------------------------------------
@@ -240,8 +293,9 @@ void or_cloud_dtau(int L, const double *p_bar, double tau_c, double p_top_bar,
  * (+ dtau_extra[l], a gray cloud's share, when dtau_extra is not NULL),
  * S_l = B(nu, T_l), F+ per wavenumber.  chi[L][n], dz[L-1], T[L], nu[n].
  * ---------------------------------------------------------------------- */
-void or_rt_emission_x(int L, int64_t n, const double *chi, const double *dz, const double *T_K,
-                      const double *nu, int n_mu, const double *dtau_extra, double *fplus) {
+void or_rt_emission_o(int L, int64_t n, const double *chi, const double *dz, const double *T_K,
+                      const double *nu, int n_mu, const double *dtau_extra, int order,
+                      double *fplus) {
 #pragma omp parallel
   {
     double *dtau = (double *)malloc(sizeof(double) * (L > 1 ? L - 1 : 1));
@@ -253,16 +307,21 @@ void or_rt_emission_x(int L, int64_t n, const double *chi, const double *dz, con
         if (dtau_extra) dtau[l] += dtau_extra[l];
       }
       for (int l = 0; l < L; ++l) S[l] = or_planck(nu[j], T_K[l]);
-      fplus[j] = or_sc_flux(L, dtau, S, n_mu);
+      fplus[j] = or_sc_flux_o(L, dtau, S, n_mu, order);
     }
     free(dtau);
     free(S);
   }
 }
 
+void or_rt_emission_x(int L, int64_t n, const double *chi, const double *dz, const double *T_K,
+                      const double *nu, int n_mu, const double *dtau_extra, double *fplus) {
+  or_rt_emission_o(L, n, chi, dz, T_K, nu, n_mu, dtau_extra, 1, fplus);
+}
+
 void or_rt_emission(int L, int64_t n, const double *chi, const double *dz, const double *T_K,
                     const double *nu, int n_mu, double *fplus) {
-  or_rt_emission_x(L, n, chi, dz, T_K, nu, n_mu, NULL, fplus);
+  or_rt_emission_o(L, n, chi, dz, T_K, nu, n_mu, NULL, 1, fplus);
 }
 
 /* ------------------------------------------------------------------------
