@@ -224,11 +224,36 @@ double or_sc_intensity(int L, const double *dtau, const double *S, double mu) {
  * downwind level, and a step whose downwind layer has zero optical depth
  * use the linear coefficients (alpha = 0); a step with du = 0 adds nothing.
  * ---------------------------------------------------------------------- */
+/* w_n = int_0^x t^n e^{-t} dt is the lower incomplete gamma function
+ * gamma(n+1, x).  Up to x = 30 it is summed from its series of positive
+ * terms, x^{n+1} e^{-x} sum_k x^k / ((n+1)(n+2)...(n+1+k)), which keeps full
+ * relative accuracy for optically thin layers (the closed forms
+ * w1 = w0 - x e^{-x} and w2 = 2 w1 - x^2 e^{-x} cancel there); beyond, the
+ * closed form n! (1 - e^{-x} sum_{k<=n} x^k/k!) has nothing to cancel. */
+static double or_moment(int n, double x) {
+  if (x > 30.0) {
+    double sum = 0.0, t = 1.0, fact = 1.0;
+    for (int k = 0; k <= n; ++k) {
+      if (k > 0) t *= x / k;
+      sum += t;
+    }
+    for (int k = 2; k <= n; ++k) fact *= k;
+    return fact * (1.0 - exp(-x) * sum);
+  }
+  const double s = n + 1.0;
+  double term = 1.0 / s, sum = term;
+  for (int k = 1; k < 400; ++k) {
+    term *= x / (s + k);
+    sum += term;
+    if (term < 1e-18 * sum) break;
+  }
+  return pow(x, s) * exp(-x) * sum;
+}
+
 void or_sc_para_coeffs(double du, double dd, double *alpha, double *beta, double *gamma) {
-  const double e = exp(-du);
   const double w0 = -expm1(-du);
-  const double w1 = w0 - du * e;
-  const double w2 = 2.0 * w1 - du * du * e;
+  const double w1 = or_moment(1, du);
+  const double w2 = or_moment(2, du);
   *gamma = (w2 + dd * w1) / (du * (du + dd));
   *beta = (du * dd * w0 - w2 - (dd - du) * w1) / (du * dd);
   *alpha = (w2 - du * w1) / (dd * (du + dd));

@@ -12,8 +12,8 @@ from scipy import integrate
 import oracle
 
 
-@pytest.mark.parametrize("du,dd", [(1e-3, 2e-3), (0.05, 0.01), (0.3, 0.7), (1.0, 1.0),
-                                   (2.5, 0.4), (12.0, 30.0)])
+@pytest.mark.parametrize("du,dd", [(1e-9, 3e-9), (2e-6, 1e-6), (1e-3, 2e-3), (0.05, 0.01),
+                                   (0.3, 0.7), (1.0, 1.0), (2.5, 0.4), (12.0, 30.0), (45.0, 5.0)])
 def test_coefficients_integrate_quadratics(du, dd):
     a, b, g = oracle.sc_para_coeffs(du, dd)
     assert abs((a + b + g) - (-np.expm1(-du))) < 1e-14
@@ -23,7 +23,20 @@ def test_coefficients_integrate_quadratics(du, dd):
         S = lambda x: c0 + c1 * x + c2 * x * x
         want, _ = integrate.quad(lambda x: S(x) * np.exp(-x), 0.0, du, epsabs=0, epsrel=1e-13)
         got = a * S(-dd) + b * S(0.0) + g * S(du)
-        assert abs(got - want) <= 1e-12 * max(abs(want), 1e-300) + 1e-16
+        assert abs(got - want) <= 1e-12 * abs(want)
+
+
+def test_moments_of_thin_layers_match_the_incomplete_gamma_function():
+    """The coefficients rest on w_n = gamma(n+1, du); scipy's regularised
+    incomplete gamma gives them independently, down to du = 1e-12."""
+    from scipy import special
+    for du in (1e-12, 1e-8, 1e-4, 0.2, 3.0, 29.5, 30.5, 60.0):
+        dd = 0.7 * du
+        w0, w1, w2 = -np.expm1(-du), special.gammainc(2, du), 2.0 * special.gammainc(3, du)
+        a, b, g = oracle.sc_para_coeffs(du, dd)
+        assert abs(g - (w2 + dd * w1) / (du * (du + dd))) <= 1e-13 * abs(g)
+        assert abs(a - (w2 - du * w1) / (dd * (du + dd))) <= 1e-12 * abs(a)
+        assert abs((a + b + g) - w0) <= 1e-13 * w0
 
 
 def _tau_grid(n, top_thin=1e-10, tot=6.0, seed=3):
