@@ -124,13 +124,23 @@ void hr2_ctx_destroy(hr2_ctx *ctx);
 /* Thread-local text of the last failure on this thread ("" if none). */
 const char *hr2_last_error(void);
 
-/* Launch-shape options (performance only; results do not depend on them
- * beyond FP32 rounding of the chunk combination, see HR2_OPT_CHUNKS). */
+/* Context options.  CHUNKS, NU_PER_LANE and TIMING shape launches only
+ * (results do not depend on them beyond FP32 rounding of the chunk
+ * combination).  SOURCE selects the source-function interpolant of the
+ * short characteristics (Eq. 4-7): 1 = linear (default, the paper's
+ * choice), 2 = parabolic (the quadratic through the upwind, local and
+ * downwind levels, Olson & Kunasz 1987 coefficients; the top step, which
+ * has no downwind level, and a step whose downwind layer has zero optical
+ * depth stay linear).  The parabolic coefficients grow like 1/dd when the
+ * downwind layer is much thinner than the upwind one, so FP32 results lose
+ * accuracy at sharp optical-depth contrasts (an opaque cloud top). */
 typedef enum {
-  HR2_OPT_CHUNKS = 0,      /* layer chunks per wavenumber tile: 0 = auto, 1, 2, 4 */
+  HR2_OPT_CHUNKS = 0,      /* layer chunks per wavenumber tile: 0 = auto, 1 .. 8 */
   HR2_OPT_NU_PER_LANE = 1, /* wavenumbers per lane: 0 = auto, 1 (only 1 is built) */
-  HR2_OPT_TIMING = 2       /* n > 0: bracket the kernels of every n-th forward-batch
+  HR2_OPT_TIMING = 2,      /* n > 0: bracket the kernels of every n-th forward-batch
                               call with HIP events (0 = off)                        */
+  HR2_OPT_SOURCE = 3       /* 1 = linear source (default), 2 = parabolic; servers
+                              take the value their context has at creation          */
 } hr2_option;
 hr2_status hr2_ctx_set_option(hr2_ctx *ctx, hr2_option opt, int value);
 

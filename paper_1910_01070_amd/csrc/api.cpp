@@ -252,6 +252,11 @@ extern "C" hr2_status hr2_ctx_set_option(hr2_ctx *ctx, hr2_option opt, int value
       ctx->timing_every = value;
       ctx->timing_calls = 0;
       return HR2_OK;
+    case HR2_OPT_SOURCE:
+      if (value != 1 && value != 2)
+        return set_error(HR2_E_INVALID_ARG, "source order must be 1 (linear) or 2 (parabolic)");
+      ctx->opt_source = value;
+      return HR2_OK;
   }
   return set_error(HR2_E_INVALID_ARG, "unknown option");
 }
@@ -553,19 +558,19 @@ ColumnsView columns_view(const void *dev, int n_sets, int L, int S) {
 // smaller of the two maxima (small penalty per chunk for the combine).
 // Depends on the request and the device only.
 int auto_chunks(const TableView &tv, int64_t base_waves, int n_levels, int n_mu,
-                bool from_chi) {
+                bool from_chi, bool para) {
   // capacities depend on the kernel variant and the device only: cache them
   static std::mutex mu;
-  static std::map<std::tuple<int, int, int, int, int, bool, int>, int> cache;
+  static std::map<std::tuple<int, int, int, int, int, bool, int, bool>, int> cache;
   int dev = 0;
   (void)hipGetDevice(&dev);
   auto capacity = [&](int c) {
     const int big = (int64_t)tv.S * tv.nT * tv.nP * tv.pitch * tv.tab_elem >= 0xFFFFFFFFll;
-    const auto key = std::make_tuple(dev, tv.dtype, tv.S, big, n_mu > 4 ? 8 : 4, from_chi, c);
+    const auto key = std::make_tuple(dev, tv.dtype, tv.S, big, n_mu > 4 ? 8 : 4, from_chi, c, para);
     std::lock_guard<std::mutex> lk(mu);
     auto it = cache.find(key);
     if (it != cache.end()) return it->second;
-    const int v = column_wave_capacity(tv, n_mu, from_chi, c);
+    const int v = column_wave_capacity(tv, n_mu, from_chi, c, para);
     cache.emplace(key, v);
     return v;
   };
@@ -573,7 +578,7 @@ int auto_chunks(const TableView &tv, int64_t base_waves, int n_levels, int n_mu,
   double best_cost = 1e300;
   for (int c = 1; c <= 8 && c <= n_levels - 1; ++c) {
     const int64_t cap = std::max(1, capacity(c));
-    const double per_wave = (double)((n_levels - 1 + c - 1) / c + 1);
+    const double per_wave = (double)((n_levels - 1 + c - 1) / c + (para && c > 1 ? 2 : 1));
     const double through = (double)base_waves * c * per_wave / (double)cap;
     const double cost = std::max(through, per_wave) * (1.0 + 0.02 * c);
     if (cost < best_cost * 0.999) {
@@ -806,7 +811,7 @@ extern "C" hr2_status hr2_rt_emission(hr2_ctx *ctx, const hr2_tables *t, const h
   const int64_t base_waves = (w.nu_count + 63) / 64;
   const int chunks = ctx->opt_chunks ? std::min(ctx->opt_chunks, std::max(1, col->n_levels - 1))
                                      : auto_chunks(t->view, base_waves, col->n_levels, n_mu,
-                                                   true);
+                                                   true, ctx->opt_source == 2);
   ColSeg seg{};
   seg.wg_begin = 0;
   seg.nu_begin = w.nu_begin;
@@ -825,7 +830,7 @@ extern "C" hr2_status hr2_rt_emission(hr2_ctx *ctx, const hr2_tables *t, const h
   if ((st = upload_cached(ctx, ctx->segs, ctx->segs_shadow, &seg, sizeof(seg), s)) != HR2_OK)
     return st;
   HIP_TRY(launch_column(t->view, (const ColSeg *)ctx->segs.ptr, 1, seg.tiles_per_set, chunks,
-                        ctx->recs.ptr, chi, fplus, n_mu, true, s));
+                        ctx->recs.ptr, chi, fplus, n_mu, true, ctx->opt_source == 2, s));
   return ctx_end(ctx, s);
 }
 
@@ -908,7 +913,8 @@ hr2_status run_forward(hr2_ctx *ctx, const hr2_tables *t, const hr2_obs *o, cons
   HIP_TRY(launch_levels(t->view, cv, ctx->recs.ptr, status, t->view.dtype == HR2_TABLE_F64, s));
   const int64_t base_waves = (int64_t)B * ((w.nu_count + 63) / 64);
   const int chunks = ctx->opt_chunks ? std::min(ctx->opt_chunks, std::max(1, L - 1))
-                                     : auto_chunks(t->view, base_waves, L, n_mu, false);
+                                     : auto_chunks(t->view, base_waves, L, n_mu, false,
+                                                   ctx->opt_source == 2);
   const int per_wg = column_nu_per_wg(chunks);
   ColSeg seg{};
   seg.wg_begin = 0;
@@ -930,7 +936,7 @@ hr2_status run_forward(hr2_ctx *ctx, const hr2_tables *t, const hr2_obs *o, cons
     return st;
   if (timed) HIP_TRY(hipEventRecord(ev[1], s));
   HIP_TRY(launch_column(t->view, (const ColSeg *)ctx->segs.ptr, 1, total_wgs, chunks,
-                        ctx->recs.ptr, nullptr, fplus, n_mu, false, s));
+                        ctx->recs.ptr, nullptr, fplus, n_mu, false, ctx->opt_source == 2, s));
   ConvSeg cs{};
   cs.item_begin = 0;
   cs.K = o->d_K;

@@ -34,6 +34,7 @@ struct hr2_ctx {
   void *pinned = nullptr;
   size_t pinned_cap = 0;
   int opt_chunks = 0;
+  int opt_source = 1;              // 1 linear, 2 parabolic short characteristics
   int timing_every = 0;            // time every n-th forward call (0 = off)
   int64_t timing_calls = 0;
   std::vector<hipEvent_t> tev;     // 4 events per timed call
@@ -54,7 +55,8 @@ hr2_status check_n_mu(int n_mu);
 void pack_columns(const hr2_tables *t, int n_sets, const hr2_column *cols,
                   std::vector<double> &buf);
 ColumnsView columns_view(const void *dev, int n_sets, int L, int S);
-int auto_chunks(const TableView &tv, int64_t base_waves, int n_levels, int n_mu, bool from_chi);
+int auto_chunks(const TableView &tv, int64_t base_waves, int n_levels, int n_mu, bool from_chi,
+                bool para);
 
 struct ObsPlan {
   int64_t N = 0, i0 = 0, n_pts = 0, nnz = 0;

@@ -153,12 +153,15 @@ hipError_t launch_levels(const TableView &tv, const ColumnsView &cv, void *recs,
 
 // One workgroup = `chunks` waves = one 64-point tile of one set; every
 // segment of the launch must use that chunk count.
+// para: parabolic source (else linear).
 hipError_t launch_column(const TableView &tv, const ColSeg *segs_dev, int n_segs,
                          int64_t total_wgs, int chunks, const void *recs, const void *chi_in,
-                         void *out, int max_mu, bool opacity_from_memory, hipStream_t stream);
+                         void *out, int max_mu, bool opacity_from_memory, bool para,
+                         hipStream_t stream);
 int column_nu_per_wg(int chunks);
 // Waves of the column kernel (with this chunk count) the device holds at once.
-int column_wave_capacity(const TableView &tv, int max_mu, bool opacity_from_memory, int chunks);
+int column_wave_capacity(const TableView &tv, int max_mu, bool opacity_from_memory, int chunks,
+                         bool para);
 
 hipError_t launch_opacity_only(const TableView &tv, const void *recs, int n_levels,
                                int64_t nu_begin, int64_t nu_count, int64_t nu_stride,

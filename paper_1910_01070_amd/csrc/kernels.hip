@@ -380,6 +380,142 @@ __device__ __forceinline__ double sc_step_d(double I, double dtau, double S1, do
   return e * I + beta * S1 + gamma * S0;
 }
 
+// One parabolic step (the higher-order interpolant of Eq. 4-7, after Olson
+// & Kunasz 1987): the source on the upwind layer is the quadratic through
+// the upwind, local and downwind levels.  With path lengths du, dd (optical
+// depths over mu of the upwind and downwind layers) and the moments
+// w_n = int_0^du x^n e^{-x} dx,
+//   I_new = e^{-du} I + w0 S_loc + gamma (S_up - S_loc) + alpha (S_dn - S_loc)
+//   gamma = (w2 + dd w1) / (du (du + dd)),  alpha = (w2 - du w1) / (dd (du + dd))
+// (alpha + beta + gamma = w0 written with differences of S).  FP32: below
+// du = 1/2 the moments come from their series, q0 = w0/du,
+// q1 = w1/du^2 and q21 = (w2 - du w1)/du^3, free of cancellation; dd > 0.
+// r_s = 1/(dtau_u + dtau_d) and r_d = 1/dtau_d, r_u = 1/dtau_u are shared
+// by the angles.
+__device__ __forceinline__ float sc_para_f(float I, float dtau_u, float dtau_d, float r_u,
+                                           float r_d, float r_s, float S_up, float S_loc,
+                                           float S_dn, float inv_mu, float l2e_mu, float mu) {
+  const float du = dtau_u * inv_mu, dd = dtau_d * inv_mu;
+  const float i_s = mu * r_s;   // 1 / (du + dd)
+  float e, w0, gam, alp;
+  if (du < 0.5f) {
+    // Horner in -du; coefficients 1/(m+1)!, 1/(m! (m+2)), -1/(m! (m+2)(m+3)), m = 9 .. 0
+    const float x = -du;
+    float q0 = 2.755731922e-07f, q1 = 2.505210839e-07f, q21 = -2.087675699e-08f;
+    q0 = fmaf(q0, x, 2.755731922e-06f);
+    q1 = fmaf(q1, x, 2.480158730e-06f);
+    q21 = fmaf(q21, x, -2.254689755e-07f);
+    q0 = fmaf(q0, x, 2.480158730e-05f);
+    q1 = fmaf(q1, x, 2.204585538e-05f);
+    q21 = fmaf(q21, x, -2.204585538e-06f);
+    q0 = fmaf(q0, x, 1.984126984e-04f);
+    q1 = fmaf(q1, x, 1.736111111e-04f);
+    q21 = fmaf(q21, x, -1.929012346e-05f);
+    q0 = fmaf(q0, x, 1.388888889e-03f);
+    q1 = fmaf(q1, x, 1.190476190e-03f);
+    q21 = fmaf(q21, x, -1.488095238e-04f);
+    q0 = fmaf(q0, x, 8.333333333e-03f);
+    q1 = fmaf(q1, x, 6.944444444e-03f);
+    q21 = fmaf(q21, x, -9.920634921e-04f);
+    q0 = fmaf(q0, x, 4.166666667e-02f);
+    q1 = fmaf(q1, x, 3.333333333e-02f);
+    q21 = fmaf(q21, x, -5.555555556e-03f);
+    q0 = fmaf(q0, x, 1.666666667e-01f);
+    q1 = fmaf(q1, x, 1.250000000e-01f);
+    q21 = fmaf(q21, x, -2.500000000e-02f);
+    q0 = fmaf(q0, x, 5.000000000e-01f);
+    q1 = fmaf(q1, x, 3.333333333e-01f);
+    q21 = fmaf(q21, x, -8.333333333e-02f);
+    q0 = fmaf(q0, x, 1.000000000e+00f);
+    q1 = fmaf(q1, x, 5.000000000e-01f);
+    q21 = fmaf(q21, x, -1.666666667e-01f);
+    w0 = du * q0;
+    e = 1.0f - w0;
+    gam = du * fmaf(du, q1 + q21, dd * q1) * i_s;
+    alp = du * du * du * q21 * (mu * r_d) * i_s;
+  } else {
+    e = fexp2(-dtau_u * l2e_mu);
+    w0 = 1.0f - e;
+    const float w1 = fmaf(-du, e, w0);
+    const float w2 = fmaf(-du * du, e, 2.0f * w1);
+    gam = fmaf(dd, w1, w2) * (mu * r_u) * i_s;
+    alp = fmaf(-du, w1, w2) * (mu * r_d) * i_s;
+  }
+  return fmaf(e, I, fmaf(w0, S_loc, fmaf(gam, S_up - S_loc, alp * (S_dn - S_loc))));
+}
+
+__device__ __forceinline__ double sc_para_d(double I, double dtau_u, double dtau_d, double S_up,
+                                            double S_loc, double S_dn, double mu) {
+  if (dtau_u == 0.0) return I;
+  const double du = dtau_u / mu, dd = dtau_d / mu;
+  double e, w0, gam, alp;
+  if (du < 0.5) {
+    // the series of the FP32 step, to m = 16 (FP64 accuracy at du = 1/2)
+    const double x = -du;
+    double q0 = 2.81145725434552060e-15, q1 = 2.65526518465965852e-15, q21 = -1.39750799192613615e-16;
+    q0 = fma(q0, x, 4.77947733238738525e-14);
+    q1 = fma(q1, x, 4.49833160695283296e-14);
+    q21 = fma(q21, x, -2.49907311497379604e-15);
+    q0 = fma(q0, x, 7.64716373181981641e-13);
+    q1 = fma(q1, x, 7.16921599858107782e-13);
+    q21 = fma(q21, x, -4.21718588151828129e-14);
+    q0 = fma(q0, x, 1.14707455977297245e-11);
+    q1 = fma(q1, x, 1.07060292245477428e-11);
+    q21 = fma(q21, x, -6.69126826534233923e-13);
+    q0 = fma(q0, x, 1.60590438368216133e-10);
+    q1 = fma(q1, x, 1.49119692770486430e-10);
+    q21 = fma(q21, x, -9.94131285136576102e-12);
+    q0 = fma(q0, x, 2.08767569878681002e-09);
+    q1 = fma(q1, x, 1.92708526041859370e-09);
+    q21 = fma(q21, x, -1.37648947172756701e-10);
+    q0 = fma(q0, x, 2.50521083854417202e-08);
+    q1 = fma(q1, x, 2.29644326866549102e-08);
+    q21 = fma(q21, x, -1.76649482205037760e-09);
+    q0 = fma(q0, x, 2.75573192239858883e-07);
+    q1 = fma(q1, x, 2.50521083854417176e-07);
+    q21 = fma(q21, x, -2.08767569878681002e-08);
+    q0 = fma(q0, x, 2.75573192239858925e-06);
+    q1 = fma(q1, x, 2.48015873015873016e-06);
+    q21 = fma(q21, x, -2.25468975468975469e-07);
+    q0 = fma(q0, x, 2.48015873015873016e-05);
+    q1 = fma(q1, x, 2.20458553791887140e-05);
+    q21 = fma(q21, x, -2.20458553791887106e-06);
+    q0 = fma(q0, x, 1.98412698412698413e-04);
+    q1 = fma(q1, x, 1.73611111111111118e-04);
+    q21 = fma(q21, x, -1.92901234567901231e-05);
+    q0 = fma(q0, x, 1.38888888888888894e-03);
+    q1 = fma(q1, x, 1.19047619047619058e-03);
+    q21 = fma(q21, x, -1.48809523809523823e-04);
+    q0 = fma(q0, x, 8.33333333333333322e-03);
+    q1 = fma(q1, x, 6.94444444444444406e-03);
+    q21 = fma(q21, x, -9.92063492063492008e-04);
+    q0 = fma(q0, x, 4.16666666666666644e-02);
+    q1 = fma(q1, x, 3.33333333333333329e-02);
+    q21 = fma(q21, x, -5.55555555555555577e-03);
+    q0 = fma(q0, x, 1.66666666666666657e-01);
+    q1 = fma(q1, x, 1.25000000000000000e-01);
+    q21 = fma(q21, x, -2.50000000000000014e-02);
+    q0 = fma(q0, x, 5.00000000000000000e-01);
+    q1 = fma(q1, x, 3.33333333333333315e-01);
+    q21 = fma(q21, x, -8.33333333333333287e-02);
+    q0 = fma(q0, x, 1.00000000000000000e+00);
+    q1 = fma(q1, x, 5.00000000000000000e-01);
+    q21 = fma(q21, x, -1.66666666666666657e-01);
+    w0 = du * q0;
+    e = exp(-du);
+    gam = du * (du * (q1 + q21) + dd * q1) / (du + dd);
+    alp = du * du * du * q21 / (dd * (du + dd));
+  } else {
+    e = exp(-du);
+    w0 = -expm1(-du);
+    const double w1 = w0 - du * e;
+    const double w2 = 2.0 * w1 - du * du * e;
+    gam = (w2 + dd * w1) / (du * (du + dd));
+    alp = (w2 - du * w1) / (dd * (du + dd));
+  }
+  return e * I + w0 * S_loc + gam * (S_up - S_loc) + alp * (S_dn - S_loc);
+}
+
 // ------------------------------------------------------------ column kernel
 // Workgroup = 4 waves.  With C chunks, wave w handles sub-tile w / C (64
 // window points) and layer chunk w % C.  Each lane sweeps its chunk's levels
@@ -391,7 +527,9 @@ __device__ __forceinline__ double sc_step_d(double I, double dtau, double S1, do
 // rides in the scalar offset operand.
 // NS: species slots compiled; a negative NS means exactly -NS species (no
 // per-species guards), otherwise tv.S <= NS species with uniform guards.
-template <typename Real, typename TT, int NSS, int MAXMU, bool FROM_CHI, bool BIG>
+// PARA: parabolic source (each step also needs the downwind level, so a
+// chunk below the top reads one level past its end).
+template <typename Real, typename TT, int NSS, int MAXMU, bool FROM_CHI, bool BIG, bool PARA>
 __global__ __launch_bounds__(512) void k_column(TableView tv, const ColSeg *__restrict__ segs,
                                                 int n_segs, int64_t total_wgs,
                                                 const void *__restrict__ recs_v,
@@ -488,6 +626,10 @@ __global__ __launch_bounds__(512) void k_column(TableView tv, const ColSeg *__re
   }
   Real tau = (Real)0, chi_prev = (Real)0, S_prev = (Real)0, hdz_prev = (Real)0,
        dtc_prev = (Real)0;
+  Real S_pp = (Real)0, dtau_last = (Real)0;   // parabolic: level l-2, layer l-2 -> l-1
+  // last level visited: the chunk's top, or one more for the parabolic
+  // step's downwind level when the chunk is not the topmost
+  const int l_end = (PARA && l1 < nlay) ? l1 + 1 : l1;
 
   // Fetch the rows a level needs that the slots do not hold yet.  The rows
   // of level l+1 are requested right after level l's opacity is formed (its
@@ -525,7 +667,7 @@ __global__ __launch_bounds__(512) void k_column(TableView tv, const ColSeg *__re
 
   if (l0 < nlay) {
     if constexpr (!FROM_CHI) fetch(rec[l0], rec[l0].mask >> 8);
-    for (int l = l0; l <= l1; ++l) {
+    for (int l = l0; l <= l_end; ++l) {
       const Rec r = rec[l];
       Real chi;
       if constexpr (FROM_CHI) {
@@ -553,7 +695,7 @@ __global__ __launch_bounds__(512) void k_column(TableView tv, const ColSeg *__re
               chi = fmaf(r.a_cia[q], fexp2(y), chi);
           }
         }
-        if (l < l1) {
+        if (l < l_end) {
           const Rec &rn = rec[l + 1];
           // keeps this fetch here, after the opacity, instead of being merged
           // with the chunk's first fetch at the top of the loop
@@ -572,23 +714,66 @@ __global__ __launch_bounds__(512) void k_column(TableView tv, const ColSeg *__re
       } else {
         // trapezoid of chi over the layer, plus its share of a gray cloud
         const Real dtau = (chi_prev + chi) * hdz_prev + dtc_prev;
-        tau += dtau;
-        if constexpr (kF64) {
+        if constexpr (!PARA) {
+          tau += dtau;
+          if constexpr (kF64) {
 #pragma unroll
-          for (int k = 0; k < MAXMU; ++k)
-            if (k < nmu) I[k] = sc_step_d(I[k], dtau, S, S_prev, a_mud[k]);
+            for (int k = 0; k < MAXMU; ++k)
+              if (k < nmu) I[k] = sc_step_d(I[k], dtau, S, S_prev, a_mud[k]);
+          } else {
+            const float rdt = frcp(dtau);
+#pragma unroll
+            for (int k = 0; k < MAXMU; ++k)
+              if (k < nmu)
+                I[k] = sc_step_f(I[k], dtau, rdt, S, S_prev, a_inv[k], a_l2e[k], a_mu[k]);
+          }
         } else {
-          const float rdt = frcp(dtau);
+          if (l <= l1) tau += dtau;
+          // the step l-2 -> l-1 now has its downwind level l; a transparent
+          // downwind layer leaves the linear coefficients
+          if (l >= l0 + 2) {
+            if constexpr (kF64) {
 #pragma unroll
-          for (int k = 0; k < MAXMU; ++k)
-            if (k < nmu)
-              I[k] = sc_step_f(I[k], dtau, rdt, S, S_prev, a_inv[k], a_l2e[k], a_mu[k]);
+              for (int k = 0; k < MAXMU; ++k)
+                if (k < nmu)
+                  I[k] = dtau > 0.0 ? sc_para_d(I[k], dtau_last, dtau, S_pp, S_prev, S, a_mud[k])
+                                    : sc_step_d(I[k], dtau_last, S_prev, S_pp, a_mud[k]);
+            } else {
+              const float r_u = frcp(dtau_last), r_d = frcp(dtau), r_s = frcp(dtau_last + dtau);
+#pragma unroll
+              for (int k = 0; k < MAXMU; ++k)
+                if (k < nmu)
+                  I[k] = dtau > 0.0f
+                             ? sc_para_f(I[k], dtau_last, dtau, r_u, r_d, r_s, S_pp, S_prev, S,
+                                         a_inv[k], a_l2e[k], a_mu[k])
+                             : sc_step_f(I[k], dtau_last, r_u, S_prev, S_pp, a_inv[k], a_l2e[k],
+                                         a_mu[k]);
+            }
+          }
+          S_pp = S_prev;
+          dtau_last = dtau;
         }
       }
       chi_prev = chi;
       S_prev = S;
       hdz_prev = r.hdz;
       dtc_prev = r.dtc;
+    }
+    if constexpr (PARA) {
+      // the topmost chunk's last step has no downwind level: linear
+      if (l_end == l1 && l1 > l0) {
+        if constexpr (kF64) {
+#pragma unroll
+          for (int k = 0; k < MAXMU; ++k)
+            if (k < nmu) I[k] = sc_step_d(I[k], dtau_last, S_prev, S_pp, a_mud[k]);
+        } else {
+          const float r_u = frcp(dtau_last);
+#pragma unroll
+          for (int k = 0; k < MAXMU; ++k)
+            if (k < nmu)
+              I[k] = sc_step_f(I[k], dtau_last, r_u, S_prev, S_pp, a_inv[k], a_l2e[k], a_mu[k]);
+        }
+      }
     }
   }
 
@@ -642,43 +827,50 @@ struct ColumnKernel {
   int real_bytes;
 };
 
-template <typename Real, typename TT, int NS, int MAXMU, bool FROM_CHI, bool BIG = false>
+template <typename Real, typename TT, int NS, int MAXMU, bool FROM_CHI, bool PARA,
+          bool BIG = false>
 static ColumnKernel ck() {
-  return ColumnKernel{&k_column<Real, TT, NS, MAXMU, FROM_CHI, BIG>, MAXMU, (int)sizeof(Real)};
+  return ColumnKernel{&k_column<Real, TT, NS, MAXMU, FROM_CHI, BIG, PARA>, MAXMU,
+                      (int)sizeof(Real)};
 }
 
-template <typename Real, typename TT, bool FROM_CHI>
+template <typename Real, typename TT, bool FROM_CHI, bool PARA>
 static ColumnKernel pick_ns(const TableView &tv, int max_mu) {
   const int S = tv.S;
   if constexpr (FROM_CHI) {
-    if (max_mu <= 4) return ck<Real, TT, 1, 4, true>();
-    return ck<Real, TT, 1, 8, true>();
+    if (max_mu <= 4) return ck<Real, TT, 1, 4, true, PARA>();
+    return ck<Real, TT, 1, 8, true, PARA>();
   } else {
     const int64_t table_bytes = (int64_t)tv.S * tv.nT * tv.nP * tv.pitch * (int64_t)sizeof(TT);
-    if (table_bytes >= 0xFFFFFFFFll) return ck<Real, TT, kMaxSpecies, 8, false, true>();
+    if (table_bytes >= 0xFFFFFFFFll) return ck<Real, TT, kMaxSpecies, 8, false, PARA, true>();
     if (max_mu <= 4) {
-      if (S <= 1) return ck<Real, TT, -1, 4, false>();
-      if (S == 8) return ck<Real, TT, -8, 4, false>();
-      if (S <= 8) return ck<Real, TT, 8, 4, false>();
-      return ck<Real, TT, kMaxSpecies, 4, false>();
+      if (S <= 1) return ck<Real, TT, -1, 4, false, PARA>();
+      if (S == 8) return ck<Real, TT, -8, 4, false, PARA>();
+      if (S <= 8) return ck<Real, TT, 8, 4, false, PARA>();
+      return ck<Real, TT, kMaxSpecies, 4, false, PARA>();
     }
-    if (S <= 1) return ck<Real, TT, -1, 8, false>();
-    if (S <= 8) return ck<Real, TT, 8, 8, false>();
-    return ck<Real, TT, kMaxSpecies, 8, false>();
+    if (S <= 1) return ck<Real, TT, -1, 8, false, PARA>();
+    if (S <= 8) return ck<Real, TT, 8, 8, false, PARA>();
+    return ck<Real, TT, kMaxSpecies, 8, false, PARA>();
   }
 }
 
-static ColumnKernel pick_column(const TableView &tv, int max_mu, bool from_chi) {
+template <bool PARA>
+static ColumnKernel pick_dtype(const TableView &tv, int max_mu, bool from_chi) {
   if (from_chi) {
-    if (tv.dtype == HR2_TABLE_F64) return pick_ns<double, double, true>(tv, max_mu);
-    return pick_ns<float, float, true>(tv, max_mu);
+    if (tv.dtype == HR2_TABLE_F64) return pick_ns<double, double, true, PARA>(tv, max_mu);
+    return pick_ns<float, float, true, PARA>(tv, max_mu);
   }
   switch (tv.dtype) {
-    case HR2_TABLE_F64: return pick_ns<double, double, false>(tv, max_mu);
-    case HR2_TABLE_F16: return pick_ns<float, _Float16, false>(tv, max_mu);
-    case HR2_TABLE_BF16: return pick_ns<float, uint16_t, false>(tv, max_mu);
-    default: return pick_ns<float, float, false>(tv, max_mu);
+    case HR2_TABLE_F64: return pick_ns<double, double, false, PARA>(tv, max_mu);
+    case HR2_TABLE_F16: return pick_ns<float, _Float16, false, PARA>(tv, max_mu);
+    case HR2_TABLE_BF16: return pick_ns<float, uint16_t, false, PARA>(tv, max_mu);
+    default: return pick_ns<float, float, false, PARA>(tv, max_mu);
   }
+}
+
+static ColumnKernel pick_column(const TableView &tv, int max_mu, bool from_chi, bool para) {
+  return para ? pick_dtype<true>(tv, max_mu, from_chi) : pick_dtype<false>(tv, max_mu, from_chi);
 }
 
 static size_t column_shmem(const ColumnKernel &k, int chunks) {
@@ -687,17 +879,19 @@ static size_t column_shmem(const ColumnKernel &k, int chunks) {
 
 hipError_t launch_column(const TableView &tv, const ColSeg *segs_dev, int n_segs,
                          int64_t total_wgs, int chunks, const void *recs, const void *chi_in,
-                         void *out, int max_mu, bool opacity_from_memory, hipStream_t stream) {
+                         void *out, int max_mu, bool opacity_from_memory, bool para,
+                         hipStream_t stream) {
   if (total_wgs <= 0) return hipSuccess;
-  const ColumnKernel k = pick_column(tv, max_mu, opacity_from_memory);
+  const ColumnKernel k = pick_column(tv, max_mu, opacity_from_memory, para);
   hipLaunchKernelGGL(k.fn, dim3((unsigned)total_wgs), dim3(64 * chunks),
                      column_shmem(k, chunks), stream, tv, segs_dev, n_segs, total_wgs, recs,
                      chi_in, out);
   return hipGetLastError();
 }
 
-int column_wave_capacity(const TableView &tv, int max_mu, bool opacity_from_memory, int chunks) {
-  const ColumnKernel k = pick_column(tv, max_mu, opacity_from_memory);
+int column_wave_capacity(const TableView &tv, int max_mu, bool opacity_from_memory, int chunks,
+                         bool para) {
+  const ColumnKernel k = pick_column(tv, max_mu, opacity_from_memory, para);
   int blocks = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, (const void *)k.fn, 64 * chunks,
                                                    column_shmem(k, chunks)) != hipSuccess ||

@@ -142,6 +142,7 @@ struct hr2_server {
   bool stop = false;
   bool fail_next = false;
   bool hold = false;
+  bool para = false;                 // parabolic source (the context's option at creation)
   hr2_serve_stats stats{};
   std::thread thr;
 
@@ -303,7 +304,7 @@ bool hr2_server::launch_step(StepSlot &sl, std::vector<Req *> &reqs) {
   const ConvSeg *dvs = (const ConvSeg *)((unsigned char *)sl.desc.ptr + round256(bytes_c));
   for (const Group &gq : groups)
     if (launch_column(tv, dcs + gq.first, (int)gq.count, gq.wgs, gq.chunks, base, nullptr, base,
-                      gq.max_mu, false, s) != hipSuccess)
+                      gq.max_mu, false, para, s) != hipSuccess)
       return false;
   if (launch_convolve_bin(fp64, dvs, (int)vs.size(), waves, base, base, s) != hipSuccess)
     return false;
@@ -477,6 +478,7 @@ extern "C" hr2_status hr2_serve_create(hr2_ctx *ctx, const hr2_tables *t, size_t
   if (hipSetDevice(ctx->device) != hipSuccess) return set_error(HR2_E_DEVICE, "hipSetDevice");
   auto *srv = new hr2_server();
   srv->ctx = ctx;
+  srv->para = ctx->opt_source == 2;
   srv->tables = t;
   srv->budget = round256(budget);
   srv->max_slots = max_slots;
@@ -528,7 +530,7 @@ extern "C" hr2_status hr2_serve_submit(hr2_server *srv, const hr2_request *q, ui
     // chunking depends on the request alone, so its result does not depend on the mix
     (void)hipSetDevice(srv->ctx->device);
     r->chunks = auto_chunks(t->view, (int64_t)r->n_sets * ((r->window.nu_count + 63) / 64), r->L,
-                            r->n_mu, false);
+                            r->n_mu, false, srv->para);
   }
   pack_columns(t, q->n_sets, q->cols, r->cols);
   layout_request(t, *r);

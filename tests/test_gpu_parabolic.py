@@ -1,0 +1,152 @@
+"""GPU parity of the parabolic short characteristics (HR2_OPT_SOURCE = 2)
+against the oracle's parabolic sweep, through every chunking (each chunk
+below the top reads one level past its end), the stage call from a given
+opacity, C2 at full size (sampled), serving, and the isothermal limit.
+Tolerances as the linear scheme: 1e-12 (FP64 tables), 1e-5 (FP32)."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as wl
+from tests import hr2_testutil as tu
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from paper_1910_01070_amd import hr2  # noqa: E402
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    c = hr2.Context(0)
+    c.set_option(hr2.OPT_SOURCE, 2)
+    yield c
+    torch.cuda.synchronize()
+    c.close()
+
+
+def run_forward(ctx, tables, obs, cols, n_mu=3, chunks=0):
+    ctx.set_option(hr2.OPT_CHUNKS, chunks)
+    B = len(cols)
+    bins = torch.empty(B * obs.n_bins, dtype=tables.real, device="cuda")
+    fplus = torch.empty(B * obs.window.count, dtype=tables.real, device="cuda")
+    hr2.forward_batch(ctx, tables, obs, cols, n_mu, bins, fplus)
+    torch.cuda.synchronize()
+    ctx.set_option(hr2.OPT_CHUNKS, 0)
+    return (bins.cpu().numpy().reshape(B, obs.n_bins).astype(np.float64),
+            fplus.cpu().numpy().reshape(B, obs.window.count).astype(np.float64))
+
+
+def test_option_values(ctx):
+    with pytest.raises(hr2.HR2Error):
+        ctx.set_option(hr2.OPT_SOURCE, 3)
+    ctx.set_option(hr2.OPT_SOURCE, 2)
+
+
+@pytest.mark.parametrize("dtype,tol", [("f64", 1e-12), ("f32", 1e-5)])
+def test_c1_parabolic_all_chunkings(ctx, dtype, tol):
+    tab = tu.c1_table()
+    cols = wl.c1_columns()
+    spec = wl.c1_obs(tab)
+    T = hr2.Tables(ctx, tab, dtype)
+    obs = hr2.Obs(ctx, T, spec.window, spec.resolving_power, spec.edges_cm)
+    refs = [oracle.forward(tab, c, spec.window, spec.resolving_power, spec.edges_cm, 3, order=2)
+            for c in cols]
+    lin = oracle.forward(tab, cols[2], spec.window, spec.resolving_power, spec.edges_cm, 3)
+    for chunks in (0, 1, 2, 3, 4, 6, 8):
+        say(f"C1 {dtype} parabolic, chunks={chunks}")
+        bins, fplus = run_forward(ctx, T, obs, cols, 3, chunks)
+        for s, ref in enumerate(refs):
+            e_f, _ = tu.max_rel_err(fplus[s], ref["fplus"])
+            e_b, _ = tu.max_rel_err(bins[s], ref["bins"])
+            say(f"  set {s}: F+ {e_f:.2e} bins {e_b:.2e}")
+            assert e_f <= tol and e_b <= tol
+    # the two schemes differ by far more than the tolerance on a curved profile
+    e_lin, _ = tu.max_rel_err(refs[2]["fplus"], lin["fplus"])
+    say(f"  parabolic vs linear (oracle): {e_lin:.2e}")
+    assert e_lin > 100 * tol
+    obs.close()
+    T.close()
+
+
+@pytest.mark.parametrize("dtype,tol", [("f64", 1e-12), ("f32", 1e-5)])
+def test_multispecies_windows_parabolic(ctx, dtype, tol):
+    tab = tu.small_multi_table()
+    T = hr2.Tables(ctx, tab, dtype)
+    for w, L in [(wl.Window(0, 3000, 1), 41), (wl.Window(5, 333, 7), 41), (wl.Window(100, 640, 1), 2),
+                 (wl.Window(0, 64, 1), 3), (wl.Window(9, 200, 3), 4)]:
+        cols = tu.small_columns(tab, 3, seed=L + w.begin, n_levels=L)
+        nu_first, dnu = oracle.window_grid(tab, w)
+        edges = wl.snapped_edges(tab, w, wl.log_edges(nu_first + 0.2 * (w.count - 1) * dnu,
+                                                      nu_first + 0.8 * (w.count - 1) * dnu, 9))
+        obs = hr2.Obs(ctx, T, w, 400.0, edges)
+        refs = [oracle.forward(tab, c, w, 400.0, edges, 3, order=2) for c in cols]
+        for chunks in (1, 2, 3, 5, 8):
+            bins, fplus = run_forward(ctx, T, obs, cols, 3, chunks)
+            for s, ref in enumerate(refs):
+                e_f, _ = tu.max_rel_err(fplus[s], ref["fplus"])
+                e_b, _ = tu.max_rel_err(bins[s], ref["bins"])
+                assert e_f <= tol and e_b <= tol, (w, L, chunks, s, e_f, e_b)
+        say(f"window {w} L={L} {dtype}: ok")
+        obs.close()
+    T.close()
+
+
+@pytest.mark.parametrize("dtype,tol", [("f64", 1e-12), ("f32", 1e-5)])
+def test_stage_rt_parabolic(ctx, dtype, tol):
+    tab = tu.small_multi_table()
+    col = tu.small_columns(tab, 1, seed=3)[0]
+    w = wl.Window(7, 2900, 1)
+    T = hr2.Tables(ctx, tab, dtype)
+    chi_ref = oracle.opacity(tab, col, oracle.window_indices(w))
+    chi_in = torch.from_numpy(chi_ref.astype(np.float64 if dtype == "f64" else np.float32)).cuda()
+    fplus = torch.empty(w.count, dtype=T.real, device="cuda")
+    st = oracle.column_state(tab, col)
+    nu = tab.nu0_cm + oracle.window_indices(w) * tab.dnu_cm
+    for n_mu in (1, 2, 3, 8):
+        hr2.rt_emission(ctx, T, col, w, chi_in.reshape(-1), n_mu, fplus)
+        torch.cuda.synchronize()
+        ref = oracle.rt_emission(chi_ref, st["dz"], col.T_K, nu, n_mu, order=2)
+        e, _ = tu.max_rel_err(fplus.cpu().numpy(), ref)
+        say(f"  stage {dtype} n_mu={n_mu}: F+ {e:.2e}")
+        assert e <= tol
+    say("isothermal column: pi B whatever the opacity")
+    iso = wl.Column(col.p_bar, np.full(col.n_levels, 1234.0), col.x, col.log_g, col.scale)
+    hr2.rt_emission(ctx, T, iso, w, chi_in.reshape(-1), 3, fplus)
+    torch.cuda.synchronize()
+    e, _ = tu.max_rel_err(fplus.cpu().numpy(), np.pi * oracle.planck(nu, np.full(len(nu), 1234.0)))
+    assert e <= tol
+    T.close()
+
+
+def test_c2_parabolic_sampled_and_serving(ctx):
+    tab = tu.c2_table()
+    T = hr2.Tables(ctx, tab, "f32")
+    spec = wl.c2_obs(tab)
+    col = wl.c2_column()
+    obs = hr2.Obs(ctx, T, spec.window, spec.resolving_power, spec.edges_cm)
+    bins, fplus = run_forward(ctx, T, obs, [col])
+    rng = np.random.default_rng(11)
+    pts = np.sort(rng.choice(tab.n_nu, 300, replace=False))
+    ref_f = oracle.fplus(tab, col, spec.window, 3, pts, order=2)
+    e_f, _ = tu.max_rel_err(fplus[0, pts], ref_f)
+    ids = [0, 57, 199, 312, 399]
+    ref_b = oracle.forward_bins_subset(tab, col, spec.window, spec.resolving_power,
+                                       spec.edges_cm, 3, ids, order=2)
+    e_b, _ = tu.max_rel_err(bins[0, ids], ref_b)
+    say(f"C2 f32 parabolic: sampled F+ {e_f:.2e}, bins {e_b:.2e}")
+    assert e_f <= 1e-5 and e_b <= 1e-5
+    say("serving with a parabolic context equals the batch entry")
+    srv = hr2.Server(ctx, T, 4 << 30, 8)
+    t = srv.submit(spec.window, spec.resolving_power, spec.edges_cm, [col], 3)
+    st, out, _ = srv.poll(t, obs.n_bins, wait_s=60.0)
+    assert st == hr2.OK
+    assert np.array_equal(out.astype(np.float64), bins[0])
+    srv.close()
+    obs.close()
+    T.close()
