@@ -83,6 +83,24 @@ def traffic_from_profile(kernel_hash):
     return d.get("hbm_bytes_per_launch")
 
 
+def valu_from_profile(kernel_hash, col_ms):
+    """The column kernel's VALU issue time per launch from a committed
+    rocprofv3 SQ_INSTS_VALU run on the current kernel source: wave
+    instructions x 4 cycles (64 lanes on a 16-wide SIMD) over the chip's
+    1024 SIMDs at 2.4 GHz, next to the measured kernel time."""
+    path = os.path.join(ROOT, "profiles", "column_kernel_c2_f32_valu.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        d = json.load(f)
+    if d.get("kernel_source_sha256_16") != kernel_hash:
+        return None
+    t_us = d["sq_insts_valu_per_launch"] * 4.0 / (1024 * 2.4e9) * 1e6
+    return {"sq_insts_valu_per_launch": d["sq_insts_valu_per_launch"],
+            "valu_issue_us": t_us, "kernel_us": col_ms * 1e3,
+            "issue_frac": t_us / (col_ms * 1e3), "source": "profiles/column_kernel_c2_f32_valu.json"}
+
+
 def cpu_baseline(tab, col, spec, n_mu, budget_s=20.0):
     """The FP64 oracle on the host cores: whole spectra of the same workload,
     repeated until about budget_s seconds have passed (at least one)."""
@@ -118,6 +136,10 @@ def main():
                          "as a HIP graph vs 512 sequential calls; c4: reduced-precision "
                          "batches; c5: Poisson serving trace; params: parameter vectors "
                          "to ln L")
+    ap.add_argument("--source", type=int, default=1, choices=[1, 2],
+                    help="short-characteristics source interpolant: 1 linear, 2 parabolic")
+    ap.add_argument("--cloud", action="store_true",
+                    help="c2: add a gray cloud (tau 5, top 0.3 bar, bottom 3 bar) to the column")
     ap.add_argument("--rate", type=float, default=2000.0, help="c5 arrival rate, requests/s")
     ap.add_argument("--duration", type=float, default=10.0, help="c5 trace length, s")
     args = ap.parse_args()
@@ -153,11 +175,14 @@ def main():
     log(f"  {time.perf_counter() - t0:.1f} s")
     spec = wl.c2_obs(tab)
     cols = [wl.c2_column()] if args.batch == 1 else wl.c4_columns(args.batch)
+    if args.cloud:
+        cols = [wl.Column(c.p_bar, c.T_K, c.x, c.log_g, c.scale, (5.0, 0.3, 10.0)) for c in cols]
     B, L = len(cols), cols[0].n_levels
     n_mu = 3
 
     ctx = hr2.Context(0)
     ctx.set_option(hr2.OPT_CHUNKS, args.chunks)
+    ctx.set_option(hr2.OPT_SOURCE, args.source)
     T = hr2.Tables(ctx, tab, args.dtype)
     obs = hr2.Obs(ctx, T, spec.window, spec.resolving_power, spec.edges_cm)
     dev = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
@@ -166,12 +191,14 @@ def main():
     x = dev(np.stack([c.x for c in cols]))
     lg = dev([c.log_g for c in cols])
     sc = dev([c.scale for c in cols])
+    cl = dev([c.cloud for c in cols]) if args.cloud else None
     bins = torch.empty(B * obs.n_bins, dtype=torch.float32, device="cuda")
     fplus = torch.empty(B * spec.window.count, dtype=torch.float32, device="cuda")
     stream = torch.cuda.current_stream()
 
     def step():
-        hr2.forward_batch_dev(ctx, T, obs, p, Tk, x, lg, sc, n_mu, bins, fplus, None, stream)
+        hr2.forward_batch_dev(ctx, T, obs, p, Tk, x, lg, sc, n_mu, bins, fplus, None, stream,
+                              cloud=cl)
 
     for _ in range(args.warmup):
         step()
@@ -205,7 +232,10 @@ def main():
     col_ms = ms_col / max(n_timed, 1)
     achieved = alg_bytes / (col_ms * 1e-3) / 1e9
     khash = kernel_source_hash()
-    traffic = traffic_from_profile(khash)
+    default_launch = (args.source == 1 and not args.cloud and args.dtype == "f32" and B == 1
+                      and args.n_nu == 150_000)
+    traffic = traffic_from_profile(khash) if default_launch else None
+    valu = valu_from_profile(khash, col_ms) if default_launch else None
 
     res = {
         "metric": METRIC,
@@ -229,6 +259,8 @@ def main():
             "species": tab.n_species, "cia_pairs": tab.n_cia, "n_mu": n_mu,
             "resolving_power": spec.resolving_power, "bins": obs.n_bins,
             "table_storage": args.dtype, "chunks": args.chunks,
+            "source": "parabolic" if args.source == 2 else "linear",
+            "cloud": "tau 5, 0.3-3 bar" if args.cloud else None,
         },
         "layer_nu_points_per_s": spectra_s * layer_nu,
         "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
@@ -242,6 +274,7 @@ def main():
             "algorithmic_bytes_per_launch": alg_bytes, "distinct_rows_per_species": U,
             "distinct_cia_rows": U_cia, "kernel_source": khash,
         },
+        "valu_roof": valu,
     }
     if not args.no_cpu_baseline:
         log("timing the oracle on the host")
