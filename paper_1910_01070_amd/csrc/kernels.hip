@@ -11,6 +11,7 @@
 // I_out = exp(-tau_c / mu) I_in + B_c are combined through LDS.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdint>
 #include <type_traits>
@@ -136,174 +137,191 @@ __device__ __forceinline__ void locate_lds(const double *a, int n, double v, int
   w = (v - a[lo]) / (a[lo + 1] - a[lo]);
 }
 
-constexpr int kLevelThreads = 1024;   // one pass over the (level, species) products of C2
+constexpr int kLevelThreads = 1024;   // one pass over the (level, species) items of C2
 
 template <typename Real>
 __global__ __launch_bounds__(kLevelThreads) void k_levels(TableView tv, ColumnsView cv,
-                                                typename RecOf<Real>::type *recs, int *status) {
+                                                typename RecOf<Real>::type *recs, int *status,
+                                                int blocks_per_set) {
   using Rec = typename RecOf<Real>::type;
   __shared__ double s_T[kMaxAxis], s_lp[kMaxAxis];
-  __shared__ CellW s_cell[HR2_MAX_LEVELS];
-  const int s = blockIdx.x;
+  __shared__ double s_pl[HR2_MAX_LEVELS], s_Tl[HR2_MAX_LEVELS];
+  __shared__ double s_x[kMaxSpecies], s_m[kMaxSpecies];
+  // blocks_per_set workgroups share one set's items; each stages the set
+  const int s = blockIdx.x / blocks_per_set;
+  const int part = blockIdx.x - s * blocks_per_set;
   const int L = cv.L;
   const int S = tv.S;
-  const double *p = cv.p + (int64_t)s * L;
-  const double *T = cv.T + (int64_t)s * L;
-  const double *x = cv.x + (int64_t)s * S;
+  // one coalesced pass over the set's inputs and the axes
   for (int i = threadIdx.x; i < tv.nT; i += blockDim.x) s_T[i] = tv.T_axis[i];
   for (int i = threadIdx.x; i < tv.nP; i += blockDim.x) s_lp[i] = tv.lp_axis[i];
+  for (int l = threadIdx.x; l < L; l += blockDim.x) {
+    s_pl[l] = cv.p[(int64_t)s * L + l];
+    s_Tl[l] = cv.T[(int64_t)s * L + l];
+  }
+  if (threadIdx.x < S) {
+    s_x[threadIdx.x] = cv.x[(int64_t)s * S + threadIdx.x];
+    s_m[threadIdx.x] = tv.mass[threadIdx.x];
+  }
+  const double logg = cv.logg[s], scale = cv.scale[s];
+  // gray cloud (App. B): tau_c >= 0; with tau_c > 0 a top pressure > 0 and a
+  // bottom at bottom_frac > 1 times the top
+  double tau_c = 0.0, c_top = 1.0, c_frac = 2.0;
+  if (cv.cloud) {
+    tau_c = cv.cloud[(int64_t)s * 3];
+    c_top = cv.cloud[(int64_t)s * 3 + 1];
+    c_frac = cv.cloud[(int64_t)s * 3 + 2];
+  }
+  __syncthreads();
 
   // column-wide quantities and validity (Sect. 5.2 filler gas, Table 1 inputs)
   bool bad = false;
   double xs = 0.0, mm = 0.0;
   for (int q = 0; q < S; ++q) {
-    bad |= !(x[q] >= 0.0) || !isfinite(x[q]);
-    xs += x[q];
-    mm += x[q] * tv.mass[q];
+    bad |= !(s_x[q] >= 0.0) || !isfinite(s_x[q]);
+    xs += s_x[q];
+    mm += s_x[q] * s_m[q];
   }
-  bad |= !(xs < 1.0) || !isfinite(cv.logg[s]) || !isfinite(cv.scale[s]);
-  // gray cloud (App. B): tau_c >= 0; with tau_c > 0 a top pressure > 0 and a
-  // bottom at bottom_frac > 1 times the top
-  double tau_c = 0.0, lc_top = 0.0, lc_bot = 1.0;
-  if (cv.cloud) {
-    const double *cl = cv.cloud + (int64_t)s * 3;
-    tau_c = cl[0];
-    bad |= !(tau_c >= 0.0) || !isfinite(tau_c);
-    if (tau_c > 0.0) {
-      bad |= !(cl[1] > 0.0) || !isfinite(cl[1]) || !(cl[2] > 1.0) || !isfinite(cl[2]);
-      lc_top = log(cl[1]);
-      lc_bot = log(cl[1] * cl[2]);
-    }
-  }
+  bad |= !(xs < 1.0) || !isfinite(logg) || !isfinite(scale);
+  bad |= !(tau_c >= 0.0) || !isfinite(tau_c);
+  if (tau_c > 0.0)
+    bad |= !(c_top > 0.0) || !isfinite(c_top) || !(c_frac > 1.0) || !isfinite(c_frac);
   for (int l = threadIdx.x; l < L; l += blockDim.x) {
-    bad |= !(p[l] > 0.0) || !isfinite(p[l]) || !(T[l] > 0.0) || !isfinite(T[l]);
-    if (l + 1 < L) bad |= !(p[l] > p[l + 1]);
+    bad |= !(s_pl[l] > 0.0) || !isfinite(s_pl[l]) || !(s_Tl[l] > 0.0) || !isfinite(s_Tl[l]);
+    if (l + 1 < L) bad |= !(s_pl[l] > s_pl[l + 1]);
   }
-  bad = __syncthreads_or(bad);   // also orders the axis copies
-  if (status != nullptr && threadIdx.x == 0) status[s] = bad ? (int)HR2_E_INVALID_ARG : 0;
-  for (int l = threadIdx.x; l < L; l += blockDim.x) {
-    CellW c;
-    locate_lds(s_T, tv.nT, T[l], c.iT, c.wT);
-    locate_lds(s_lp, tv.nP, log10(p[l]), c.ip, c.wp);
-    s_cell[l] = c;
-  }
-  __syncthreads();
+  bad = __syncthreads_or(bad);
+  if (status != nullptr && threadIdx.x == 0 && part == 0)
+    status[s] = bad ? (int)HR2_E_INVALID_ARG : 0;
 
   const double h2 = (1.0 - xs) / (1.0 + tv.he_ratio);
   const double he = tv.he_ratio * h2;
   mm += h2 * kMH2 + he * kMHe;
-  const double g = exp10(cv.logg[s]);
   const int64_t rows_per_species = (int64_t)tv.nT * tv.nP;
   const uint32_t row_bytes = (uint32_t)(tv.pitch * tv.tab_elem);
   const uint32_t cia_row_bytes = (uint32_t)(tv.pitch * tv.cia_elem);
+  auto cell_of = [&](int l) {
+    CellW c;
+    locate_lds(s_T, tv.nT, s_Tl[l], c.iT, c.wT);
+    locate_lds(s_lp, tv.nP, log10(s_pl[l]), c.ip, c.wp);
+    return c;
+  };
 
-  for (int l = threadIdx.x; l < L; l += blockDim.x) {
-    const double n = p[l] * 1.0e6 / (kKB * T[l]);
-    Rec r;
-    const CellW c = s_cell[l];
-    const bool has_prev = l > 0;
-    const CellW cp = has_prev ? s_cell[l - 1] : c;
-    int mask = 0;
-    for (int k = 0; k < 4; ++k) {
-      int row, rowp;
-      double w, wp;
-      slot_corner(c, k, tv.nP, row, w);
-      slot_corner(cp, k, tv.nP, rowp, wp);
-      r.w[k] = (Real)w;
-      r.rowb[k] = (uint32_t)row * row_bytes;
-      const bool nz = w != 0.0;
-      const bool kept = has_prev && wp != 0.0 && rowp == row;
-      if (nz) mask |= 1 << (8 + k);
-      if (nz && !kept) mask |= 1 << k;
-    }
-    for (int k = 0; k < 2; ++k) {
-      int row, rowp;
-      double w, wp;
-      cia_slot(c, k, row, w);
-      cia_slot(cp, k, rowp, wp);
-      r.cia_rowb[k] = (uint32_t)row * cia_row_bytes;
-      r.cia_w[k] = (Real)w;
-      const bool nz = w != 0.0 && tv.n_cia > 0;
-      const bool kept = has_prev && wp != 0.0 && rowp == row;
-      if (nz) mask |= 1 << (12 + k);
-      if (nz && !kept) mask |= 1 << (4 + k);
-    }
-    r.mask = mask;
-
-    for (int q = 0; q < kMaxSpecies; ++q) r.a_s[q] = (Real)0;
-    r.a_cia[0] = r.a_cia[1] = (Real)0;
-    double hdz = 0.0;
-    if (l + 1 < L) {
-      const double tbar = 0.5 * (T[l] + T[l + 1]);
-      hdz = 0.5 * kKB * tbar / (mm * kAMU * g) * log(p[l] / p[l + 1]);
-    }
-    if (bad) hdz = __builtin_nan("");
-    r.hdz = (Real)hdz;
-    // the cloud's optical depth, spread uniformly in ln p over
-    // [p_top, p_top bottom_frac]: this layer's share of that range
-    double dtc = 0.0;
-    if (tau_c > 0.0 && l + 1 < L) {
-      const double hi = fmin(log(p[l]), lc_bot), lo = fmax(log(p[l + 1]), lc_top);
-      if (hi > lo) dtc = tau_c * (hi - lo) / (lc_bot - lc_top);
-    }
-    r.dtc = (Real)dtc;
-    if constexpr (std::is_same<Real, float>::value) {
-      const double pl = kC2 * kLog2e / T[l];
-      const float hi = (float)pl;
-      r.pl_hi = hi;
-      r.pl_lo = (float)(pl - (double)hi);
-      r.pad = 0.0f;
-    } else {
-      r.T = T[l];
-      r.pad0 = 0;
-      for (int q = 0; q < 5; ++q) r.pad[q] = 0.0;
-    }
-    recs[(int64_t)s * L + l] = r;
-  }
-  __syncthreads();
-
-  // n_s 2^{interpolated row offset} (and the CIA pairs' n_a n_b 2^{...}),
-  // one (level, species) per thread: the kernel exponentiates only the
-  // stored offset-free part, keeping its exp2 argument small.
+  // Items: first one per level (everything but the species factors), then
+  // one per (level, species or CIA pair).  Each item finds the cells it needs
+  // itself, so no item waits for another and the table offsets are fetched
+  // while the level items run.  Items write disjoint fields of the records.
   const int per_level = S + tv.n_cia;
-  for (int t = threadIdx.x; t < L * per_level; t += blockDim.x) {
-    const int l = t / per_level, q = t - l * per_level;
-    const CellW c = s_cell[l];
-    const double n = p[l] * 1.0e6 / (kKB * T[l]);
-    Rec *r = recs + (int64_t)s * L + l;
-    if (q < S) {
-      double off[4], w[4];
+  const int n_items = L * (1 + per_level);
+  for (int t = part * blockDim.x + threadIdx.x; t < n_items; t += blocks_per_set * blockDim.x) {
+    if (t < L) {
+      const int l = t;
+      Rec *r = recs + (int64_t)s * L + l;
+      const CellW c = cell_of(l);
+      const bool has_prev = l > 0;
+      const CellW cp = has_prev ? cell_of(l - 1) : c;
+      int mask = 0;
       for (int k = 0; k < 4; ++k) {
-        int row;
-        slot_corner(c, k, tv.nP, row, w[k]);
-        off[k] = tv.off[q * rows_per_species + row];
+        int row, rowp;
+        double w, wp;
+        slot_corner(c, k, tv.nP, row, w);
+        slot_corner(cp, k, tv.nP, rowp, wp);
+        r->w[k] = (Real)w;
+        r->rowb[k] = (uint32_t)row * row_bytes;
+        const bool nz = w != 0.0;
+        const bool kept = has_prev && wp != 0.0 && rowp == row;
+        if (nz) mask |= 1 << (8 + k);
+        if (nz && !kept) mask |= 1 << k;
       }
-      const double cq = w[0] * off[0] + w[1] * off[1] + w[2] * off[2] + w[3] * off[3];
-      r->a_s[q] = (Real)(x[q] * n * exp2(cq));
-    } else {
-      const int qc = q - S;
-      double cq = 0.0;
       for (int k = 0; k < 2; ++k) {
-        int row;
-        double w;
+        int row, rowp;
+        double w, wp;
         cia_slot(c, k, row, w);
-        cq += w * tv.off_cia[qc * tv.nT + row];
+        cia_slot(cp, k, rowp, wp);
+        r->cia_rowb[k] = (uint32_t)row * cia_row_bytes;
+        r->cia_w[k] = (Real)w;
+        const bool nz = w != 0.0 && tv.n_cia > 0;
+        const bool kept = has_prev && wp != 0.0 && rowp == row;
+        if (nz) mask |= 1 << (12 + k);
+        if (nz && !kept) mask |= 1 << (4 + k);
       }
-      const double nh2 = h2 * n, nhe = he * n;
-      r->a_cia[qc] = (Real)((qc == 0 ? nh2 * nh2 : nh2 * nhe) * exp2(cq));
+      r->mask = mask;
+      for (int q = S; q < kMaxSpecies; ++q) r->a_s[q] = (Real)0;
+      if (tv.n_cia == 0) r->a_cia[0] = r->a_cia[1] = (Real)0;
+      double hdz = 0.0, dtc = 0.0;
+      if (l + 1 < L) {
+        const double tbar = 0.5 * (s_Tl[l] + s_Tl[l + 1]);
+        const double lr = log(s_pl[l] / s_pl[l + 1]);
+        hdz = 0.5 * kKB * tbar / (mm * kAMU * exp10(logg)) * lr;
+        // the cloud's optical depth, spread uniformly in ln p over
+        // [p_top, p_top bottom_frac]: this layer's share of that range
+        if (tau_c > 0.0) {
+          const double lc_top = log(c_top), lc_bot = log(c_top * c_frac);
+          const double hi = fmin(log(s_pl[l]), lc_bot), lo = fmax(log(s_pl[l + 1]), lc_top);
+          if (hi > lo) dtc = tau_c * (hi - lo) / (lc_bot - lc_top);
+        }
+      }
+      if (bad) hdz = __builtin_nan("");
+      r->hdz = (Real)hdz;
+      r->dtc = (Real)dtc;
+      if constexpr (std::is_same<Real, float>::value) {
+        const double pl = kC2 * kLog2e / s_Tl[l];
+        const float hi = (float)pl;
+        r->pl_hi = hi;
+        r->pl_lo = (float)(pl - (double)hi);
+        r->pad = 0.0f;
+      } else {
+        r->T = s_Tl[l];
+        r->pad0 = 0;
+        for (int q = 0; q < 5; ++q) r->pad[q] = 0.0;
+      }
+    } else {
+      // n_s 2^{interpolated row offset} (and the CIA pairs' n_a n_b 2^{...}):
+      // the column kernel exponentiates only the stored offset-free part,
+      // keeping its exp2 argument small.
+      const int u = t - L;
+      const int l = u / per_level, q = u - l * per_level;
+      Rec *r = recs + (int64_t)s * L + l;
+      const CellW c = cell_of(l);
+      const double n = s_pl[l] * 1.0e6 / (kKB * s_Tl[l]);
+      if (q < S) {
+        double off[4], w[4];
+        for (int k = 0; k < 4; ++k) {
+          int row;
+          slot_corner(c, k, tv.nP, row, w[k]);
+          off[k] = tv.off[q * rows_per_species + row];
+        }
+        const double cq = w[0] * off[0] + w[1] * off[1] + w[2] * off[2] + w[3] * off[3];
+        r->a_s[q] = (Real)(s_x[q] * n * exp2(cq));
+      } else {
+        const int qc = q - S;
+        double cq = 0.0;
+        for (int k = 0; k < 2; ++k) {
+          int row;
+          double w;
+          cia_slot(c, k, row, w);
+          cq += w * tv.off_cia[qc * tv.nT + row];
+        }
+        const double nh2 = h2 * n, nhe = he * n;
+        r->a_cia[qc] = (Real)((qc == 0 ? nh2 * nh2 : nh2 * nhe) * exp2(cq));
+      }
     }
   }
 }
 
 hipError_t launch_levels(const TableView &tv, const ColumnsView &cv, void *recs, int *status,
                          bool fp64, hipStream_t stream) {
-  const dim3 grid((unsigned)cv.B);
+  // one workgroup per kLevelThreads items of a set: every item runs at once
+  const int64_t items = (int64_t)cv.L * (1 + tv.S + tv.n_cia);
+  const int threads = (int)std::min<int64_t>(kLevelThreads, (items + 63) / 64 * 64);
+  const int per_set = (int)((items + threads - 1) / threads);
+  const dim3 grid((unsigned)((int64_t)cv.B * per_set));
   if (fp64)
-    hipLaunchKernelGGL(k_levels<double>, grid, dim3(kLevelThreads), 0, stream, tv, cv,
-                       (LevelRecD *)recs, status);
+    hipLaunchKernelGGL(k_levels<double>, grid, dim3(threads), 0, stream, tv, cv,
+                       (LevelRecD *)recs, status, per_set);
   else
-    hipLaunchKernelGGL(k_levels<float>, grid, dim3(kLevelThreads), 0, stream, tv, cv,
-                       (LevelRecF *)recs, status);
+    hipLaunchKernelGGL(k_levels<float>, grid, dim3(threads), 0, stream, tv, cv,
+                       (LevelRecF *)recs, status, per_set);
   return hipGetLastError();
 }
 
