@@ -186,3 +186,56 @@ def test_c2_params_lnl(ctx):
     P.close()
     obs.close()
     T.close()
+
+
+def test_params_to_lnl_graph_replay(ctx):
+    """hr2_forward_params_dev with ln L, captured once into a HIP graph after an
+    eager call, replayed with eager work and synchronisations in between, with
+    new parameter vectors copied in between replays: every replay equals an
+    eager call on the same vectors."""
+    tab = tu.c1_table()
+    spec = wl.c1_obs(tab)
+    lay = wl.c1_param_layout(2, 2, with_eps=True)
+    T = hr2.Tables(ctx, tab, "f32")
+    obs = hr2.Obs(ctx, T, spec.window, spec.resolving_power, spec.edges_cm)
+    P = hr2.Params(ctx, T, lay)
+    B = 64
+    th_all = [wl.draw_theta(lay, B, seed=900 + r) for r in range(3)]
+    ref0 = oracle.forward(tab, oracle_column(lay, th_all[0][0])[0], spec.window,
+                          spec.resolving_power, spec.edges_cm, 3)["bins"]
+    D, sigma = wl.noisy_data(ref0, seed=4)
+    obs.set_data(D, sigma)
+    for th in th_all:
+        th[:, -1] = np.log10(float(sigma[0]) ** 2)
+    theta = dev(th_all[0])
+    bins = torch.empty(B * obs.n_bins, dtype=torch.float32, device="cuda")
+    lnl = torch.empty(B, dtype=torch.float64, device="cuda")
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        hr2.forward_params_dev(ctx, T, obs, P, theta, 3, bins, lnl, None, s)
+        s.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=s):
+            hr2.forward_params_dev(ctx, T, obs, P, theta, 3, bins, lnl, None, s)
+    torch.cuda.synchronize()
+    for rep, th in enumerate(th_all):
+        say(f"replay {rep}")
+        theta.copy_(dev(th))
+        want_l = torch.empty_like(lnl)
+        want_b = torch.empty_like(bins)
+        hr2.forward_params_dev(ctx, T, obs, P, theta, 3, want_b, want_l)
+        torch.cuda.synchronize()
+        bins.zero_()
+        lnl.zero_()
+        junk = torch.randn(1 << 16, device="cuda").sum()
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(bins, want_b) and torch.equal(lnl, want_l), rep
+        del junk
+    del g
+    torch.cuda.synchronize()
+    P.close()
+    obs.close()
+    T.close()
