@@ -142,6 +142,7 @@ def main():
                     help="c2: add a gray cloud (tau 5, top 0.3 bar, bottom 3 bar) to the column")
     ap.add_argument("--rate", type=float, default=2000.0, help="c5 arrival rate, requests/s")
     ap.add_argument("--duration", type=float, default=10.0, help="c5 trace length, s")
+    ap.add_argument("--rates", default="", help="c5: comma-separated arrival rates to sweep")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
@@ -460,25 +461,10 @@ def run_params(args):
                       "table_storage": args.dtype, "rows": rows}))
 
 
-def run_c5(args):
-    """Poisson arrivals of uneven requests against the FP16-table server;
-    then the plain FP32 one-request-at-a-time path on a sample of them."""
+def _serve_trace(hr2, srv, trace):
+    """Submit a trace at its arrival times, collect every result; returns
+    (latencies, done times, submit times, failures, submit-loop end)."""
     import threading
-    import torch
-    import workloads as wl
-    from paper_1910_01070_amd import hr2
-    tab = wl.c2_table(n_nu=args.n_nu)
-    log("generating the trace")
-    trace = wl.c5_trace_packed(tab, rate_hz=args.rate, duration_s=args.duration)
-    log(f"  {len(trace)} requests")
-    ctx = hr2.Context(0)
-    T16 = hr2.Tables(ctx, tab, args.dtype if args.dtype != "f32" else "f16")
-    srv = hr2.Server(ctx, T16, 16 << 30, 512)
-    # warm the kernels once
-    r = trace[0]
-    t = srv.submit_packed(r.obs.window, r.obs.resolving_power, r.obs.edges_cm, r.p, r.T, r.x,
-                          r.log_g, r.scale)
-    srv.poll(t, r.n_sets * r.obs.n_bins, wait_s=60.0)
     tickets = [None] * len(trace)
     lat, done_t, sub_t = [], [], []
     fails = [0]
@@ -505,11 +491,52 @@ def run_c5(args):
                                        rq.p, rq.T, rq.x, rq.log_g, rq.scale)
     t_sub_end = time.perf_counter() - t0
     th.join()
-    stats = srv.stats()
-    srv.close()
-    span = max(done_t) - min(sub_t)
-    work = sum(rq.layer_nu for rq in trace)
-    lat = np.array(lat)
+    return np.array(lat), done_t, sub_t, fails[0], t_sub_end
+
+
+def run_c5(args):
+    """Poisson arrivals of uneven requests against the FP16-table server;
+    then the plain FP32 one-request-at-a-time path on a sample of them.
+    With --rates, a sweep of arrival rates (one fresh server each) instead."""
+    import torch
+    import workloads as wl
+    from paper_1910_01070_amd import hr2
+    tab = wl.c2_table(n_nu=args.n_nu)
+    ctx = hr2.Context(0)
+    T16 = hr2.Tables(ctx, tab, args.dtype if args.dtype != "f32" else "f16")
+    rates = [float(v) for v in args.rates.split(",")] if args.rates else [args.rate]
+    rows = []
+    for rate in rates:
+        log(f"trace at {rate:g} req/s for {args.duration:g} s")
+        trace = wl.c5_trace_packed(tab, rate_hz=rate, duration_s=args.duration)
+        srv = hr2.Server(ctx, T16, 16 << 30, 512)
+        r = trace[0]   # warm the kernels once
+        t = srv.submit_packed(r.obs.window, r.obs.resolving_power, r.obs.edges_cm, r.p, r.T,
+                              r.x, r.log_g, r.scale)
+        srv.poll(t, r.n_sets * r.obs.n_bins, wait_s=60.0)
+        lat, done_t, sub_t, fails, t_sub_end = _serve_trace(hr2, srv, trace)
+        stats = srv.stats()
+        srv.close()
+        span = max(done_t) - min(sub_t)
+        work = sum(rq.layer_nu for rq in trace)
+        strided = sum(rq.layer_nu for rq in trace if rq.obs.window.stride > 1)
+        rows.append({
+            "rate_req_per_s": rate, "requests": len(trace), "failed": fails,
+            "offered_layer_nu_per_s": work / args.duration,
+            "served_layer_nu_per_s": work / span,
+            "served_requests_per_s": len(lat) / span,
+            "latency_s": {"p50": float(np.percentile(lat, 50)),
+                          "p99": float(np.percentile(lat, 99))},
+            "drain_s_after_last_arrival": max(done_t) - min(sub_t) - t_sub_end,
+            "steps": stats.steps, "max_admitted": stats.max_inflight,
+            "peak_bytes": stats.peak_bytes, "strided_work_frac": strided / work})
+        log(rows[-1])
+    desc = ("C5 serving trace: Poisson arrivals, 50-200 layers, 20k-150k point windows at 0.1 or "
+            "1 cm^-1, R 100-1000, 1-64 sets per request, FP16 tables resident")
+    if args.rates:
+        print(json.dumps({"workload": desc + f", {args.duration:g} s per rate",
+                          "rate_sweep": rows}))
+        return
     # the plain FP32 path: one request at a time, synchronous, same requests
     T32 = hr2.Tables(ctx, tab, "f32")
     sample = trace[: min(len(trace), 200)]
@@ -524,20 +551,11 @@ def run_c5(args):
         obs.close()
     t_plain = time.perf_counter() - t0
     plain_rate = sum(rq.layer_nu for rq in sample) / t_plain
-    print(json.dumps({
-        "workload": f"C5 serving trace: Poisson {args.rate:g} req/s for {args.duration:g} s, "
-                    "50-200 layers, 20k-150k point windows at 0.1 or 1 cm^-1, R 100-1000, "
-                    "1-64 sets per request, FP16 tables resident",
-        "requests": len(trace), "failed": fails[0],
-        "offered_layer_nu_per_s": work / args.duration,
-        "served_layer_nu_per_s": work / span,
-        "served_requests_per_s": len(lat) / span,
-        "latency_s": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
-        "drain_s_after_last_arrival": max(done_t) - min(sub_t) - t_sub_end,
-        "steps": stats.steps, "max_admitted": stats.max_inflight, "peak_bytes": stats.peak_bytes,
-        "plain_fp32_one_at_a_time_layer_nu_per_s": plain_rate,
-        "speedup_vs_plain_fp32": (work / span) / plain_rate,
-    }))
+    res = dict(rows[0])
+    res["workload"] = desc + f", {args.rate:g} req/s for {args.duration:g} s"
+    res["plain_fp32_one_at_a_time_layer_nu_per_s"] = plain_rate
+    res["speedup_vs_plain_fp32"] = res["served_layer_nu_per_s"] / plain_rate
+    print(json.dumps(res))
 
 
 if __name__ == "__main__":

@@ -618,36 +618,43 @@ hr2_status plan_obs(const hr2_tables *t, const hr2_window &w, double R, int n_bi
     if (e > 0 && pl.idx[e] <= pl.idx[e - 1])
       return set_error(HR2_E_INVALID_ARG, "snapped bin edges must be strictly increasing");
   }
-  // 5 sigma half widths of the points the bins use (same FP64 test as the
-  // definition: keep k with k dnu <= 5 sigma_i).
+  // 5 sigma half widths (the same FP64 test as the definition: the largest k
+  // with k dnu <= 5 sigma_i).  The device computes them for every point with
+  // the same operations; the host needs them only at the bin edges: 5 sigma
+  // grows by less than one grid step per point when R > 5 / (2 sqrt(2 ln 2)),
+  // so i - h_i and i + h_i never decrease and each bin's support runs from
+  // its first edge's reach to its last edge's.
   pl.i0 = pl.idx[0];
   pl.n_pts = pl.idx[n_bins] - pl.i0 + 1;
-  pl.h.assign(pl.n_pts, 0);
-  const double denom = R * 2.0 * std::sqrt(2.0 * std::log(2.0));
-  // 5 sigma grows by less than one grid step per point, so h is found
-  // incrementally from its neighbour (the test itself is unchanged)
-  int64_t hh = -1;
-  for (int64_t q = 0; q < pl.n_pts; ++q) {
-    const int64_t i = pl.i0 + q;
-    const double sig = (pl.first + (double)i * pl.dnu) / denom;
-    if (hh < 0) {
-      const double hv = std::floor(5.0 * sig / pl.dnu);
-      if (!(hv < 1e9)) return set_error(HR2_E_OUT_OF_RANGE, "instrument profile too wide");
-      hh = (int64_t)hv;
-    }
+  pl.denom = R * 2.0 * std::sqrt(2.0 * std::log(2.0));
+  auto half_width = [&](int64_t i) -> int64_t {
+    const double sig = (pl.first + (double)i * pl.dnu) / pl.denom;
+    const double hv = std::floor(5.0 * sig / pl.dnu);
+    int64_t hh = hv < 1e9 ? (int64_t)hv : (int64_t)1e9;
     while ((double)(hh + 1) * pl.dnu <= 5.0 * sig) ++hh;
     while (hh > 0 && (double)hh * pl.dnu > 5.0 * sig) --hh;
-    pl.h[q] = (int32_t)std::min<int64_t>(hh, pl.N);
-  }
+    return std::min<int64_t>(hh, pl.N);
+  };
+  if (!(5.0 * ((pl.first + (double)pl.idx[n_bins] * pl.dnu) / pl.denom) / pl.dnu < 1e9))
+    return set_error(HR2_E_OUT_OF_RANGE, "instrument profile too wide");
+  const bool monotone = R > 2.2;
   pl.kstart.assign(n_bins, 0);
   pl.mlo.assign(n_bins, 0);
   pl.mlen.assign(n_bins, 0);
   pl.nnz = 0;
   for (int j = 0; j < n_bins; ++j) {
-    int64_t lo = INT64_MAX, hi = INT64_MIN;
-    for (int64_t i = pl.idx[j]; i <= pl.idx[j + 1]; ++i) {
-      lo = std::min(lo, std::max<int64_t>(0, i - pl.h[i - pl.i0]));
-      hi = std::max(hi, std::min<int64_t>(pl.N - 1, i + pl.h[i - pl.i0]));
+    int64_t lo, hi;
+    if (monotone) {
+      lo = std::max<int64_t>(0, pl.idx[j] - half_width(pl.idx[j]));
+      hi = std::min<int64_t>(pl.N - 1, pl.idx[j + 1] + half_width(pl.idx[j + 1]));
+    } else {
+      lo = INT64_MAX;
+      hi = INT64_MIN;
+      for (int64_t i = pl.idx[j]; i <= pl.idx[j + 1]; ++i) {
+        const int64_t h = half_width(i);
+        lo = std::min(lo, std::max<int64_t>(0, i - h));
+        hi = std::max(hi, std::min<int64_t>(pl.N - 1, i + h));
+      }
     }
     pl.kstart[j] = pl.nnz;
     pl.mlo[j] = (int32_t)lo;
@@ -701,10 +708,8 @@ extern "C" hr2_status hr2_obs_create(hr2_ctx *ctx, const hr2_tables *t, hr2_wind
     e = hipMemcpyAsync(d_edges, pl.idx.data(), (n_bins + 1) * sizeof(int64_t),
                        hipMemcpyHostToDevice, s);
   if (e == hipSuccess)
-    e = hipMemcpyAsync(d_h, pl.h.data(), n_pts * sizeof(int32_t), hipMemcpyHostToDevice, s);
-  if (e == hipSuccess)
-    e = launch_obs_build(o->fp64, pl.N, pl.first, pl.dnu, R, n_bins, nnz,
-                         (const int64_t *)d_edges, (const int32_t *)d_h, pl.i0, n_pts, d_q, d_z,
+    e = launch_obs_build(o->fp64, pl.N, pl.first, pl.dnu, pl.denom, n_bins, nnz,
+                         (const int64_t *)d_edges, (int32_t *)d_h, pl.i0, n_pts, d_q, d_z,
                          o->d_kstart, o->d_mlo, o->d_K, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (d_edges) (void)hipFree(d_edges);

@@ -63,7 +63,7 @@ struct ObsPlan {
   double first = 0, dnu = 0, R = 0;
   int n_bins = 0;
   std::vector<int64_t> idx;      // snapped edges [n_bins + 1]
-  std::vector<int32_t> h;        // 5 sigma half widths of points i0 .. i0 + n_pts - 1
+  double denom = 0;              // R 2 sqrt(2 ln 2): sigma_i = nu_i / denom
   std::vector<int64_t> kstart;   // [n_bins]
   std::vector<int32_t> mlo, mlen;
 };

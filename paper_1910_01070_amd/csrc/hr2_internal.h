@@ -180,13 +180,14 @@ hipError_t launch_unpack(const ParamView &pv, int n_sets, const double *theta, d
                          double *T, double *x, double *logg, double *scale, double *cloud,
                          double *eps, hipStream_t stream);
 
-// Observation layout build: Z_i and q_i for window points [i0, i0 + n_pts),
-// then the nnz banded per-bin weights.
-hipError_t launch_obs_build(bool fp64, int64_t N, double nu_first, double dnu_eff, double R,
-                            int n_bins, int64_t nnz, const int64_t *edge_idx_dev,
-                            const int32_t *h_dev, int64_t i0, int64_t n_pts, void *q_scratch,
-                            void *invz_scratch, const int64_t *kstart_dev, const int32_t *mlo_dev,
-                            void *K_dev, hipStream_t stream);
+// Observation layout build: the 5 sigma half widths h_i (written to h_dev),
+// Z_i and q_i for window points [i0, i0 + n_pts), then the nnz banded
+// per-bin weights.  sigma_i = nu_i / denom.
+hipError_t launch_obs_build(bool fp64, int64_t N, double nu_first, double dnu_eff, double denom,
+                            int n_bins, int64_t nnz, const int64_t *edge_idx_dev, int32_t *h_dev,
+                            int64_t i0, int64_t n_pts, void *q_scratch, void *invz_scratch,
+                            const int64_t *kstart_dev, const int32_t *mlo_dev, void *K_dev,
+                            hipStream_t stream);
 
 }  // namespace hr2
 

@@ -1196,15 +1196,29 @@ hipError_t launch_unpack(const ParamView &pv, int n_sets, const double *theta, d
 // (trapezoid rule over the bin's points, divided by its width).
 template <typename Real>
 __global__ __launch_bounds__(256) void k_obs_norm(int64_t N, double nu_first, double dnu,
-                                                  double R, const int32_t *h, int64_t i0,
+                                                  double denom, int32_t *h, int64_t i0,
                                                   int64_t n, Real *q_out, Real *invz_out) {
   // one wave per window point: lanes split the 2h+1 taps, fixed butterfly sum
   const int64_t t = (int64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (t >= n) return;
   const int64_t i = i0 + t;
-  const double sig = (nu_first + (double)i * dnu) / (R * 2.0 * sqrt(2.0 * log(2.0)));
-  const int hi = h[t];
+  // the 5 sigma cut decides which taps exist: the same FP64 operations as the
+  // host's plan (no contraction into fused multiply-adds), so both find the
+  // same largest k with k dnu <= 5 sigma_i
+  double sig;
+  int hi;
+  {
+#pragma clang fp contract(off)
+    sig = (nu_first + (double)i * dnu) / denom;
+    const double lim = 5.0 * sig;
+    const double hv = floor(lim / dnu);
+    int64_t hh = hv < 1e9 ? (int64_t)hv : (int64_t)1e9;
+    while ((double)(hh + 1) * dnu <= lim) ++hh;
+    while (hh > 0 && (double)hh * dnu > lim) --hh;
+    hi = (int)(hh < N ? hh : N);
+  }
+  if (lane == 0) h[t] = hi;
   int64_t klo = -hi, khi = hi;
   if (i + klo < 0) klo = -i;
   if (i + khi > N - 1) khi = N - 1 - i;
@@ -1272,22 +1286,22 @@ __global__ __launch_bounds__(256) void k_obs_weights(int n_bins, int64_t nnz,
   K[e] = acc * (Real)(1.0 / (double)(b - a));
 }
 
-hipError_t launch_obs_build(bool fp64, int64_t N, double nu_first, double dnu_eff, double R,
-                            int n_bins, int64_t nnz, const int64_t *edge_idx_dev,
-                            const int32_t *h_dev, int64_t i0, int64_t n_pts, void *q_scratch,
-                            void *invz_scratch, const int64_t *kstart_dev, const int32_t *mlo_dev,
-                            void *K_dev, hipStream_t stream) {
+hipError_t launch_obs_build(bool fp64, int64_t N, double nu_first, double dnu_eff, double denom,
+                            int n_bins, int64_t nnz, const int64_t *edge_idx_dev, int32_t *h_dev,
+                            int64_t i0, int64_t n_pts, void *q_scratch, void *invz_scratch,
+                            const int64_t *kstart_dev, const int32_t *mlo_dev, void *K_dev,
+                            hipStream_t stream) {
   const dim3 g1((unsigned)((n_pts + 3) / 4));
   const dim3 g2((unsigned)((nnz + 255) / 256));
   if (fp64) {
-    hipLaunchKernelGGL(k_obs_norm<double>, g1, dim3(256), 0, stream, N, nu_first, dnu_eff, R,
+    hipLaunchKernelGGL(k_obs_norm<double>, g1, dim3(256), 0, stream, N, nu_first, dnu_eff, denom,
                        h_dev, i0, n_pts, (double *)q_scratch, (double *)invz_scratch);
     hipLaunchKernelGGL(k_obs_weights<double>, g2, dim3(256), 0, stream, n_bins, nnz,
                        edge_idx_dev, h_dev, i0, (const double *)q_scratch,
                        (const double *)invz_scratch, dnu_eff, kstart_dev, mlo_dev,
                        (double *)K_dev);
   } else {
-    hipLaunchKernelGGL(k_obs_norm<float>, g1, dim3(256), 0, stream, N, nu_first, dnu_eff, R,
+    hipLaunchKernelGGL(k_obs_norm<float>, g1, dim3(256), 0, stream, N, nu_first, dnu_eff, denom,
                        h_dev, i0, n_pts, (float *)q_scratch, (float *)invz_scratch);
     hipLaunchKernelGGL(k_obs_weights<float>, g2, dim3(256), 0, stream, n_bins, nnz, edge_idx_dev,
                        h_dev, i0, (const float *)q_scratch, (const float *)invz_scratch, dnu_eff,

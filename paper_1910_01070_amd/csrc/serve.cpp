@@ -175,8 +175,8 @@ void layout_request(const hr2_tables *t, Req &r) {
   r.o_mlo = take(r.n_bins * sizeof(int32_t));
   r.o_mlen = take(r.n_bins * sizeof(int32_t));
   r.o_edges = take((r.n_bins + 1) * sizeof(int64_t));
-  r.o_h = take(r.plan.n_pts * sizeof(int32_t));
   r.upload = o;
+  r.o_h = take(r.plan.n_pts * sizeof(int32_t));   // written by the layout build
   r.o_recs = take((size_t)r.n_sets * r.L * rec_bytes(t));
   r.o_fplus = take((size_t)r.n_sets * r.window.nu_count * rs);
   r.bins_bytes = (size_t)r.n_sets * r.n_bins * rs;
@@ -196,7 +196,6 @@ void fill_upload_image(const Req &r, unsigned char *img) {
   std::memcpy(img + r.o_mlo, r.plan.mlo.data(), r.n_bins * sizeof(int32_t));
   std::memcpy(img + r.o_mlen, r.plan.mlen.data(), r.n_bins * sizeof(int32_t));
   std::memcpy(img + r.o_edges, r.plan.idx.data(), (r.n_bins + 1) * sizeof(int64_t));
-  std::memcpy(img + r.o_h, r.plan.h.data(), r.plan.n_pts * sizeof(int32_t));
 }
 
 }  // namespace
@@ -247,9 +246,9 @@ bool hr2_server::launch_step(StepSlot &sl, std::vector<Req *> &reqs) {
       return false;
     const ColumnsView cv = columns_view(blk + r.o_cols, r.n_sets, r.L, tv.S);
     if (launch_levels(tv, cv, blk + r.o_recs, nullptr, fp64, s) != hipSuccess) return false;
-    if (launch_obs_build(fp64, r.plan.N, r.plan.first, r.plan.dnu, r.plan.R, r.n_bins,
+    if (launch_obs_build(fp64, r.plan.N, r.plan.first, r.plan.dnu, r.plan.denom, r.n_bins,
                          r.plan.nnz, (const int64_t *)(blk + r.o_edges),
-                         (const int32_t *)(blk + r.o_h), r.plan.i0, r.plan.n_pts, blk + r.o_q,
+                         (int32_t *)(blk + r.o_h), r.plan.i0, r.plan.n_pts, blk + r.o_q,
                          blk + r.o_z, (const int64_t *)(blk + r.o_kstart),
                          (const int32_t *)(blk + r.o_mlo), blk + r.o_K, s) != hipSuccess)
       return false;
