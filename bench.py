@@ -143,6 +143,8 @@ def main():
     ap.add_argument("--rate", type=float, default=2000.0, help="c5 arrival rate, requests/s")
     ap.add_argument("--duration", type=float, default=10.0, help="c5 trace length, s")
     ap.add_argument("--rates", default="", help="c5: comma-separated arrival rates to sweep")
+    ap.add_argument("--strided-frac", type=float, default=0.5,
+                    help="c5: share of requests on 1 cm^-1 windows (stride 10)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
@@ -508,7 +510,8 @@ def run_c5(args):
     rows = []
     for rate in rates:
         log(f"trace at {rate:g} req/s for {args.duration:g} s")
-        trace = wl.c5_trace_packed(tab, rate_hz=rate, duration_s=args.duration)
+        trace = wl.c5_trace_packed(tab, rate_hz=rate, duration_s=args.duration,
+                                   strided_frac=args.strided_frac)
         srv = hr2.Server(ctx, T16, 16 << 30, 512)
         r = trace[0]   # warm the kernels once
         t = srv.submit_packed(r.obs.window, r.obs.resolving_power, r.obs.edges_cm, r.p, r.T,

@@ -350,10 +350,11 @@ class TraceRequest:
     n_mu: int = 3
 
 
-def c5_request(rng, table: Table, t_arrival=0.0, max_sets=64, span_range=(20_000, 150_000)):
+def c5_request(rng, table: Table, t_arrival=0.0, max_sets=64, span_range=(20_000, 150_000),
+               strided_frac=0.5):
     layers = int(rng.integers(50, 201))
     span = int(rng.integers(span_range[0], min(span_range[1], table.n_nu) + 1))
-    stride = 1 if rng.random() < 0.5 else 10
+    stride = 1 if rng.random() < 1.0 - strided_frac else 10
     begin = int(rng.integers(0, table.n_nu - span + 1))
     count = (span + stride - 1) // stride
     w = Window(begin, count, stride)
@@ -431,7 +432,7 @@ def packed_c2_like_columns(rng, n_sets, n_levels, n_species):
 
 
 def c5_trace_packed(table: Table, rate_hz=2000.0, duration_s=10.0, seed=505, max_sets=64,
-                    span_range=(20_000, 150_000)):
+                    span_range=(20_000, 150_000), strided_frac=0.5):
     rng = np.random.default_rng(seed)
     t = 0.0
     out = []
@@ -439,7 +440,8 @@ def c5_trace_packed(table: Table, rate_hz=2000.0, duration_s=10.0, seed=505, max
         t += rng.exponential(1.0 / rate_hz)
         if t > duration_s:
             break
-        r = c5_request(rng, table, t, max_sets=1, span_range=span_range)
+        r = c5_request(rng, table, t, max_sets=1, span_range=span_range,
+                       strided_frac=strided_frac)
         n_sets = int(rng.integers(1, max_sets + 1))
         L = r.cols[0].n_levels
         p, T, x, lg, sc = packed_c2_like_columns(rng, n_sets, L, table.n_species)
