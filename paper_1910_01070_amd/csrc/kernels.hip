@@ -147,6 +147,7 @@ __global__ __launch_bounds__(kLevelThreads) void k_levels(TableView tv, ColumnsV
   __shared__ double s_T[kMaxAxis], s_lp[kMaxAxis];
   __shared__ double s_pl[HR2_MAX_LEVELS], s_Tl[HR2_MAX_LEVELS];
   __shared__ double s_x[kMaxSpecies], s_m[kMaxSpecies];
+  __shared__ CellW s_cell[HR2_MAX_LEVELS];
   // blocks_per_set workgroups share one set's items; each stages the set
   const int s = blockIdx.x / blocks_per_set;
   const int part = blockIdx.x - s * blocks_per_set;
@@ -194,23 +195,27 @@ __global__ __launch_bounds__(kLevelThreads) void k_levels(TableView tv, ColumnsV
   if (status != nullptr && threadIdx.x == 0 && part == 0)
     status[s] = bad ? (int)HR2_E_INVALID_ARG : 0;
 
+  // every level's table cell, once per workgroup
+  for (int l = threadIdx.x; l < L; l += blockDim.x) {
+    CellW c;
+    locate_lds(s_T, tv.nT, s_Tl[l], c.iT, c.wT);
+    locate_lds(s_lp, tv.nP, log10(s_pl[l]), c.ip, c.wp);
+    s_cell[l] = c;
+  }
+  __syncthreads();
+
   const double h2 = (1.0 - xs) / (1.0 + tv.he_ratio);
   const double he = tv.he_ratio * h2;
   mm += h2 * kMH2 + he * kMHe;
   const int64_t rows_per_species = (int64_t)tv.nT * tv.nP;
   const uint32_t row_bytes = (uint32_t)(tv.pitch * tv.tab_elem);
   const uint32_t cia_row_bytes = (uint32_t)(tv.pitch * tv.cia_elem);
-  auto cell_of = [&](int l) {
-    CellW c;
-    locate_lds(s_T, tv.nT, s_Tl[l], c.iT, c.wT);
-    locate_lds(s_lp, tv.nP, log10(s_pl[l]), c.ip, c.wp);
-    return c;
-  };
+  auto cell_of = [&](int l) { return s_cell[l]; };
 
   // Items: first one per level (everything but the species factors), then
-  // one per (level, species or CIA pair).  Each item finds the cells it needs
-  // itself, so no item waits for another and the table offsets are fetched
-  // while the level items run.  Items write disjoint fields of the records.
+  // one per (level, species or CIA pair); no item waits for another, so the
+  // table offsets are fetched while the level items run.  Items write
+  // disjoint fields of the records.
   const int per_level = S + tv.n_cia;
   const int n_items = L * (1 + per_level);
   for (int t = part * blockDim.x + threadIdx.x; t < n_items; t += blocks_per_set * blockDim.x) {
