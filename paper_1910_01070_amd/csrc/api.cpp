@@ -176,20 +176,6 @@ hr2_status stage_upload(hr2_ctx *ctx, DevBuf &dst, const void *src, size_t bytes
   return HR2_OK;
 }
 
-// Upload descriptors unless the device copy already holds the same bytes.
-hr2_status upload_cached(hr2_ctx *ctx, DevBuf &dst, std::vector<unsigned char> &shadow,
-                         const void *src, size_t bytes, hipStream_t stream) {
-  if (shadow.size() == bytes && dst.ptr != nullptr && std::memcmp(shadow.data(), src, bytes) == 0)
-    return HR2_OK;
-  hr2_status st = stage_upload(ctx, dst, src, bytes, stream);
-  if (st != HR2_OK) {
-    shadow.clear();
-    return st;
-  }
-  shadow.assign((const unsigned char *)src, (const unsigned char *)src + bytes);
-  return HR2_OK;
-}
-
 }  // namespace hr2
 
 // ----------------------------------------------------------------- context
@@ -224,8 +210,6 @@ extern "C" void hr2_ctx_destroy(hr2_ctx *ctx) {
   ctx->recs.release();
   ctx->fplus.release();
   ctx->cols.release();
-  ctx->segs.release();
-  ctx->convsegs.release();
   ctx->terms.release();
   ctx->unpacked.release();
   if (ctx->pinned) (void)hipHostFree(ctx->pinned);
@@ -832,10 +816,8 @@ extern "C" hr2_status hr2_rt_emission(hr2_ctx *ctx, const hr2_tables *t, const h
   seg.chunks = chunks;
   const int per_wg = column_nu_per_wg(chunks);
   seg.tiles_per_set = (int32_t)((w.nu_count + per_wg - 1) / per_wg);
-  if ((st = upload_cached(ctx, ctx->segs, ctx->segs_shadow, &seg, sizeof(seg), s)) != HR2_OK)
-    return st;
-  HIP_TRY(launch_column(t->view, (const ColSeg *)ctx->segs.ptr, 1, seg.tiles_per_set, chunks,
-                        ctx->recs.ptr, chi, fplus, n_mu, true, ctx->opt_source == 2, s));
+  HIP_TRY(launch_column(t->view, nullptr, 1, &seg, seg.tiles_per_set, chunks, ctx->recs.ptr, chi,
+                        fplus, n_mu, true, ctx->opt_source == 2, s));
   return ctx_end(ctx, s);
 }
 
@@ -859,10 +841,7 @@ extern "C" hr2_status hr2_convolve_bin(hr2_ctx *ctx, const hr2_obs *o, const voi
   cs.scale_const = scale;
   cs.n_sets = 1;
   cs.n_bins = o->n_bins;
-  if ((st = upload_cached(ctx, ctx->convsegs, ctx->convsegs_shadow, &cs, sizeof(cs), s)) != HR2_OK)
-    return st;
-  HIP_TRY(launch_convolve_bin(o->fp64, (const ConvSeg *)ctx->convsegs.ptr, 1, o->n_bins, fplus,
-                              bins, s));
+  HIP_TRY(launch_convolve_bin(o->fp64, nullptr, 1, &cs, o->n_bins, fplus, bins, s));
   return ctx_end(ctx, s);
 }
 
@@ -937,11 +916,9 @@ hr2_status run_forward(hr2_ctx *ctx, const hr2_tables *t, const hr2_obs *o, cons
   seg.tiles_per_set = (int32_t)((w.nu_count + per_wg - 1) / per_wg);
   const int64_t total_wgs = (int64_t)B * seg.tiles_per_set;
   if (total_wgs > 0x7fffffff) return set_error(HR2_E_OUT_OF_RANGE, "launch too large");
-  if ((st = upload_cached(ctx, ctx->segs, ctx->segs_shadow, &seg, sizeof(seg), s)) != HR2_OK)
-    return st;
   if (timed) HIP_TRY(hipEventRecord(ev[1], s));
-  HIP_TRY(launch_column(t->view, (const ColSeg *)ctx->segs.ptr, 1, total_wgs, chunks,
-                        ctx->recs.ptr, nullptr, fplus, n_mu, false, ctx->opt_source == 2, s));
+  HIP_TRY(launch_column(t->view, nullptr, 1, &seg, total_wgs, chunks, ctx->recs.ptr, nullptr,
+                        fplus, n_mu, false, ctx->opt_source == 2, s));
   ConvSeg cs{};
   cs.item_begin = 0;
   cs.K = o->d_K;
@@ -961,11 +938,8 @@ hr2_status run_forward(hr2_ctx *ctx, const hr2_tables *t, const hr2_obs *o, cons
     cs.log10_eps = like->log10_eps;
     cs.terms = (double *)ctx->terms.ptr;
   }
-  if ((st = upload_cached(ctx, ctx->convsegs, ctx->convsegs_shadow, &cs, sizeof(cs), s)) != HR2_OK)
-    return st;
   if (timed) HIP_TRY(hipEventRecord(ev[2], s));
-  HIP_TRY(launch_convolve_bin(o->fp64, (const ConvSeg *)ctx->convsegs.ptr, 1,
-                              (int64_t)B * o->n_bins, fplus, bins, s));
+  HIP_TRY(launch_convolve_bin(o->fp64, nullptr, 1, &cs, (int64_t)B * o->n_bins, fplus, bins, s));
   if (like) HIP_TRY(launch_lnl_reduce(cs.terms, B, o->n_bins, like->lnl, s));
   if (timed) {
     HIP_TRY(hipEventRecord(ev[3], s));

@@ -39,8 +39,7 @@ struct hr2_ctx {
   int64_t timing_calls = 0;
   std::vector<hipEvent_t> tev;     // 4 events per timed call
   size_t tev_used = 0;             // events recorded since the last collection
-  hr2::DevBuf recs, fplus, cols, segs, convsegs, terms, unpacked;
-  std::vector<unsigned char> segs_shadow, convsegs_shadow;
+  hr2::DevBuf recs, fplus, cols, terms, unpacked;
 };
 
 namespace hr2 {

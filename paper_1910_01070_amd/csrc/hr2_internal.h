@@ -154,10 +154,11 @@ hipError_t launch_levels(const TableView &tv, const ColumnsView &cv, void *recs,
 // One workgroup = `chunks` waves = one 64-point tile of one set; every
 // segment of the launch must use that chunk count.
 // para: parabolic source (else linear).
+// seg0_host: a launch of one segment passes it by value (segs_dev unused).
 hipError_t launch_column(const TableView &tv, const ColSeg *segs_dev, int n_segs,
-                         int64_t total_wgs, int chunks, const void *recs, const void *chi_in,
-                         void *out, int max_mu, bool opacity_from_memory, bool para,
-                         hipStream_t stream);
+                         const ColSeg *seg0_host, int64_t total_wgs, int chunks, const void *recs,
+                         const void *chi_in, void *out, int max_mu, bool opacity_from_memory,
+                         bool para, hipStream_t stream);
 int column_nu_per_wg(int chunks);
 // Waves of the column kernel (with this chunk count) the device holds at once.
 int column_wave_capacity(const TableView &tv, int max_mu, bool opacity_from_memory, int chunks,
@@ -168,8 +169,8 @@ hipError_t launch_opacity_only(const TableView &tv, const void *recs, int n_leve
                                void *chi, hipStream_t stream);
 
 hipError_t launch_convolve_bin(bool fp64, const ConvSeg *segs_dev, int n_segs,
-                               int64_t total_items, const void *in, void *out,
-                               hipStream_t stream);
+                               const ConvSeg *seg0_host, int64_t total_items, const void *in,
+                               void *out, hipStream_t stream);
 // ln L per set: the sum over bins of the terms k_convolve_bin wrote.
 hipError_t launch_lnl_reduce(const double *terms, int n_sets, int n_bins, double *lnl,
                              hipStream_t stream);

@@ -554,7 +554,7 @@ __device__ __forceinline__ double sc_para_d(double I, double dtau_u, double dtau
 // chunk below the top reads one level past its end).
 template <typename Real, typename TT, int NSS, int MAXMU, bool FROM_CHI, bool BIG, bool PARA>
 __global__ __launch_bounds__(512) void k_column(TableView tv, const ColSeg *__restrict__ segs,
-                                                int n_segs, int64_t total_wgs,
+                                                int n_segs, ColSeg seg0, int64_t total_wgs,
                                                 const void *__restrict__ recs_v,
                                                 const void *__restrict__ chi_in_v,
                                                 void *__restrict__ out_v) {
@@ -570,6 +570,7 @@ __global__ __launch_bounds__(512) void k_column(TableView tv, const ColSeg *__re
   Real *sh = (Real *)sh_raw;
 
   const int64_t g = xcd_remap(blockIdx.x, total_wgs);
+  // n_segs == 0: the launch is the one segment passed by value; otherwise
   // the segment holding workgroup g: last one with wg_begin <= g (ascending)
   int sg = 0;
   for (int lo = 0, hi = n_segs; hi - lo > 1;) {
@@ -578,7 +579,7 @@ __global__ __launch_bounds__(512) void k_column(TableView tv, const ColSeg *__re
     else hi = mid;
     sg = lo;
   }
-  const ColSeg &d = segs[sg];
+  const ColSeg d = n_segs == 0 ? seg0 : segs[sg];
   const int n_sets = d.n_sets;
   const int C = blockDim.x >> 6;   // one wave per layer chunk (the segment's chunks)
   const int64_t local = g - d.wg_begin;
@@ -842,8 +843,8 @@ __global__ __launch_bounds__(512) void k_column(TableView tv, const ColSeg *__re
 
 int column_nu_per_wg(int) { return 64; }
 
-using ColumnFn = void (*)(TableView, const ColSeg *, int, int64_t, const void *, const void *,
-                         void *);
+using ColumnFn = void (*)(TableView, const ColSeg *, int, ColSeg, int64_t, const void *,
+                          const void *, void *);
 struct ColumnKernel {
   ColumnFn fn;
   int max_mu;
@@ -901,14 +902,15 @@ static size_t column_shmem(const ColumnKernel &k, int chunks) {
 }
 
 hipError_t launch_column(const TableView &tv, const ColSeg *segs_dev, int n_segs,
-                         int64_t total_wgs, int chunks, const void *recs, const void *chi_in,
-                         void *out, int max_mu, bool opacity_from_memory, bool para,
-                         hipStream_t stream) {
+                         const ColSeg *seg0_host, int64_t total_wgs, int chunks, const void *recs,
+                         const void *chi_in, void *out, int max_mu, bool opacity_from_memory,
+                         bool para, hipStream_t stream) {
   if (total_wgs <= 0) return hipSuccess;
   const ColumnKernel k = pick_column(tv, max_mu, opacity_from_memory, para);
+  const ColSeg seg0 = seg0_host ? *seg0_host : ColSeg{};
   hipLaunchKernelGGL(k.fn, dim3((unsigned)total_wgs), dim3(64 * chunks),
-                     column_shmem(k, chunks), stream, tv, segs_dev, n_segs, total_wgs, recs,
-                     chi_in, out);
+                     column_shmem(k, chunks), stream, tv, segs_dev, seg0_host ? 0 : n_segs, seg0,
+                     total_wgs, recs, chi_in, out);
   return hipGetLastError();
 }
 
@@ -1012,7 +1014,8 @@ hipError_t launch_opacity_only(const TableView &tv, const void *recs, int n_leve
 // not depend on what else is in the launch.
 template <typename Real>
 __global__ __launch_bounds__(256) void k_convolve_bin(const ConvSeg *__restrict__ segs,
-                                                      int n_segs, int64_t total_items,
+                                                      int n_segs, ConvSeg seg0,
+                                                      int64_t total_items,
                                                       const Real *__restrict__ in,
                                                       Real *__restrict__ out) {
   __shared__ Real part[4];
@@ -1024,7 +1027,7 @@ __global__ __launch_bounds__(256) void k_convolve_bin(const ConvSeg *__restrict_
     else hi = mid;
     sg = lo;
   }
-  const ConvSeg &d = segs[sg];
+  const ConvSeg d = n_segs == 0 ? seg0 : segs[sg];   // n_segs == 0: the one segment by value
   const int64_t local = it - d.item_begin;
   const int s = (int)(local / d.n_bins);
   const int jb = (int)(local - (int64_t)s * d.n_bins);
@@ -1068,15 +1071,17 @@ __global__ __launch_bounds__(256) void k_convolve_bin(const ConvSeg *__restrict_
 }
 
 hipError_t launch_convolve_bin(bool fp64, const ConvSeg *segs_dev, int n_segs,
-                               int64_t total_items, const void *in, void *out,
-                               hipStream_t stream) {
+                               const ConvSeg *seg0_host, int64_t total_items, const void *in,
+                               void *out, hipStream_t stream) {
   if (total_items <= 0) return hipSuccess;
   const dim3 grid((unsigned)total_items);
+  const ConvSeg seg0 = seg0_host ? *seg0_host : ConvSeg{};
+  const int ns = seg0_host ? 0 : n_segs;
   if (fp64)
-    hipLaunchKernelGGL(k_convolve_bin<double>, grid, dim3(256), 0, stream, segs_dev, n_segs,
+    hipLaunchKernelGGL(k_convolve_bin<double>, grid, dim3(256), 0, stream, segs_dev, ns, seg0,
                        total_items, (const double *)in, (double *)out);
   else
-    hipLaunchKernelGGL(k_convolve_bin<float>, grid, dim3(256), 0, stream, segs_dev, n_segs,
+    hipLaunchKernelGGL(k_convolve_bin<float>, grid, dim3(256), 0, stream, segs_dev, ns, seg0,
                        total_items, (const float *)in, (float *)out);
   return hipGetLastError();
 }

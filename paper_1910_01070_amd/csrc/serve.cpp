@@ -302,10 +302,10 @@ bool hr2_server::launch_step(StepSlot &sl, std::vector<Req *> &reqs) {
   const ColSeg *dcs = (const ColSeg *)sl.desc.ptr;
   const ConvSeg *dvs = (const ConvSeg *)((unsigned char *)sl.desc.ptr + round256(bytes_c));
   for (const Group &gq : groups)
-    if (launch_column(tv, dcs + gq.first, (int)gq.count, gq.wgs, gq.chunks, base, nullptr, base,
-                      gq.max_mu, false, para, s) != hipSuccess)
+    if (launch_column(tv, dcs + gq.first, (int)gq.count, nullptr, gq.wgs, gq.chunks, base,
+                      nullptr, base, gq.max_mu, false, para, s) != hipSuccess)
       return false;
-  if (launch_convolve_bin(fp64, dvs, (int)vs.size(), waves, base, base, s) != hipSuccess)
+  if (launch_convolve_bin(fp64, dvs, (int)vs.size(), nullptr, waves, base, base, s) != hipSuccess)
     return false;
   for (Req *r : reqs)
     if (hipMemcpyAsync(pbase + r->pin_off + round256(r->upload), base + r->dev_off + r->o_bins,
