@@ -26,8 +26,9 @@ constexpr int kMaxMu = HR2_MAX_MU;
 struct alignas(16) LevelRecF {
   float w[4];            // slot weights (bilinear corner weights)
   uint32_t rowb[4];      // byte offset of each slot's row in a species block: (iT n_p + ip) pitch b
-  int32_t mask;          // bit k < 4: species slot k changes here; bit 4 + q: CIA slot q;
-                         // bits 8 + k, 12 + q: the slot's weight is nonzero
+  int32_t mask;          // bit k < 4: species slot k changes here (coming from level l-1);
+                         // bit 4 + q: CIA slot q; bits 8 + k, 12 + q: the slot's weight is
+                         // nonzero; bits 16 + k, 20 + q: as bits k, 4 + q coming from l+1
   uint32_t cia_rowb[2];  // byte offset of each CIA slot's row (T node) in a pair block
   float cia_w[2];        // CIA slot weights
   float a_cia[2];        // n_H2^2 2^{c}, n_H2 n_He 2^{c'} (c: interpolated row offsets)

@@ -223,32 +223,39 @@ __global__ __launch_bounds__(kLevelThreads) void k_levels(TableView tv, ColumnsV
       const int l = t;
       Rec *r = recs + (int64_t)s * L + l;
       const CellW c = cell_of(l);
-      const bool has_prev = l > 0;
+      const bool has_prev = l > 0, has_next = l + 1 < L;
       const CellW cp = has_prev ? cell_of(l - 1) : c;
+      const CellW cn = has_next ? cell_of(l + 1) : c;
       int mask = 0;
       for (int k = 0; k < 4; ++k) {
-        int row, rowp;
-        double w, wp;
+        int row, rowp, rown;
+        double w, wp, wn;
         slot_corner(c, k, tv.nP, row, w);
         slot_corner(cp, k, tv.nP, rowp, wp);
+        slot_corner(cn, k, tv.nP, rown, wn);
         r->w[k] = (Real)w;
         r->rowb[k] = (uint32_t)row * row_bytes;
         const bool nz = w != 0.0;
         const bool kept = has_prev && wp != 0.0 && rowp == row;
+        const bool kept_dn = has_next && wn != 0.0 && rown == row;
         if (nz) mask |= 1 << (8 + k);
         if (nz && !kept) mask |= 1 << k;
+        if (nz && !kept_dn) mask |= 1 << (16 + k);
       }
       for (int k = 0; k < 2; ++k) {
-        int row, rowp;
-        double w, wp;
+        int row, rowp, rown;
+        double w, wp, wn;
         cia_slot(c, k, row, w);
         cia_slot(cp, k, rowp, wp);
+        cia_slot(cn, k, rown, wn);
         r->cia_rowb[k] = (uint32_t)row * cia_row_bytes;
         r->cia_w[k] = (Real)w;
         const bool nz = w != 0.0 && tv.n_cia > 0;
         const bool kept = has_prev && wp != 0.0 && rowp == row;
+        const bool kept_dn = has_next && wn != 0.0 && rown == row;
         if (nz) mask |= 1 << (12 + k);
         if (nz && !kept) mask |= 1 << (4 + k);
+        if (nz && !kept_dn) mask |= 1 << (20 + k);
       }
       r->mask = mask;
       for (int q = S; q < kMaxSpecies; ++q) r->a_s[q] = (Real)0;
@@ -364,34 +371,42 @@ __device__ __forceinline__ double planck_d(double nu, double c1nu3, double T) {
 }
 
 // One layer of Eq. 4-7 for one angle (FP32).  Linear source, alpha = 0,
-// attenuation exp(-Delta), Delta = dtau / mu; beta = 1 - u, gamma = u - e,
-// u = (1 - e)/Delta.  Below Delta = 1/2, beta comes from its Taylor series
-// and gamma = Delta (1 - beta) - beta, e = 1 - Delta (1 - beta), which avoids
-// the cancellation in 1 - u.
-__device__ __forceinline__ float sc_step_f(float I, float dtau, float rdt, float S1, float S0,
-                                           float inv_mu, float l2e_mu, float mu) {
+// attenuation e = exp(-Delta), Delta = dtau / mu, u = (1 - e)/Delta:
+//   I_new = e I + (1 - u) S1 + (u - e) S0 = S1 + e (I - S0) + u (S0 - S1).
+// D = S0 - S1 and rD = D / dtau are per layer.  Below Delta = 1/20, u comes
+// from its series to Delta^3 (truncation < 1e-7) and e = 1 - Delta u, which
+// avoids the cancellation in 1 - e; above, u D = (1 - e) mu rD.
+__device__ __forceinline__ void sc_coef_f(float dtau, float rD, float D, float inv_mu,
+                                          float l2e_mu, float mu, float &e, float &uD) {
   const float d = dtau * inv_mu;
-  float e, beta, gamma;
-  if (d < 0.5f) {
-    float b = -1.0f / 362880.0f;
-    b = fmaf(b, d, 1.0f / 40320.0f);
-    b = fmaf(b, d, -1.0f / 5040.0f);
-    b = fmaf(b, d, 1.0f / 720.0f);
-    b = fmaf(b, d, -1.0f / 120.0f);
-    b = fmaf(b, d, 1.0f / 24.0f);
-    b = fmaf(b, d, -1.0f / 6.0f);
-    b = fmaf(b, d, 0.5f);
-    beta = b * d;
-    const float ome = d * (1.0f - beta);
-    gamma = ome - beta;
-    e = 1.0f - ome;
+  if (d < 0.05f) {
+    float u = fmaf(d, -1.0f / 24.0f, 1.0f / 6.0f);
+    u = fmaf(d, u, -0.5f);
+    u = fmaf(d, u, 1.0f);
+    e = fmaf(-d, u, 1.0f);
+    uD = u * D;
   } else {
     e = fexp2(-dtau * l2e_mu);
-    const float u = (1.0f - e) * (rdt * mu);
-    beta = 1.0f - u;
-    gamma = u - e;
+    const float m = mu * rD;
+    uD = fmaf(-e, m, m);
   }
-  return fmaf(e, I, fmaf(beta, S1, gamma * S0));
+}
+
+__device__ __forceinline__ float sc_step_f(float I, float dtau, float rD, float S1, float S0,
+                                           float D, float inv_mu, float l2e_mu, float mu) {
+  float e, uD;
+  sc_coef_f(dtau, rD, D, inv_mu, l2e_mu, mu, e, uD);
+  return fmaf(e, I - S0, S1) + uD;
+}
+
+// The layer as an affine map I -> e I + c (FP64), for sweeps that compose
+// maps from the top down.
+__device__ __forceinline__ void sc_coef_d(double dtau, double S1, double S0, double mu, double &e,
+                                          double &c) {
+  const double d = dtau / mu;
+  e = exp(-d);
+  const double u = d > 0.0 ? -expm1(-d) / d : 1.0;
+  c = (1.0 - u) * S1 + (u - e) * S0;
 }
 
 __device__ __forceinline__ double sc_step_d(double I, double dtau, double S1, double S0,
@@ -689,36 +704,98 @@ __global__ __launch_bounds__(512) void k_column(TableView tv, const ColSeg *__re
     }
   };
 
-  if (l0 < nlay) {
+  // stage 1 at one level: chi from the slot rows (or read back from memory)
+  auto opacity = [&](const Rec &r, int l) -> Real {
+    if constexpr (FROM_CHI) {
+      return chi_in[d.chi_offset + (int64_t)l * nu_count + jj];
+    } else {
+      Real chi = (Real)0;
+#pragma unroll
+      for (int q = 0; q < NS; ++q) {
+        if (q < S) {
+          const Real y = r.w[0] * slot[q][0] + r.w[1] * slot[q][1] + r.w[2] * slot[q][2] +
+                         r.w[3] * slot[q][3];
+          if constexpr (kF64)
+            chi += r.a_s[q] * exp2(y);
+          else
+            chi = fmaf(r.a_s[q], fexp2(y), chi);
+        }
+      }
+      if (has_cia) {
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+          const Real y = r.cia_w[0] * cslot[q][0] + r.cia_w[1] * cslot[q][1];
+          if constexpr (kF64)
+            chi += r.a_cia[q] * exp2(y);
+          else
+            chi = fmaf(r.a_cia[q], fexp2(y), chi);
+        }
+      }
+      return chi;
+    }
+  };
+  auto source = [&](const Rec &r) -> Real {
+    if constexpr (kF64)
+      return planck_d(nu_d, c1nu3_d, r.T);
+    else
+      return planck_f(nu_hi, nu_lo, c1nu3_f, r.pl_hi, r.pl_lo);
+  };
+
+  // Odd chunks (linear source) compose their layers' maps from the top
+  // down, so that the rows at each chunk boundary are read by the two chunks
+  // that share it at about the same time (the second read is an L2 hit)
+  // instead of at opposite ends of the sweep.
+  const bool down = !PARA && (chunk & 1) != 0;
+  if (down && l0 < nlay) {
+    if constexpr (!FROM_CHI) fetch(rec[l1], rec[l1].mask >> 8);
+    Real A[MAXMU];   // transmission of the layers composed so far
+#pragma unroll
+    for (int k = 0; k < MAXMU; ++k) A[k] = (Real)1;
+    for (int l = l1; l >= l0; --l) {
+      const Rec r = rec[l];
+      const Real chi = opacity(r, l);
+      if constexpr (!FROM_CHI) {
+        if (l > l0) {
+          const Rec &rn = rec[l - 1];
+          asm volatile("" ::: "memory");
+          fetch(rn, rn.mask >> 16);
+        }
+      }
+      const Real Sl = source(r);
+      if (l < l1) {
+        // layer l -> l+1: lower level l (S0 = Sl), upper level l+1 (S1 = S_prev)
+        const Real dtau = (chi + chi_prev) * r.hdz + r.dtc;
+        tau += dtau;
+        if constexpr (kF64) {
+#pragma unroll
+          for (int k = 0; k < MAXMU; ++k)
+            if (k < nmu) {
+              double e, c;
+              sc_coef_d(dtau, S_prev, Sl, a_mud[k], e, c);
+              I[k] = fma(A[k], c, I[k]);
+              A[k] *= e;
+            }
+        } else {
+          const float D = Sl - S_prev, rD = D * frcp(dtau);
+#pragma unroll
+          for (int k = 0; k < MAXMU; ++k)
+            if (k < nmu) {
+              float e, uD;
+              sc_coef_f(dtau, rD, D, a_inv[k], a_l2e[k], a_mu[k], e, uD);
+              I[k] = fmaf(A[k], fmaf(-e, Sl, S_prev) + uD, I[k]);
+              A[k] *= e;
+            }
+        }
+      }
+      chi_prev = chi;
+      S_prev = Sl;
+    }
+  } else if (l0 < nlay) {
     if constexpr (!FROM_CHI) fetch(rec[l0], rec[l0].mask >> 8);
     for (int l = l0; l <= l_end; ++l) {
       const Rec r = rec[l];
-      Real chi;
-      if constexpr (FROM_CHI) {
-        chi = chi_in[d.chi_offset + (int64_t)l * nu_count + jj];
-      } else {
-        chi = (Real)0;
-#pragma unroll
-        for (int q = 0; q < NS; ++q) {
-          if (q < S) {
-            const Real y = r.w[0] * slot[q][0] + r.w[1] * slot[q][1] + r.w[2] * slot[q][2] +
-                           r.w[3] * slot[q][3];
-            if constexpr (kF64)
-              chi += r.a_s[q] * exp2(y);
-            else
-              chi = fmaf(r.a_s[q], fexp2(y), chi);
-          }
-        }
-        if (has_cia) {
-#pragma unroll
-          for (int q = 0; q < 2; ++q) {
-            const Real y = r.cia_w[0] * cslot[q][0] + r.cia_w[1] * cslot[q][1];
-            if constexpr (kF64)
-              chi += r.a_cia[q] * exp2(y);
-            else
-              chi = fmaf(r.a_cia[q], fexp2(y), chi);
-          }
-        }
+      const Real chi = opacity(r, l);
+      if constexpr (!FROM_CHI) {
         if (l < l_end) {
           const Rec &rn = rec[l + 1];
           // keeps this fetch here, after the opacity, instead of being merged
@@ -727,11 +804,7 @@ __global__ __launch_bounds__(512) void k_column(TableView tv, const ColSeg *__re
           fetch(rn, rn.mask);
         }
       }
-      Real S;
-      if constexpr (kF64)
-        S = planck_d(nu_d, c1nu3_d, r.T);
-      else
-        S = planck_f(nu_hi, nu_lo, c1nu3_f, r.pl_hi, r.pl_lo);
+      const Real S = source(r);
       if (l == l0) {
 #pragma unroll
         for (int k = 0; k < MAXMU; ++k) I[k] = (chunk == 0) ? S : (Real)0;
@@ -745,11 +818,11 @@ __global__ __launch_bounds__(512) void k_column(TableView tv, const ColSeg *__re
             for (int k = 0; k < MAXMU; ++k)
               if (k < nmu) I[k] = sc_step_d(I[k], dtau, S, S_prev, a_mud[k]);
           } else {
-            const float rdt = frcp(dtau);
+            const float D = S_prev - S, rD = D * frcp(dtau);
 #pragma unroll
             for (int k = 0; k < MAXMU; ++k)
               if (k < nmu)
-                I[k] = sc_step_f(I[k], dtau, rdt, S, S_prev, a_inv[k], a_l2e[k], a_mu[k]);
+                I[k] = sc_step_f(I[k], dtau, rD, S, S_prev, D, a_inv[k], a_l2e[k], a_mu[k]);
           }
         } else {
           if (l <= l1) tau += dtau;
@@ -764,14 +837,15 @@ __global__ __launch_bounds__(512) void k_column(TableView tv, const ColSeg *__re
                                     : sc_step_d(I[k], dtau_last, S_prev, S_pp, a_mud[k]);
             } else {
               const float r_u = frcp(dtau_last), r_d = frcp(dtau), r_s = frcp(dtau_last + dtau);
+              const float D = S_pp - S_prev, rD = D * r_u;
 #pragma unroll
               for (int k = 0; k < MAXMU; ++k)
                 if (k < nmu)
                   I[k] = dtau > 0.0f
                              ? sc_para_f(I[k], dtau_last, dtau, r_u, r_d, r_s, S_pp, S_prev, S,
                                          a_inv[k], a_l2e[k], a_mu[k])
-                             : sc_step_f(I[k], dtau_last, r_u, S_prev, S_pp, a_inv[k], a_l2e[k],
-                                         a_mu[k]);
+                             : sc_step_f(I[k], dtau_last, rD, S_prev, S_pp, D, a_inv[k],
+                                         a_l2e[k], a_mu[k]);
             }
           }
           S_pp = S_prev;
@@ -791,11 +865,11 @@ __global__ __launch_bounds__(512) void k_column(TableView tv, const ColSeg *__re
           for (int k = 0; k < MAXMU; ++k)
             if (k < nmu) I[k] = sc_step_d(I[k], dtau_last, S_prev, S_pp, a_mud[k]);
         } else {
-          const float r_u = frcp(dtau_last);
+          const float D = S_pp - S_prev, rD = D * frcp(dtau_last);
 #pragma unroll
           for (int k = 0; k < MAXMU; ++k)
             if (k < nmu)
-              I[k] = sc_step_f(I[k], dtau_last, r_u, S_prev, S_pp, a_inv[k], a_l2e[k], a_mu[k]);
+              I[k] = sc_step_f(I[k], dtau_last, rD, S_prev, S_pp, D, a_inv[k], a_l2e[k], a_mu[k]);
         }
       }
     }
