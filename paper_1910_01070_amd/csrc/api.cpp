@@ -550,7 +550,8 @@ int auto_chunks(const TableView &tv, int64_t base_waves, int n_levels, int n_mu,
   (void)hipGetDevice(&dev);
   auto capacity = [&](int c) {
     const int big = (int64_t)tv.S * tv.nT * tv.nP * tv.pitch * tv.tab_elem >= 0xFFFFFFFFll;
-    const auto key = std::make_tuple(dev, tv.dtype, tv.S, big, n_mu > 4 ? 8 : 4, from_chi, c, para);
+    const auto key =
+        std::make_tuple(dev, tv.dtype, tv.S, big, column_mu_class(n_mu), from_chi, c, para);
     std::lock_guard<std::mutex> lk(mu);
     auto it = cache.find(key);
     if (it != cache.end()) return it->second;

@@ -162,6 +162,9 @@ hipError_t launch_column(const TableView &tv, const ColSeg *segs_dev, int n_segs
                          bool para, hipStream_t stream);
 int column_nu_per_wg(int chunks);
 // Waves of the column kernel (with this chunk count) the device holds at once.
+// Largest angle count of the column kernel variant a request of n_mu angles
+// runs (requests of one class share a launch).
+int column_mu_class(int n_mu);
 int column_wave_capacity(const TableView &tv, int max_mu, bool opacity_from_memory, int chunks,
                          bool para);
 

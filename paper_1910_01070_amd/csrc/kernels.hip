@@ -399,6 +399,37 @@ __device__ __forceinline__ float sc_step_f(float I, float dtau, float rD, float 
   return fmaf(e, I - S0, S1) + uD;
 }
 
+// The same step with the weights beta = 1 - u, gamma = u - e formed
+// explicitly (FP32): I_new = e I + beta S1 + gamma S0.  Below Delta = 1/2,
+// beta comes from its series and gamma = Delta (1 - beta) - beta,
+// e = 1 - Delta (1 - beta).  Used by the parabolic sweep for its linear
+// steps, where it needs no per-layer source difference in registers.
+__device__ __forceinline__ float sc_step_weights_f(float I, float dtau, float rdt, float S1,
+                                                   float S0, float inv_mu, float l2e_mu, float mu) {
+  const float d = dtau * inv_mu;
+  float e, beta, gamma;
+  if (d < 0.5f) {
+    float b = -1.0f / 362880.0f;
+    b = fmaf(b, d, 1.0f / 40320.0f);
+    b = fmaf(b, d, -1.0f / 5040.0f);
+    b = fmaf(b, d, 1.0f / 720.0f);
+    b = fmaf(b, d, -1.0f / 120.0f);
+    b = fmaf(b, d, 1.0f / 24.0f);
+    b = fmaf(b, d, -1.0f / 6.0f);
+    b = fmaf(b, d, 0.5f);
+    beta = b * d;
+    const float ome = d * (1.0f - beta);
+    gamma = ome - beta;
+    e = 1.0f - ome;
+  } else {
+    e = fexp2(-dtau * l2e_mu);
+    const float u = (1.0f - e) * (rdt * mu);
+    beta = 1.0f - u;
+    gamma = u - e;
+  }
+  return fmaf(e, I, fmaf(beta, S1, gamma * S0));
+}
+
 // The layer as an affine map I -> e I + c (FP64), for sweeps that compose
 // maps from the top down.
 __device__ __forceinline__ void sc_coef_d(double dtau, double S1, double S0, double mu, double &e,
@@ -837,15 +868,14 @@ __global__ __launch_bounds__(512) void k_column(TableView tv, const ColSeg *__re
                                     : sc_step_d(I[k], dtau_last, S_prev, S_pp, a_mud[k]);
             } else {
               const float r_u = frcp(dtau_last), r_d = frcp(dtau), r_s = frcp(dtau_last + dtau);
-              const float D = S_pp - S_prev, rD = D * r_u;
 #pragma unroll
               for (int k = 0; k < MAXMU; ++k)
                 if (k < nmu)
                   I[k] = dtau > 0.0f
                              ? sc_para_f(I[k], dtau_last, dtau, r_u, r_d, r_s, S_pp, S_prev, S,
                                          a_inv[k], a_l2e[k], a_mu[k])
-                             : sc_step_f(I[k], dtau_last, rD, S_prev, S_pp, D, a_inv[k],
-                                         a_l2e[k], a_mu[k]);
+                             : sc_step_weights_f(I[k], dtau_last, r_u, S_prev, S_pp, a_inv[k],
+                                                 a_l2e[k], a_mu[k]);
             }
           }
           S_pp = S_prev;
@@ -865,11 +895,12 @@ __global__ __launch_bounds__(512) void k_column(TableView tv, const ColSeg *__re
           for (int k = 0; k < MAXMU; ++k)
             if (k < nmu) I[k] = sc_step_d(I[k], dtau_last, S_prev, S_pp, a_mud[k]);
         } else {
-          const float D = S_pp - S_prev, rD = D * frcp(dtau_last);
+          const float r_u = frcp(dtau_last);
 #pragma unroll
           for (int k = 0; k < MAXMU; ++k)
             if (k < nmu)
-              I[k] = sc_step_f(I[k], dtau_last, rD, S_prev, S_pp, D, a_inv[k], a_l2e[k], a_mu[k]);
+              I[k] = sc_step_weights_f(I[k], dtau_last, r_u, S_prev, S_pp, a_inv[k], a_l2e[k],
+                                       a_mu[k]);
         }
       }
     }
@@ -932,20 +963,25 @@ static ColumnKernel ck() {
                       (int)sizeof(Real)};
 }
 
+// Angle tiers compiled: up to 3 angles (registers for exactly 3), else up
+// to 8.  A request runs the kernel of its tier.
+constexpr int kMuTierSmall = 3;
+int column_mu_class(int n_mu) { return n_mu > kMuTierSmall ? 8 : kMuTierSmall; }
+
 template <typename Real, typename TT, bool FROM_CHI, bool PARA>
 static ColumnKernel pick_ns(const TableView &tv, int max_mu) {
   const int S = tv.S;
   if constexpr (FROM_CHI) {
-    if (max_mu <= 4) return ck<Real, TT, 1, 4, true, PARA>();
+    if (max_mu <= kMuTierSmall) return ck<Real, TT, 1, kMuTierSmall, true, PARA>();
     return ck<Real, TT, 1, 8, true, PARA>();
   } else {
     const int64_t table_bytes = (int64_t)tv.S * tv.nT * tv.nP * tv.pitch * (int64_t)sizeof(TT);
     if (table_bytes >= 0xFFFFFFFFll) return ck<Real, TT, kMaxSpecies, 8, false, PARA, true>();
-    if (max_mu <= 4) {
-      if (S <= 1) return ck<Real, TT, -1, 4, false, PARA>();
-      if (S == 8) return ck<Real, TT, -8, 4, false, PARA>();
-      if (S <= 8) return ck<Real, TT, 8, 4, false, PARA>();
-      return ck<Real, TT, kMaxSpecies, 4, false, PARA>();
+    if (max_mu <= kMuTierSmall) {
+      if (S <= 1) return ck<Real, TT, -1, kMuTierSmall, false, PARA>();
+      if (S == 8) return ck<Real, TT, -8, kMuTierSmall, false, PARA>();
+      if (S <= 8) return ck<Real, TT, 8, kMuTierSmall, false, PARA>();
+      return ck<Real, TT, kMaxSpecies, kMuTierSmall, false, PARA>();
     }
     if (S <= 1) return ck<Real, TT, -1, 8, false, PARA>();
     if (S <= 8) return ck<Real, TT, 8, 8, false, PARA>();

@@ -222,7 +222,8 @@ bool hr2_server::launch_step(StepSlot &sl, std::vector<Req *> &reqs) {
   // and by angle class (kernel variant), so each request runs exactly the
   // code it would run alone
   std::stable_sort(reqs.begin(), reqs.end(), [](const Req *a, const Req *b) {
-    const int ka = a->chunks * 2 + (a->n_mu > 4), kb = b->chunks * 2 + (b->n_mu > 4);
+    const int ka = a->chunks * 16 + column_mu_class(a->n_mu);
+    const int kb = b->chunks * 16 + column_mu_class(b->n_mu);
     return ka < kb;
   });
   std::vector<ColSeg> cs(reqs.size());
@@ -236,7 +237,7 @@ bool hr2_server::launch_step(StepSlot &sl, std::vector<Req *> &reqs) {
   int64_t wg = 0, waves = 0;
   for (size_t i = 0; i < reqs.size(); ++i) {
     Req &r = *reqs[i];
-    const int mu_class = r.n_mu > 4 ? 8 : 4;
+    const int mu_class = column_mu_class(r.n_mu);
     if (groups.empty() || groups.back().chunks != r.chunks || groups.back().max_mu != mu_class) {
       groups.push_back(Group{i, 0, 0, r.chunks, mu_class});
       wg = 0;

@@ -108,7 +108,7 @@ def test_stage_rt_parabolic(ctx, dtype, tol):
     fplus = torch.empty(w.count, dtype=T.real, device="cuda")
     st = oracle.column_state(tab, col)
     nu = tab.nu0_cm + oracle.window_indices(w) * tab.dnu_cm
-    for n_mu in (1, 2, 3, 8):
+    for n_mu in (1, 2, 3, 4, 8):
         hr2.rt_emission(ctx, T, col, w, chi_in.reshape(-1), n_mu, fplus)
         torch.cuda.synchronize()
         ref = oracle.rt_emission(chi_ref, st["dz"], col.T_K, nu, n_mu, order=2)

@@ -65,6 +65,30 @@ def test_c1_full_chain(ctx, dtype, tol):
 
 
 @pytest.mark.parametrize("dtype,tol", [("f64", 1e-12), ("f32", 1e-5)])
+def test_angle_counts(ctx, dtype, tol):
+    """The fused path at every angle count across the two compiled angle
+    tiers (up to 3, and 4 to 8 angles), with one and with several layer
+    chunks."""
+    tab = tu.c1_table()
+    cols = wl.c1_columns()[:2]
+    spec = wl.c1_obs(tab)
+    T = hr2.Tables(ctx, tab, dtype)
+    obs = hr2.Obs(ctx, T, spec.window, spec.resolving_power, spec.edges_cm)
+    for n_mu in (1, 2, 3, 4, 6, 8):
+        refs = [oracle.forward(tab, c, spec.window, spec.resolving_power, spec.edges_cm, n_mu)
+                for c in cols]
+        for chunks in (1, 3):
+            say(f"C1 {dtype}: n_mu={n_mu} chunks={chunks}")
+            bins, fplus = run_forward(ctx, T, obs, cols, n_mu, chunks)
+            for s, ref in enumerate(refs):
+                e_f, _ = tu.max_rel_err(fplus[s], ref["fplus"])
+                e_b, _ = tu.max_rel_err(bins[s], ref["bins"])
+                assert e_f <= tol and e_b <= tol, (dtype, n_mu, chunks, s, e_f, e_b)
+    obs.close()
+    T.close()
+
+
+@pytest.mark.parametrize("dtype,tol", [("f64", 1e-12), ("f32", 1e-5)])
 def test_stage_calls(ctx, dtype, tol):
     """hr2_opacity, hr2_rt_emission and hr2_convolve_bin one at a time, each
     fed the oracle's previous stage."""
@@ -84,7 +108,7 @@ def test_stage_calls(ctx, dtype, tol):
     say(f"stage calls {dtype}: rt_emission from the oracle's chi")
     chi_in = torch.from_numpy(chi_ref.astype(np.float64 if dtype == "f64" else np.float32)).cuda()
     fplus = torch.empty(w.count, dtype=T.real, device="cuda")
-    for n_mu in (1, 2, 3, 5, 8):
+    for n_mu in (1, 2, 3, 4, 5, 8):
         hr2.rt_emission(ctx, T, col, w, chi_in.reshape(-1), n_mu, fplus)
         torch.cuda.synchronize()
         st = oracle.column_state(tab, col)
@@ -135,6 +159,38 @@ def test_multispecies_cia_windows(ctx, dtype, tol):
                 e_f, _ = tu.max_rel_err(fplus[s], ref["fplus"])
                 e_b, _ = tu.max_rel_err(bins[s], ref["bins"])
                 assert e_f <= tol and e_b <= tol, (w, L, chunks, s, e_f, e_b)
+
+
+@pytest.mark.parametrize("dtype,tol", [("f64", 1e-12), ("f32", 1e-5)])
+def test_zigzag_temperature_profiles(ctx, dtype, tol):
+    """Temperature profiles that cross the table's T nodes back and forth
+    (and leave the axis at both ends), so that table rows leave the cell and
+    come back in both sweep directions: the row masks for upward and
+    downward layer chunks must fetch exactly what the slots lack."""
+    tab = tu.small_multi_table()
+    T = hr2.Tables(ctx, tab, dtype)
+    w = wl.Window(3, 2990, 1)
+    nu_first, dnu = oracle.window_grid(tab, w)
+    edges = wl.snapped_edges(tab, w, wl.log_edges(nu_first + 200 * dnu, nu_first + 2700 * dnu, 7))
+    obs = hr2.Obs(ctx, T, w, 400.0, edges)
+    rng = np.random.default_rng(11)
+    cols = []
+    for L, period, amp in ((57, 5.0, 1300.0), (33, 2.3, 900.0), (64, 9.7, 1600.0)):
+        p = wl.levels(L, 2.3, -4.7)
+        lev = np.arange(L)
+        Tk = np.clip(1500.0 + amp * np.sin(2 * np.pi * lev / period + rng.uniform(0, 6)), 120.0, 3400.0)
+        x = wl.log_uniform(rng, 1e-6, 1e-2, tab.n_species)
+        cols.append(wl.Column(p, Tk, x, 4.5, wl.scale_factor(1.0)))
+    refs = [oracle.forward(tab, c, w, 400.0, edges, 3) for c in cols]
+    for chunks in (1, 2, 3, 4, 5, 8):
+        for s, col in enumerate(cols):
+            say(f"zigzag {dtype} L={col.n_levels} chunks={chunks}")
+            bins, fplus = run_forward(ctx, T, obs, [col], 3, chunks)
+            e_f, _ = tu.max_rel_err(fplus[0], refs[s]["fplus"])
+            e_b, _ = tu.max_rel_err(bins[0], refs[s]["bins"])
+            assert e_f <= tol and e_b <= tol, (dtype, chunks, s, e_f, e_b)
+    obs.close()
+    T.close()
 
 
 def test_isothermal_and_transparent_limits(ctx):
