@@ -191,18 +191,17 @@ __global__ __launch_bounds__(kLevelThreads) void k_levels(TableView tv, ColumnsV
     bad |= !(s_pl[l] > 0.0) || !isfinite(s_pl[l]) || !(s_Tl[l] > 0.0) || !isfinite(s_Tl[l]);
     if (l + 1 < L) bad |= !(s_pl[l] > s_pl[l + 1]);
   }
-  bad = __syncthreads_or(bad);
-  if (status != nullptr && threadIdx.x == 0 && part == 0)
-    status[s] = bad ? (int)HR2_E_INVALID_ARG : 0;
-
-  // every level's table cell, once per workgroup
+  // every level's table cell, once per workgroup (independent of the
+  // validity checks: invalid inputs give NaN weights and NaN hdz records)
   for (int l = threadIdx.x; l < L; l += blockDim.x) {
     CellW c;
     locate_lds(s_T, tv.nT, s_Tl[l], c.iT, c.wT);
     locate_lds(s_lp, tv.nP, log10(s_pl[l]), c.ip, c.wp);
     s_cell[l] = c;
   }
-  __syncthreads();
+  bad = __syncthreads_or(bad);
+  if (status != nullptr && threadIdx.x == 0 && part == 0)
+    status[s] = bad ? (int)HR2_E_INVALID_ARG : 0;
 
   const double h2 = (1.0 - xs) / (1.0 + tv.he_ratio);
   const double he = tv.he_ratio * h2;
@@ -217,9 +216,29 @@ __global__ __launch_bounds__(kLevelThreads) void k_levels(TableView tv, ColumnsV
   // table offsets are fetched while the level items run.  Items write
   // disjoint fields of the records.
   const int per_level = S + tv.n_cia;
-  const int n_items = L * (1 + per_level);
+  const int n_items = L * (2 + per_level);
   for (int t = part * blockDim.x + threadIdx.x; t < n_items; t += blocks_per_set * blockDim.x) {
-    if (t < L) {
+    if (t >= L && t < 2 * L) {
+      // the layer above level l: half thickness and cloud optical depth
+      const int l = t - L;
+      Rec *r = recs + (int64_t)s * L + l;
+      double hdz = 0.0, dtc = 0.0;
+      if (l + 1 < L) {
+        const double tbar = 0.5 * (s_Tl[l] + s_Tl[l + 1]);
+        const double lr = log(s_pl[l] / s_pl[l + 1]);
+        hdz = 0.5 * kKB * tbar / (mm * kAMU * exp10(logg)) * lr;
+        // the cloud's optical depth, spread uniformly in ln p over
+        // [p_top, p_top bottom_frac]: this layer's share of that range
+        if (tau_c > 0.0) {
+          const double lc_top = log(c_top), lc_bot = log(c_top * c_frac);
+          const double hi = fmin(log(s_pl[l]), lc_bot), lo = fmax(log(s_pl[l + 1]), lc_top);
+          if (hi > lo) dtc = tau_c * (hi - lo) / (lc_bot - lc_top);
+        }
+      }
+      if (bad) hdz = __builtin_nan("");
+      r->hdz = (Real)hdz;
+      r->dtc = (Real)dtc;
+    } else if (t < L) {
       const int l = t;
       Rec *r = recs + (int64_t)s * L + l;
       const CellW c = cell_of(l);
@@ -260,22 +279,6 @@ __global__ __launch_bounds__(kLevelThreads) void k_levels(TableView tv, ColumnsV
       r->mask = mask;
       for (int q = S; q < kMaxSpecies; ++q) r->a_s[q] = (Real)0;
       if (tv.n_cia == 0) r->a_cia[0] = r->a_cia[1] = (Real)0;
-      double hdz = 0.0, dtc = 0.0;
-      if (l + 1 < L) {
-        const double tbar = 0.5 * (s_Tl[l] + s_Tl[l + 1]);
-        const double lr = log(s_pl[l] / s_pl[l + 1]);
-        hdz = 0.5 * kKB * tbar / (mm * kAMU * exp10(logg)) * lr;
-        // the cloud's optical depth, spread uniformly in ln p over
-        // [p_top, p_top bottom_frac]: this layer's share of that range
-        if (tau_c > 0.0) {
-          const double lc_top = log(c_top), lc_bot = log(c_top * c_frac);
-          const double hi = fmin(log(s_pl[l]), lc_bot), lo = fmax(log(s_pl[l + 1]), lc_top);
-          if (hi > lo) dtc = tau_c * (hi - lo) / (lc_bot - lc_top);
-        }
-      }
-      if (bad) hdz = __builtin_nan("");
-      r->hdz = (Real)hdz;
-      r->dtc = (Real)dtc;
       if constexpr (std::is_same<Real, float>::value) {
         const double pl = kC2 * kLog2e / s_Tl[l];
         const float hi = (float)pl;
@@ -291,7 +294,7 @@ __global__ __launch_bounds__(kLevelThreads) void k_levels(TableView tv, ColumnsV
       // n_s 2^{interpolated row offset} (and the CIA pairs' n_a n_b 2^{...}):
       // the column kernel exponentiates only the stored offset-free part,
       // keeping its exp2 argument small.
-      const int u = t - L;
+      const int u = t - 2 * L;
       const int l = u / per_level, q = u - l * per_level;
       Rec *r = recs + (int64_t)s * L + l;
       const CellW c = cell_of(l);
@@ -324,7 +327,7 @@ __global__ __launch_bounds__(kLevelThreads) void k_levels(TableView tv, ColumnsV
 hipError_t launch_levels(const TableView &tv, const ColumnsView &cv, void *recs, int *status,
                          bool fp64, hipStream_t stream) {
   // one workgroup per kLevelThreads items of a set: every item runs at once
-  const int64_t items = (int64_t)cv.L * (1 + tv.S + tv.n_cia);
+  const int64_t items = (int64_t)cv.L * (2 + tv.S + tv.n_cia);
   const int threads = (int)std::min<int64_t>(kLevelThreads, (items + 63) / 64 * 64);
   const int per_set = (int)((items + threads - 1) / threads);
   const dim3 grid((unsigned)((int64_t)cv.B * per_set));
