@@ -1147,6 +1147,17 @@ __global__ __launch_bounds__(256) void k_convolve_bin(const ConvSeg *__restrict_
   const Real *K = (const Real *)d.K + d.kstart[jb];
   const int len = d.mlen[jb];
   const Real *F = in + d.in_offset + (int64_t)s * d.in_stride + d.mlo[jb];
+  // what thread 0 needs after the reduction, requested now so that it
+  // arrives with the data
+  double sc = d.scale_const, Dj = 0.0, s2 = 0.0, l10e = 0.0;
+  if (threadIdx.x == 0) {
+    if (d.scale) sc = d.scale[s];
+    if (d.terms) {
+      Dj = d.D[jb];
+      s2 = d.s2[jb];
+      if (d.log10_eps) l10e = d.log10_eps[s];
+    }
+  }
   // four independent partial sums, so that each thread's loads of a round
   // are in flight together
   Real a0 = (Real)0, a1 = (Real)0, a2 = (Real)0, a3 = (Real)0;
@@ -1170,14 +1181,12 @@ __global__ __launch_bounds__(256) void k_convolve_bin(const ConvSeg *__restrict_
   __syncthreads();
   if (threadIdx.x == 0) {
     const Real tot = (part[0] + part[1]) + (part[2] + part[3]);
-    const double sc = d.scale ? d.scale[s] : d.scale_const;
     const Real v = tot * (Real)sc;
     if (out) out[d.out_offset + (int64_t)s * d.n_bins + jb] = v;
     if (d.terms) {
       // Eq. 19 term of bin j in FP64; with Eq. 22 the variance gains 10^eps
-      double s2 = d.s2[jb];
-      if (d.log10_eps) s2 += exp10(d.log10_eps[s]);
-      const double r = d.D[jb] - (double)v;
+      if (d.log10_eps) s2 += exp10(l10e);
+      const double r = Dj - (double)v;
       d.terms[(int64_t)s * d.n_bins + jb] = -r * r / (2.0 * s2) - 0.5 * log(kTwoPi * s2);
     }
   }
