@@ -871,7 +871,7 @@ struct LikeArgs {
 
 hr2_status run_forward(hr2_ctx *ctx, const hr2_tables *t, const hr2_obs *o, const ColumnsView &cv,
                        int n_mu, void *bins, void *fplus, int *status, hipStream_t s,
-                       const LikeArgs *like = nullptr) {
+                       const LikeArgs *like = nullptr, const ThetaArgs *theta = nullptr) {
   const hr2_window &w = o->window;
   const int B = cv.B, L = cv.L;
   const size_t rec_bytes = (size_t)B * L * rec_size(t);
@@ -895,7 +895,8 @@ hr2_status run_forward(hr2_ctx *ctx, const hr2_tables *t, const hr2_obs *o, cons
     for (int k = 0; k < 4; ++k) ev[k] = timing_event(ctx, k);
   const bool timed = ev[0] && ev[1] && ev[2] && ev[3];
   if (timed) HIP_TRY(hipEventRecord(ev[0], s));
-  HIP_TRY(launch_levels(t->view, cv, ctx->recs.ptr, status, t->view.dtype == HR2_TABLE_F64, s));
+  HIP_TRY(launch_levels(t->view, cv, ctx->recs.ptr, status, t->view.dtype == HR2_TABLE_F64, s,
+                        theta));
   const int64_t base_waves = (int64_t)B * ((w.nu_count + 63) / 64);
   const int chunks = ctx->opt_chunks ? std::min(ctx->opt_chunks, std::max(1, L - 1))
                                      : auto_chunks(t->view, base_waves, L, n_mu, false,
@@ -1203,16 +1204,15 @@ extern "C" hr2_status hr2_forward_params_dev(hr2_ctx *ctx, const hr2_tables *t, 
                      "scratch would grow under stream capture: make the same call once first");
   if ((st = ctx_begin(ctx, s)) != HR2_OK) return st;
   if ((st = ctx->unpacked.ensure(n_dbl * sizeof(double))) != HR2_OK) return st;
+  // the level kernel forms the columns from theta and writes each set's
+  // scale and eps where the later stages read them
   ColumnsView cv = columns_view(ctx->unpacked.ptr, B, L, S);
   double *cloud = const_cast<double *>(cv.cloud);
   double *eps = cloud + (size_t)3 * B;
-  HIP_TRY(launch_unpack(v, B, theta, const_cast<double *>(cv.p), const_cast<double *>(cv.T),
-                        const_cast<double *>(cv.x), const_cast<double *>(cv.logg),
-                        const_cast<double *>(cv.scale), cloud, eps, s));
-  if (!v.with_cloud) cv.cloud = nullptr;
+  const ThetaArgs ta{v, theta, const_cast<double *>(cv.scale), eps};
   LikeArgs like{v.with_eps ? eps : nullptr, lnl};
-  if ((st = run_forward(ctx, t, o, cv, n_mu, bins, nullptr, status_dev, s, lnl ? &like : nullptr)) !=
-      HR2_OK)
+  if ((st = run_forward(ctx, t, o, cv, n_mu, bins, nullptr, status_dev, s, lnl ? &like : nullptr,
+                        &ta)) != HR2_OK)
     return st;
   return ctx_end(ctx, s);
 }

@@ -149,8 +149,20 @@ struct ParamView {
 // All launchers enqueue on `stream` and return hipSuccess or the launch error.
 hipError_t upload_angle_table(const AngleTable &t);
 
+// Level records straight from parameter vectors: the level kernel forms
+// each set's column from theta (the same arithmetic as launch_unpack) and
+// writes the per-set scale and error-inflation exponent the later stages
+// read.  theta == nullptr: the columns come from the ColumnsView.
+struct ThetaArgs {
+  ParamView pv;
+  const double *theta;   // [B][n_theta]
+  double *scale;         // [B] out
+  double *eps;           // [B] out, or NULL
+};
+
 hipError_t launch_levels(const TableView &tv, const ColumnsView &cv, void *recs,
-                         int *status, bool fp64, hipStream_t stream);
+                         int *status, bool fp64, hipStream_t stream,
+                         const ThetaArgs *theta = nullptr);
 
 // One workgroup = `chunks` waves = one 64-point tile of one set; every
 // segment of the launch must use that chunk count.

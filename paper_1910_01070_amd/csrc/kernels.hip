@@ -137,12 +137,84 @@ __device__ __forceinline__ void locate_lds(const double *a, int n, double v, int
   w = (v - a[lo]) / (a[lo + 1] - a[lo]);
 }
 
+// ------------------------------------------------- parameter vector pieces
+// Layout of theta (Table 1 order): log g, f, d [pc], T1, b_1..b_{NT-1}, the
+// free mixing ratios, then (tau_c, p_top, bottom_frac) with a cloud and eps
+// last.  Node temperatures T_0 = T1, T_n = b_n T_{n-1} (Sect. 2.5.1); the
+// return value says whether the vector is invalid.
+__device__ bool theta_nodes(const ParamView &pv, const double *th, double *Tn) {
+  const int NT = pv.K * pv.q + 1;
+  bool bad = !isfinite(th[0]) || !(th[1] > 0.0) || !isfinite(th[1]) || !(th[2] > 0.0) ||
+             !isfinite(th[2]);
+  double t = th[3];
+  bad |= !(t > 0.0) || !isfinite(t);
+  Tn[0] = t;
+  for (int n = 1; n < NT; ++n) {
+    const double b = th[3 + n];
+    bad |= !(b > 0.0) || !isfinite(b);
+    t *= b;
+    Tn[n] = t;
+  }
+  for (int k = 0; k < pv.n_free; ++k) {
+    const double xf = th[3 + NT + k];
+    bad |= !(xf >= 0.0) || !isfinite(xf);
+  }
+  if (pv.with_cloud) {
+    const double *c = th + 3 + NT + pv.n_free;
+    bad |= !(c[0] >= 0.0) || !isfinite(c[0]);
+    if (c[0] > 0.0)
+      bad |= !(c[1] > 0.0) || !isfinite(c[1]) || !(c[2] > 1.0) || !isfinite(c[2]);
+  }
+  if (pv.with_eps) bad |= !isfinite(th[3 + NT + pv.n_free + 3 * pv.with_cloud]);
+  return bad;
+}
+
+// Level l sits at u = l K / (L - 1) element widths above the bottom (levels
+// and elements both equidistant in log p over the same range), in element
+// k = min(floor(u), K - 1) at local coordinate xi = u - k, where
+// T = sum_i T_{kq+i} l_i(xi) (Eq. 12-13); NaN for an invalid vector.
+__device__ void theta_level(const ParamView &pv, const double *Tn, int l, bool bad, double &p,
+                            double &T) {
+  const int L = pv.L;
+  const double step = (pv.lp_top - pv.lp_bottom) / (double)(L - 1);
+  const double lp = l == L - 1 ? pv.lp_top : pv.lp_bottom + (double)l * step;
+  p = exp10(lp);
+  const double u = (double)l * (double)pv.K / (double)(L - 1);
+  int k = (int)floor(u);
+  k = k < 0 ? 0 : (k > pv.K - 1 ? pv.K - 1 : k);
+  const double xi = u - (double)k;
+  double acc = 0.0;
+  for (int i = 0; i <= pv.q; ++i) {
+    double li = pv.inv_den[i];
+    for (int j = 0; j <= pv.q; ++j)
+      if (j != i) li *= xi - pv.nodes[j];
+    acc += Tn[k * pv.q + i] * li;
+  }
+  T = bad ? __builtin_nan("") : acc;
+}
+
+__device__ double theta_x(const ParamView &pv, const double *th, int sp) {
+  const int src = pv.src[sp];
+  return src >= 0 ? pv.fac[sp] * th[3 + pv.K * pv.q + 1 + src] : 0.0;
+}
+
+// f (R/d)^2 (Eq. 9), d in parsec
+__device__ double theta_scale(const ParamView &pv, const double *th) {
+  const double rd = pv.radius_cm / (th[2] * kParsecCm);
+  return th[1] * rd * rd;
+}
+
+// the cloud triple (with a cloud) and eps follow the free mixing ratios
+__device__ const double *theta_tail(const ParamView &pv, const double *th) {
+  return th + 3 + pv.K * pv.q + 1 + pv.n_free;
+}
+
 constexpr int kLevelThreads = 1024;   // one pass over the (level, species) items of C2
 
 template <typename Real>
 __global__ __launch_bounds__(kLevelThreads) void k_levels(TableView tv, ColumnsView cv,
                                                 typename RecOf<Real>::type *recs, int *status,
-                                                int blocks_per_set) {
+                                                int blocks_per_set, ThetaArgs ta) {
   using Rec = typename RecOf<Real>::type;
   __shared__ double s_T[kMaxAxis], s_lp[kMaxAxis];
   __shared__ double s_pl[HR2_MAX_LEVELS], s_Tl[HR2_MAX_LEVELS];
@@ -156,22 +228,47 @@ __global__ __launch_bounds__(kLevelThreads) void k_levels(TableView tv, ColumnsV
   // one coalesced pass over the set's inputs and the axes
   for (int i = threadIdx.x; i < tv.nT; i += blockDim.x) s_T[i] = tv.T_axis[i];
   for (int i = threadIdx.x; i < tv.nP; i += blockDim.x) s_lp[i] = tv.lp_axis[i];
-  for (int l = threadIdx.x; l < L; l += blockDim.x) {
-    s_pl[l] = cv.p[(int64_t)s * L + l];
-    s_Tl[l] = cv.T[(int64_t)s * L + l];
-  }
-  if (threadIdx.x < S) {
-    s_x[threadIdx.x] = cv.x[(int64_t)s * S + threadIdx.x];
-    s_m[threadIdx.x] = tv.mass[threadIdx.x];
-  }
-  const double logg = cv.logg[s], scale = cv.scale[s];
+  if (threadIdx.x < S) s_m[threadIdx.x] = tv.mass[threadIdx.x];
+  double logg, scale;
   // gray cloud (App. B): tau_c >= 0; with tau_c > 0 a top pressure > 0 and a
   // bottom at bottom_frac > 1 times the top
   double tau_c = 0.0, c_top = 1.0, c_frac = 2.0;
-  if (cv.cloud) {
-    tau_c = cv.cloud[(int64_t)s * 3];
-    c_top = cv.cloud[(int64_t)s * 3 + 1];
-    c_frac = cv.cloud[(int64_t)s * 3 + 2];
+  if (ta.theta != nullptr) {
+    // the column from the set's parameter vector
+    __shared__ double s_Tn[kMaxTNodes];
+    __shared__ int s_badt;
+    const double *th = ta.theta + (int64_t)s * ta.pv.n_theta;
+    if (threadIdx.x == 0) s_badt = theta_nodes(ta.pv, th, s_Tn) ? 1 : 0;
+    __syncthreads();
+    const bool badt = s_badt != 0;
+    for (int l = threadIdx.x; l < L; l += blockDim.x)
+      theta_level(ta.pv, s_Tn, l, badt, s_pl[l], s_Tl[l]);
+    if (threadIdx.x < S) s_x[threadIdx.x] = theta_x(ta.pv, th, threadIdx.x);
+    logg = th[0];
+    scale = theta_scale(ta.pv, th);
+    const double *c = theta_tail(ta.pv, th);
+    if (ta.pv.with_cloud) {
+      tau_c = c[0];
+      c_top = c[1];
+      c_frac = c[2];
+    }
+    if (part == 0 && threadIdx.x == 0) {
+      ta.scale[s] = scale;
+      if (ta.eps) ta.eps[s] = ta.pv.with_eps ? c[3 * ta.pv.with_cloud] : 0.0;
+    }
+  } else {
+    for (int l = threadIdx.x; l < L; l += blockDim.x) {
+      s_pl[l] = cv.p[(int64_t)s * L + l];
+      s_Tl[l] = cv.T[(int64_t)s * L + l];
+    }
+    if (threadIdx.x < S) s_x[threadIdx.x] = cv.x[(int64_t)s * S + threadIdx.x];
+    logg = cv.logg[s];
+    scale = cv.scale[s];
+    if (cv.cloud) {
+      tau_c = cv.cloud[(int64_t)s * 3];
+      c_top = cv.cloud[(int64_t)s * 3 + 1];
+      c_frac = cv.cloud[(int64_t)s * 3 + 2];
+    }
   }
   __syncthreads();
 
@@ -325,7 +422,9 @@ __global__ __launch_bounds__(kLevelThreads) void k_levels(TableView tv, ColumnsV
 }
 
 hipError_t launch_levels(const TableView &tv, const ColumnsView &cv, void *recs, int *status,
-                         bool fp64, hipStream_t stream) {
+                         bool fp64, hipStream_t stream, const ThetaArgs *theta) {
+  ThetaArgs ta{};
+  if (theta) ta = *theta;
   // one workgroup per kLevelThreads items of a set: every item runs at once
   const int64_t items = (int64_t)cv.L * (2 + tv.S + tv.n_cia);
   const int threads = (int)std::min<int64_t>(kLevelThreads, (items + 63) / 64 * 64);
@@ -333,10 +432,10 @@ hipError_t launch_levels(const TableView &tv, const ColumnsView &cv, void *recs,
   const dim3 grid((unsigned)((int64_t)cv.B * per_set));
   if (fp64)
     hipLaunchKernelGGL(k_levels<double>, grid, dim3(threads), 0, stream, tv, cv,
-                       (LevelRecD *)recs, status, per_set);
+                       (LevelRecD *)recs, status, per_set, ta);
   else
     hipLaunchKernelGGL(k_levels<float>, grid, dim3(threads), 0, stream, tv, cv,
-                       (LevelRecF *)recs, status, per_set);
+                       (LevelRecF *)recs, status, per_set, ta);
   return hipGetLastError();
 }
 
@@ -1234,11 +1333,8 @@ hipError_t launch_lnl_reduce(const double *terms, int n_sets, int n_bins, double
 }
 
 // ------------------------------------------------------ parameter unpack
-// One workgroup per parameter vector.  Node temperatures T_0 = T1,
-// T_n = b_n T_{n-1} (Sect. 2.5.1); level l sits at u = l K / (L - 1) element
-// widths above the bottom (levels and elements both equidistant in log p
-// over the same range), in element k = min(floor(u), K - 1) at local
-// coordinate xi = u - k, where T = sum_i T_{kq+i} l_i(xi) (Eq. 12-13).
+// One workgroup per parameter vector, writing the columns out (the fused
+// path forms them inside the level kernel with the same functions).
 __global__ __launch_bounds__(256) void k_unpack(ParamView pv, const double *__restrict__ theta,
                                                 double *__restrict__ p, double *__restrict__ T,
                                                 double *__restrict__ x, double *__restrict__ logg,
@@ -1249,61 +1345,18 @@ __global__ __launch_bounds__(256) void k_unpack(ParamView pv, const double *__re
   __shared__ int bad_s;
   const int s = blockIdx.x;
   const double *th = theta + (int64_t)s * pv.n_theta;
-  const int NT = pv.K * pv.q + 1;
-  if (threadIdx.x == 0) {
-    bool bad = !isfinite(th[0]) || !(th[1] > 0.0) || !isfinite(th[1]) || !(th[2] > 0.0) ||
-               !isfinite(th[2]);
-    double t = th[3];
-    bad |= !(t > 0.0) || !isfinite(t);
-    Tn[0] = t;
-    for (int n = 1; n < NT; ++n) {
-      const double b = th[3 + n];
-      bad |= !(b > 0.0) || !isfinite(b);
-      t *= b;
-      Tn[n] = t;
-    }
-    for (int k = 0; k < pv.n_free; ++k) {
-      const double xf = th[3 + NT + k];
-      bad |= !(xf >= 0.0) || !isfinite(xf);
-    }
-    if (pv.with_cloud) {
-      const double *c = th + 3 + NT + pv.n_free;
-      bad |= !(c[0] >= 0.0) || !isfinite(c[0]);
-      if (c[0] > 0.0)
-        bad |= !(c[1] > 0.0) || !isfinite(c[1]) || !(c[2] > 1.0) || !isfinite(c[2]);
-    }
-    if (pv.with_eps) bad |= !isfinite(th[3 + NT + pv.n_free + 3 * pv.with_cloud]);
-    bad_s = bad ? 1 : 0;
-  }
+  if (threadIdx.x == 0) bad_s = theta_nodes(pv, th, Tn) ? 1 : 0;
   __syncthreads();
   const bool bad = bad_s != 0;
   const int L = pv.L;
-  const double step = (pv.lp_top - pv.lp_bottom) / (double)(L - 1);
-  for (int l = threadIdx.x; l < L; l += blockDim.x) {
-    const double lp = l == L - 1 ? pv.lp_top : pv.lp_bottom + (double)l * step;
-    p[(int64_t)s * L + l] = exp10(lp);
-    const double u = (double)l * (double)pv.K / (double)(L - 1);
-    int k = (int)floor(u);
-    k = k < 0 ? 0 : (k > pv.K - 1 ? pv.K - 1 : k);
-    const double xi = u - (double)k;
-    double acc = 0.0;
-    for (int i = 0; i <= pv.q; ++i) {
-      double li = pv.inv_den[i];
-      for (int j = 0; j <= pv.q; ++j)
-        if (j != i) li *= xi - pv.nodes[j];
-      acc += Tn[k * pv.q + i] * li;
-    }
-    T[(int64_t)s * L + l] = bad ? __builtin_nan("") : acc;
-  }
-  for (int sp = threadIdx.x; sp < pv.S; sp += blockDim.x) {
-    const int src = pv.src[sp];
-    x[(int64_t)s * pv.S + sp] = src >= 0 ? pv.fac[sp] * th[3 + NT + src] : 0.0;
-  }
+  for (int l = threadIdx.x; l < L; l += blockDim.x)
+    theta_level(pv, Tn, l, bad, p[(int64_t)s * L + l], T[(int64_t)s * L + l]);
+  for (int sp = threadIdx.x; sp < pv.S; sp += blockDim.x)
+    x[(int64_t)s * pv.S + sp] = theta_x(pv, th, sp);
   if (threadIdx.x == 0) {
     logg[s] = th[0];
-    const double rd = pv.radius_cm / (th[2] * kParsecCm);
-    scale[s] = th[1] * rd * rd;
-    const double *c = th + 3 + NT + pv.n_free;
+    scale[s] = theta_scale(pv, th);
+    const double *c = theta_tail(pv, th);
     if (cloud)
       for (int k = 0; k < 3; ++k) cloud[(int64_t)s * 3 + k] = pv.with_cloud ? c[k] : 0.0;
     if (eps) eps[s] = pv.with_eps ? c[3 * pv.with_cloud] : 0.0;
