@@ -842,7 +842,9 @@ extern "C" hr2_status hr2_convolve_bin(hr2_ctx *ctx, const hr2_obs *o, const voi
   cs.scale_const = scale;
   cs.n_sets = 1;
   cs.n_bins = o->n_bins;
-  HIP_TRY(launch_convolve_bin(o->fp64, nullptr, 1, &cs, o->n_bins, fplus, bins, s));
+  cs.items_per_wg = conv_items_per_wg(o->nnz, o->n_bins);
+  HIP_TRY(launch_convolve_bin(o->fp64, nullptr, 1, &cs,
+                              conv_workgroups(o->n_bins, cs.items_per_wg), fplus, bins, s));
   return ctx_end(ctx, s);
 }
 
@@ -941,7 +943,10 @@ hr2_status run_forward(hr2_ctx *ctx, const hr2_tables *t, const hr2_obs *o, cons
     cs.terms = (double *)ctx->terms.ptr;
   }
   if (timed) HIP_TRY(hipEventRecord(ev[2], s));
-  HIP_TRY(launch_convolve_bin(o->fp64, nullptr, 1, &cs, (int64_t)B * o->n_bins, fplus, bins, s));
+  cs.items_per_wg = conv_items_per_wg(o->nnz, o->n_bins);
+  HIP_TRY(launch_convolve_bin(o->fp64, nullptr, 1, &cs,
+                              conv_workgroups((int64_t)B * o->n_bins, cs.items_per_wg), fplus,
+                              bins, s));
   if (like) HIP_TRY(launch_lnl_reduce(cs.terms, B, o->n_bins, like->lnl, s));
   if (timed) {
     HIP_TRY(hipEventRecord(ev[3], s));

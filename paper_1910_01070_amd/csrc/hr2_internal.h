@@ -104,7 +104,9 @@ struct ColSeg {
 
 // One segment of a convolve/bin launch: n_sets spectra against one layout.
 struct ConvSeg {
-  int64_t item_begin;       // first workgroup (one per (set, bin))
+  int64_t item_begin;       // first workgroup of the segment
+  int32_t items_per_wg;     // 1: a (set, bin) per workgroup of four waves;
+                            // 4: one per wave (short supports)
   const void *K;            // weights (Real)
   const int64_t *kstart;    // [n_bins]
   const int32_t *mlo;       // [n_bins] first window point of the support
@@ -184,8 +186,15 @@ hipError_t launch_opacity_only(const TableView &tv, const void *recs, int n_leve
                                int64_t nu_begin, int64_t nu_count, int64_t nu_stride,
                                void *chi, hipStream_t stream);
 
+// Items per convolution workgroup for a layout whose n_bins supports hold
+// nnz weights in total (the choice depends on the layout alone), and the
+// workgroups that n_items (set, bin) items of it take.
+int conv_items_per_wg(int64_t nnz, int n_bins);
+int64_t conv_workgroups(int64_t n_items, int items_per_wg);
+
+// total_wgs: the workgroups of all segments.
 hipError_t launch_convolve_bin(bool fp64, const ConvSeg *segs_dev, int n_segs,
-                               const ConvSeg *seg0_host, int64_t total_items, const void *in,
+                               const ConvSeg *seg0_host, int64_t total_wgs, const void *in,
                                void *out, hipStream_t stream);
 // ln L per set: the sum over bins of the terms k_convolve_bin wrote.
 hipError_t launch_lnl_reduce(const double *terms, int n_sets, int n_bins, double *lnl,

@@ -1220,36 +1220,73 @@ hipError_t launch_opacity_only(const TableView &tv, const void *recs, int n_leve
 }
 
 // ------------------------------------------------------ convolution + bins
-// One wave per (set, bin): bin_j = scale * sum_m K_j[m] F+[m] over the
-// bin's support (Eq. 9, 17 and the binning, composed into one banded row per
-// bin).  Lane-strided partial sums then a fixed butterfly: the result does
-// not depend on what else is in the launch.
+// bin_j = scale * sum_m K_j[m] F+[m] over the bin's support (Eq. 9, 17 and
+// the binning, composed into one banded row per bin).  A layout whose
+// supports average 512 points or more gets four waves per (set, bin), a
+// shorter one one wave per (set, bin) (four per workgroup).  Either way
+// lane-strided partial sums then a fixed butterfly, and the scheme depends
+// on the layout alone: a bin's value does not depend on what else is in the
+// launch.
+int conv_items_per_wg(int64_t nnz, int n_bins) {
+  return n_bins > 0 && nnz < (int64_t)512 * n_bins ? 4 : 1;
+}
+
+int64_t conv_workgroups(int64_t n_items, int items_per_wg) {
+  return (n_items + items_per_wg - 1) / items_per_wg;
+}
+
+// One thread's share of a support of len points: the item's WIDTH threads
+// stride it, four independent partial sums per thread so that a round's
+// loads are in flight together.
+template <typename Real, int WIDTH>
+__device__ __forceinline__ Real conv_partial(const Real *__restrict__ K,
+                                             const Real *__restrict__ F, int len, int q) {
+  Real a0 = (Real)0, a1 = (Real)0, a2 = (Real)0, a3 = (Real)0;
+  for (; q + 3 * WIDTH < len; q += 4 * WIDTH) {
+    const Real k0 = K[q], k1 = K[q + WIDTH], k2 = K[q + 2 * WIDTH], k3 = K[q + 3 * WIDTH];
+    const Real f0 = F[q], f1 = F[q + WIDTH], f2 = F[q + 2 * WIDTH], f3 = F[q + 3 * WIDTH];
+    a0 += k0 * f0;
+    a1 += k1 * f1;
+    a2 += k2 * f2;
+    a3 += k3 * f3;
+  }
+  if (q < len) a0 += K[q] * F[q];
+  if (q + WIDTH < len) a1 += K[q + WIDTH] * F[q + WIDTH];
+  if (q + 2 * WIDTH < len) a2 += K[q + 2 * WIDTH] * F[q + 2 * WIDTH];
+  return (a0 + a1) + (a2 + a3);
+}
+
 template <typename Real>
 __global__ __launch_bounds__(256) void k_convolve_bin(const ConvSeg *__restrict__ segs,
                                                       int n_segs, ConvSeg seg0,
-                                                      int64_t total_items,
+                                                      int64_t total_wgs,
                                                       const Real *__restrict__ in,
                                                       Real *__restrict__ out) {
   __shared__ Real part[4];
-  const int64_t it = blockIdx.x;
+  const int64_t g = blockIdx.x;
   int sg = 0;
   for (int lo = 0, hi = n_segs; hi - lo > 1;) {
     const int mid = (lo + hi) >> 1;
-    if (segs[mid].item_begin <= it) lo = mid;
+    if (segs[mid].item_begin <= g) lo = mid;
     else hi = mid;
     sg = lo;
   }
   const ConvSeg d = n_segs == 0 ? seg0 : segs[sg];   // n_segs == 0: the one segment by value
-  const int64_t local = it - d.item_begin;
+  const bool per_wave = d.items_per_wg == 4;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  const int64_t local = per_wave ? (g - d.item_begin) * 4 + wave : g - d.item_begin;
+  if (per_wave && local >= (int64_t)d.n_sets * d.n_bins) return;
   const int s = (int)(local / d.n_bins);
   const int jb = (int)(local - (int64_t)s * d.n_bins);
   const Real *K = (const Real *)d.K + d.kstart[jb];
   const int len = d.mlen[jb];
   const Real *F = in + d.in_offset + (int64_t)s * d.in_stride + d.mlo[jb];
-  // what thread 0 needs after the reduction, requested now so that it
-  // arrives with the data
+  // what the storing thread needs after the reduction, requested now so
+  // that it arrives with the data
+  const bool storer = per_wave ? lane == 0 : threadIdx.x == 0;
   double sc = d.scale_const, Dj = 0.0, s2 = 0.0, l10e = 0.0;
-  if (threadIdx.x == 0) {
+  if (storer) {
     if (d.scale) sc = d.scale[s];
     if (d.terms) {
       Dj = d.D[jb];
@@ -1257,30 +1294,17 @@ __global__ __launch_bounds__(256) void k_convolve_bin(const ConvSeg *__restrict_
       if (d.log10_eps) l10e = d.log10_eps[s];
     }
   }
-  // four independent partial sums, so that each thread's loads of a round
-  // are in flight together
-  Real a0 = (Real)0, a1 = (Real)0, a2 = (Real)0, a3 = (Real)0;
-  int q = threadIdx.x;
-  for (; q + 768 < len; q += 1024) {
-    const Real k0 = K[q], k1 = K[q + 256], k2 = K[q + 512], k3 = K[q + 768];
-    const Real f0 = F[q], f1 = F[q + 256], f2 = F[q + 512], f3 = F[q + 768];
-    a0 += k0 * f0;
-    a1 += k1 * f1;
-    a2 += k2 * f2;
-    a3 += k3 * f3;
-  }
-  if (q < len) a0 += K[q] * F[q];
-  if (q + 256 < len) a1 += K[q + 256] * F[q + 256];
-  if (q + 512 < len) a2 += K[q + 512] * F[q + 512];
-  Real acc = (a0 + a1) + (a2 + a3);
+  Real acc = per_wave ? conv_partial<Real, 64>(K, F, len, lane)
+                      : conv_partial<Real, 256>(K, F, len, (int)threadIdx.x);
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
-  const int wave = threadIdx.x >> 6;
-  if ((threadIdx.x & 63) == 0) part[wave] = acc;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    const Real tot = (part[0] + part[1]) + (part[2] + part[3]);
-    const Real v = tot * (Real)sc;
+  if (!per_wave) {
+    if (lane == 0) part[wave] = acc;
+    __syncthreads();
+    acc = (part[0] + part[1]) + (part[2] + part[3]);
+  }
+  if (storer) {
+    const Real v = acc * (Real)sc;
     if (out) out[d.out_offset + (int64_t)s * d.n_bins + jb] = v;
     if (d.terms) {
       // Eq. 19 term of bin j in FP64; with Eq. 22 the variance gains 10^eps
@@ -1292,18 +1316,18 @@ __global__ __launch_bounds__(256) void k_convolve_bin(const ConvSeg *__restrict_
 }
 
 hipError_t launch_convolve_bin(bool fp64, const ConvSeg *segs_dev, int n_segs,
-                               const ConvSeg *seg0_host, int64_t total_items, const void *in,
+                               const ConvSeg *seg0_host, int64_t total_wgs, const void *in,
                                void *out, hipStream_t stream) {
-  if (total_items <= 0) return hipSuccess;
-  const dim3 grid((unsigned)total_items);
+  if (total_wgs <= 0) return hipSuccess;
+  const dim3 grid((unsigned)total_wgs);
   const ConvSeg seg0 = seg0_host ? *seg0_host : ConvSeg{};
   const int ns = seg0_host ? 0 : n_segs;
   if (fp64)
     hipLaunchKernelGGL(k_convolve_bin<double>, grid, dim3(256), 0, stream, segs_dev, ns, seg0,
-                       total_items, (const double *)in, (double *)out);
+                       total_wgs, (const double *)in, (double *)out);
   else
     hipLaunchKernelGGL(k_convolve_bin<float>, grid, dim3(256), 0, stream, segs_dev, ns, seg0,
-                       total_items, (const float *)in, (float *)out);
+                       total_wgs, (const float *)in, (float *)out);
   return hipGetLastError();
 }
 

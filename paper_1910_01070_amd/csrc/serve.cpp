@@ -234,7 +234,7 @@ bool hr2_server::launch_step(StepSlot &sl, std::vector<Req *> &reqs) {
     int chunks, max_mu;
   };
   std::vector<Group> groups;
-  int64_t wg = 0, waves = 0;
+  int64_t wg = 0, conv_wgs = 0;
   for (size_t i = 0; i < reqs.size(); ++i) {
     Req &r = *reqs[i];
     const int mu_class = column_mu_class(r.n_mu);
@@ -274,7 +274,7 @@ bool hr2_server::launch_step(StepSlot &sl, std::vector<Req *> &reqs) {
     if (wg > 0x7fffffff) return false;
     ConvSeg &v = vs[i];
     std::memset(&v, 0, sizeof(v));
-    v.item_begin = waves;
+    v.item_begin = conv_wgs;
     v.K = blk + r.o_K;
     v.kstart = (const int64_t *)(blk + r.o_kstart);
     v.mlo = (const int32_t *)(blk + r.o_mlo);
@@ -285,7 +285,8 @@ bool hr2_server::launch_step(StepSlot &sl, std::vector<Req *> &reqs) {
     v.scale = cv.scale;
     v.n_sets = r.n_sets;
     v.n_bins = r.n_bins;
-    waves += (int64_t)r.n_sets * r.n_bins;
+    v.items_per_wg = conv_items_per_wg(r.plan.nnz, r.n_bins);
+    conv_wgs += conv_workgroups((int64_t)r.n_sets * r.n_bins, v.items_per_wg);
   }
   const size_t bytes_c = cs.size() * sizeof(ColSeg), bytes_v = vs.size() * sizeof(ConvSeg);
   const size_t total = round256(bytes_c) + bytes_v;
@@ -306,7 +307,7 @@ bool hr2_server::launch_step(StepSlot &sl, std::vector<Req *> &reqs) {
     if (launch_column(tv, dcs + gq.first, (int)gq.count, nullptr, gq.wgs, gq.chunks, base,
                       nullptr, base, gq.max_mu, false, para, s) != hipSuccess)
       return false;
-  if (launch_convolve_bin(fp64, dvs, (int)vs.size(), nullptr, waves, base, base, s) != hipSuccess)
+  if (launch_convolve_bin(fp64, dvs, (int)vs.size(), nullptr, conv_wgs, base, base, s) != hipSuccess)
     return false;
   for (Req *r : reqs)
     if (hipMemcpyAsync(pbase + r->pin_off + round256(r->upload), base + r->dev_off + r->o_bins,
