@@ -304,6 +304,7 @@ def run_c3(args):
     cols = wl.c3_columns()
     B = len(cols)
     ctx = hr2.Context(0)
+    ctx.set_option(hr2.OPT_CHUNKS, args.chunks)
     T = hr2.Tables(ctx, tab, "f32")
     obs = hr2.Obs(ctx, T, spec.window, spec.resolving_power, spec.edges_cm)
     p, Tk, x, lg, sc = _dev_columns(cols)
