@@ -279,6 +279,16 @@ def main():
         },
         "valu_roof": valu,
     }
+    if valu is not None:
+        # the binding roof: the larger of the kernel's HBM time at the peak
+        # (measured traffic when the counters match, else algorithmic bytes)
+        # and its VALU issue time, against the measured kernel time
+        hbm_us = (traffic if traffic else alg_bytes) / (HBM_PEAK_GBS * 1e9) * 1e6
+        valu_us = valu["valu_issue_us"]
+        roof_us = max(hbm_us, valu_us)
+        res["binding_roof"] = {"hbm_us": hbm_us, "valu_issue_us": valu_us,
+                               "bound": "valu" if valu_us >= hbm_us else "hbm",
+                               "kernel_us": col_ms * 1e3, "frac": roof_us / (col_ms * 1e3)}
     if not args.no_cpu_baseline:
         log("timing the oracle on the host")
         res["cpu_baseline"] = cpu_baseline(tab, cols[0], spec, n_mu, args.cpu_budget_s)
