@@ -382,8 +382,10 @@ hr2_status hr2_params_unpack_dev(hr2_ctx *ctx, const hr2_params *params, int n_s
                                  double *x_dev, double *log_g_dev, double *scale_dev,
                                  double *cloud_dev, double *log10_eps_dev, void *stream);
 
-/* Parameter vectors straight to spectra and/or ln L: unpack (above) into
- * context scratch, then the forward model, then (lnl_dev non-NULL) the
+/* Parameter vectors straight to spectra and/or ln L: the level stage forms
+ * each set's column from its vector (the same arithmetic as the unpack
+ * above, so results equal unpack-then-forward exactly), then the forward
+ * model, then (lnl_dev non-NULL) the
  * likelihood of Eq. 19, or Eq. 22-23 with the vector's own eps when the
  * layout has with_eps.  bins_dev: NULL or device hr2_real[n_sets][n_bins];
  * lnl_dev: NULL or device double[n_sets]; at least one of the two.
