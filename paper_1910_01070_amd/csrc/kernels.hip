@@ -7,7 +7,7 @@
 // points each (coalesced table rows); all per-level quantities are uniform
 // across the workgroup and arrive through scalar loads of a 128-byte record;
 // the table rows of the bilinear cell stay in registers between levels; the
-// layer recurrence may be split into up to four chunks whose affine maps
+// layer recurrence may be split into up to eight chunks whose affine maps
 // I_out = exp(-tau_c / mu) I_in + B_c are combined through LDS.
 #include <hip/hip_runtime.h>
 
@@ -92,8 +92,11 @@ __device__ __forceinline__ float fexp2(float x) { return __builtin_amdgcn_exp2f(
 __device__ __forceinline__ float frcp(float x) { return __builtin_amdgcn_rcpf(x); }
 
 // ------------------------------------------------------------ level records
-// One thread per (set, level).  Everything here is FP64; the column kernel
-// gets FP32 (FP64 for F64 tables) per-level constants:
+// Each workgroup stages one set (inputs and axes in LDS, every level's cell)
+// and runs independent items: per level, one for the cell, rows, weights and
+// masks, one for the layer above it, and one per species and CIA pair.
+// Everything here is FP64; the column kernel gets FP32 (FP64 for F64
+// tables) per-level constants:
 //   n = p / (k_B T); n_s = x_s n; x_H2 = (1 - sum x)/(1 + r), x_He = r x_H2;
 //   mubar; dz_l = k_B (T_l + T_l+1)/2 / (mubar m_u g) ln(p_l / p_l+1)
 //   (Sect. 2, 2.4, 5.2 and the hydrostatic reading of the optical depths);
@@ -688,11 +691,13 @@ __device__ __forceinline__ double sc_para_d(double I, double dtau_u, double dtau
 }
 
 // ------------------------------------------------------------ column kernel
-// Workgroup = 4 waves.  With C chunks, wave w handles sub-tile w / C (64
-// window points) and layer chunk w % C.  Each lane sweeps its chunk's levels
-// bottom to top: stage 1 (opacity, Sect. 2.3) from the slot registers,
-// dtau (trapezoid over the layer), Planck, and the recurrence for every
-// angle; then the chunks' affine maps are combined and Eq. 8 applied.
+// Workgroup = C waves over one 64-point tile of one set; wave c sweeps layer
+// chunk c: stage 1 (opacity, Sect. 2.3) from the slot registers, dtau
+// (trapezoid over the layer), Planck, and the recurrence for every angle.
+// Even chunks go bottom to top; with the linear source odd chunks compose
+// their layers' maps top down, so neighbouring chunks read the rows of their
+// shared boundary level at about the same time.  Then the chunks' affine
+// maps are combined through LDS and Eq. 8 applied.
 // BIG: the table spans 4 GiB or more, so each species gets its own buffer
 // resource; otherwise one resource covers the table and the species offset
 // rides in the scalar offset operand.
@@ -1398,7 +1403,8 @@ hipError_t launch_unpack(const ParamView &pv, int n_sets, const double *theta, d
 
 // ------------------------------------------------ observation layout build
 // Eq. 17 with the 5 sigma cut: for window point i, sigma_i = nu_i / (R 2
-// sqrt(2 ln 2)), h_i = the largest k with k dnu <= 5 sigma_i (host-computed),
+// sqrt(2 ln 2)), h_i = the largest k with k dnu <= 5 sigma_i (found here with
+// the host plan's operations, written out for the weights kernel),
 // g_i(k) = exp(-(k dnu)^2 / (2 sigma_i^2)), Z_i = sum of g_i over the
 // window.  Then per bin j with edges a < b: K_j(x) = 1/(b - a) *
 // sum_{i=a}^{b} c_i g_i(x - i) / Z_i, c_i = 1/2 at i = a, b and 1 inside
