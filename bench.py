@@ -131,11 +131,12 @@ def main():
     ap.add_argument("--cpu-budget-s", type=float, default=20.0)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy 5 times (counter scale)")
-    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4", "c5", "params"],
+    ap.add_argument("--workload", default="c2",
+                    choices=["c2", "c3", "c4", "c5", "params", "oracle"],
                     help="c2 (default): one realistic spectrum per step; c3: 512-set C1 batch "
                          "as a HIP graph vs 512 sequential calls; c4: reduced-precision "
                          "batches; c5: Poisson serving trace; params: parameter vectors "
-                         "to ln L")
+                         "to ln L; oracle: the FP64 oracle timed on the host")
     ap.add_argument("--source", type=int, default=1, choices=[1, 2],
                     help="short-characteristics source interpolant: 1 linear, 2 parabolic")
     ap.add_argument("--cloud", action="store_true",
@@ -149,6 +150,8 @@ def main():
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
         sys.exit(2)
+    if args.workload == "oracle":
+        return run_oracle_timing(args)   # host only
 
     import torch
     import workloads as wl
@@ -292,6 +295,54 @@ def main():
     if not args.no_cpu_baseline:
         log("timing the oracle on the host")
         res["cpu_baseline"] = cpu_baseline(tab, cols[0], spec, n_mu, args.cpu_budget_s)
+    print(json.dumps(res))
+
+
+def run_oracle_timing(args):
+    """The FP64 oracle timed on the host: per C1 and C2 spectrum with one thread
+    and with all of them (median of 3; one single-threaded C2 run), and the
+    C3 batch of 512 C1 sets.  Host-only; reports the core count and CPU."""
+    import oracle
+    import workloads as wl
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    all_threads = oracle.max_threads()
+
+    def med(fn, reps):
+        ts = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            fn()
+            ts.append(time.perf_counter() - t0)
+        return float(np.median(ts))
+
+    res = {"workload": "FP64 oracle on the host", "cpu": model, "nproc": os.cpu_count(),
+           "threads_all": all_threads}
+    t1 = wl.c1_table()
+    s1 = wl.c1_obs(t1)
+    c1 = wl.c1_columns()[-1]
+    f1 = lambda: oracle.forward(t1, c1, s1.window, s1.resolving_power, s1.edges_cm, 3)
+    t2 = wl.c2_table(n_nu=args.n_nu)
+    s2 = wl.c2_obs(t2)
+    c2 = wl.c2_column()
+    f2 = lambda: oracle.forward(t2, c2, s2.window, s2.resolving_power, s2.edges_cm, 3)
+    c3 = wl.c3_columns()
+    f3 = lambda: [oracle.forward(t1, c, s1.window, s1.resolving_power, s1.edges_cm, 3)
+                  for c in c3]
+    for n, tag in ((1, "1_thread"), (all_threads, "all_threads")):
+        oracle.set_threads(n)
+        log(f"oracle with {n} thread(s)")
+        res[f"c1_s_per_spectrum_{tag}"] = med(f1, 3)
+        res[f"c2_s_per_spectrum_{tag}"] = med(f2, 1 if n == 1 else 3)
+        res[f"c3_s_per_batch_of_512_{tag}"] = med(f3, 1)
+    oracle.set_threads(all_threads)
     print(json.dumps(res))
 
 

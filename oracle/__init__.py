@@ -48,6 +48,10 @@ def lib():
         if not os.path.exists(LIB_PATH) or os.path.getmtime(src) > os.path.getmtime(LIB_PATH):
             build(force=True)
         L = ctypes.CDLL(LIB_PATH)
+        L.or_set_threads.argtypes = [_I]
+        L.or_set_threads.restype = None
+        L.or_max_threads.argtypes = []
+        L.or_max_threads.restype = _I
         L.or_gauss_legendre01.argtypes = [_I, _DP, _DP]
         L.or_gauss_legendre01.restype = _I
         L.or_planck.argtypes = [_D, _D]
@@ -237,6 +241,15 @@ def log_likelihood(model, D, sigma, log10_eps=None):
     m, D, sg = _f64(model), _f64(D), _f64(sigma)
     return lib().or_lnl(len(m), _p(m), _p(D), _p(sg), 0 if log10_eps is None else 1,
                         0.0 if log10_eps is None else float(log10_eps))
+
+
+def set_threads(n):
+    """Threads of the oracle's OpenMP loops (for timing; results do not change)."""
+    lib().or_set_threads(int(n))
+
+
+def max_threads():
+    return int(lib().or_max_threads())
 
 
 # ------------------------------------------------------------- composition

@@ -18,6 +18,7 @@
 #include <stddef.h>
 #include <stdint.h>
 #include <stdlib.h>
+#include <omp.h>
 
 /* CODATA 2018 exact SI-defined constants in cgs, atomic mass constant. */
 #define OR_H 6.62607015e-27        /* erg s */
@@ -453,3 +454,11 @@ double or_lnl(int n_bins, const double *model, const double *D, const double *si
   }
   return lnl;
 }
+
+/* Threads of the OpenMP loops (timing runs of the oracle; the results do not
+ * depend on it: every loop writes independent outputs). */
+void or_set_threads(int n) {
+  if (n > 0) omp_set_num_threads(n);
+}
+
+int or_max_threads(void) { return omp_get_max_threads(); }
