@@ -168,9 +168,13 @@ hr2_status hr2_ctx_collect_timing(hr2_ctx *ctx, double ms[3], int64_t *n_calls);
  *                       log10_sigma * log2(10) values (FP64); F64 keeps
  *                       log10_sigma * log2(10) with no offset.  CIA rows are
  *                       float (double for F64) in every case.
- * Copies everything to the device; host arrays may be freed on return.
+ * Copies everything to the device; host arrays may be freed on return.  One
+ * species block (n_T * n_p rows of n_nu rounded up to 64 entries, in the
+ * storage type) and one CIA pair block must each stay below 4 GiB; the
+ * whole table may be larger.
  * Errors: HR2_E_INVALID_ARG (NULL, NaN/Inf, non-monotone axis, counts out of
- * [1, HR2_MAX_SPECIES], n_cia not 0/2), HR2_E_NO_MEMORY, HR2_E_DEVICE. */
+ * [1, HR2_MAX_SPECIES], n_cia not 0/2), HR2_E_OUT_OF_RANGE (a block of 4 GiB
+ * or more), HR2_E_NO_MEMORY, HR2_E_DEVICE. */
 typedef struct {
   int n_species, n_T, n_p;
   const double *T_K;

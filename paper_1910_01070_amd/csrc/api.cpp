@@ -361,8 +361,12 @@ extern "C" hr2_status hr2_tables_create(hr2_ctx *ctx, const hr2_tables_desc *d, 
 
   const int S = d->n_species, nT = d->n_T, nP = d->n_p, nc = d->n_cia;
   const int64_t n_nu = d->n_nu, pitch = (n_nu + 63) / 64 * 64;
-  // rows are addressed by 32-bit byte offsets inside one species block
-  if ((double)nT * nP * pitch * 8.0 >= 4294967296.0)
+  // rows are addressed by 32-bit byte offsets inside one species block (and
+  // inside one CIA pair block), in the storage type
+  const double elem = d->dtype == HR2_TABLE_F64 ? 8.0 : (d->dtype == HR2_TABLE_F32 ? 4.0 : 2.0);
+  const double cia_elem = d->dtype == HR2_TABLE_F64 ? 8.0 : 4.0;
+  if ((double)nT * nP * pitch * elem >= 4294967296.0 ||
+      (double)nT * pitch * cia_elem >= 4294967296.0)
     return set_error(HR2_E_OUT_OF_RANGE, "one species block of the table must stay below 4 GiB");
   HIP_TRY(hipSetDevice(ctx->device));
   auto *t = new hr2_tables();
