@@ -161,6 +161,43 @@ def test_multispecies_cia_windows(ctx, dtype, tol):
                 assert e_f <= tol and e_b <= tol, (w, L, chunks, s, e_f, e_b)
 
 
+@pytest.mark.parametrize("dtype,tol", [("f64", 1e-12), ("f32", 1e-5), ("f16", None)])
+def test_species_counts(ctx, dtype, tol):
+    """Every compiled species variant of the column kernel: 2, 5 and 8 species
+    (up to eight slots with guards, or exactly eight), 10 and 12 (the twelve-slot
+    variant), with CIA, fused path and the stage-1 call, FP64/FP32 against the
+    oracle and FP16 against the oracle on the dequantised table."""
+    names = ["H2O", "CH4", "CO", "CO2", "NH3", "H2S", "K", "X", "Na", "TiO", "VO", "FeH"]
+    for S in (2, 5, 8, 10, 12):
+        tab = wl.make_table(600 + S, names[:S], [250.0, 700.0, 1400.0, 2300.0],
+                            [-4.0, -1.5, 1.0, 2.5], 3000.0, 0.5, 700, n_lines=40,
+                            with_cia=True)
+        T = hr2.Tables(ctx, tab, dtype)
+        ref_tab = tu.dequantised(tab, dtype) if dtype == "f16" else tab
+        w = wl.Window(11, 650, 1)
+        nu_first, dnu = oracle.window_grid(tab, w)
+        edges = wl.snapped_edges(tab, w, wl.log_edges(nu_first + 60 * dnu, nu_first + 590 * dnu, 6))
+        obs = hr2.Obs(ctx, T, w, 500.0, edges)
+        cols = tu.small_columns(tab, 2, seed=S, n_levels=23)
+        t = tol if tol is not None else 1e-5
+        for chunks in (1, 3):
+            say(f"{S} species {dtype} chunks={chunks}")
+            bins, fplus = run_forward(ctx, T, obs, cols, 3, chunks)
+            for s, col in enumerate(cols):
+                ref = oracle.forward(ref_tab, col, w, 500.0, edges, 3)
+                e_f, _ = tu.max_rel_err(fplus[s], ref["fplus"])
+                e_b, _ = tu.max_rel_err(bins[s], ref["bins"])
+                assert e_f <= t and e_b <= t, (S, dtype, chunks, s, e_f, e_b)
+        chi = torch.empty(23 * w.count, dtype=T.real, device="cuda")
+        hr2.opacity(ctx, T, cols[0], w, chi)
+        torch.cuda.synchronize()
+        chi_ref = oracle.opacity(ref_tab, cols[0], oracle.window_indices(w))
+        e, _ = tu.max_rel_err(chi.cpu().numpy().astype(np.float64).reshape(23, -1), chi_ref)
+        assert e <= t, (S, dtype, e)
+        obs.close()
+        T.close()
+
+
 @pytest.mark.parametrize("dtype,tol", [("f64", 1e-12), ("f32", 1e-5)])
 def test_zigzag_temperature_profiles(ctx, dtype, tol):
     """Temperature profiles that cross the table's T nodes back and forth
