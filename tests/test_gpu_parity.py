@@ -199,6 +199,28 @@ def test_species_counts(ctx, dtype, tol):
 
 
 @pytest.mark.parametrize("dtype,tol", [("f64", 1e-12), ("f32", 1e-5)])
+def test_most_levels(ctx, dtype, tol):
+    """The largest column the library takes (HR2_MAX_LEVELS = 1024 levels) in
+    one chunk, in the automatic chunking and in eight chunks."""
+    tab = tu.small_multi_table()
+    T = hr2.Tables(ctx, tab, dtype)
+    w = wl.Window(1500, 300, 1)
+    nu_first, dnu = oracle.window_grid(tab, w)
+    edges = wl.snapped_edges(tab, w, wl.log_edges(nu_first + 40 * dnu, nu_first + 260 * dnu, 4))
+    obs = hr2.Obs(ctx, T, w, 400.0, edges)
+    col = tu.small_columns(tab, 1, seed=1024, n_levels=1024)[0]
+    ref = oracle.forward(tab, col, w, 400.0, edges, 3)
+    for chunks in (1, 0, 8):
+        say(f"1024 levels {dtype} chunks={chunks}")
+        bins, fplus = run_forward(ctx, T, obs, [col], 3, chunks)
+        e_f, _ = tu.max_rel_err(fplus[0], ref["fplus"])
+        e_b, _ = tu.max_rel_err(bins[0], ref["bins"])
+        assert e_f <= tol and e_b <= tol, (dtype, chunks, e_f, e_b)
+    obs.close()
+    T.close()
+
+
+@pytest.mark.parametrize("dtype,tol", [("f64", 1e-12), ("f32", 1e-5)])
 def test_zigzag_temperature_profiles(ctx, dtype, tol):
     """Temperature profiles that cross the table's T nodes back and forth
     (and leave the axis at both ends), so that table rows leave the cell and
