@@ -512,10 +512,11 @@ __device__ __forceinline__ float sc_step_f(float I, float dtau, float rD, float 
 // beta comes from its series and gamma = Delta (1 - beta) - beta,
 // e = 1 - Delta (1 - beta).  Used by the parabolic sweep for its linear
 // steps, where it needs no per-layer source difference in registers.
-__device__ __forceinline__ float sc_step_weights_f(float I, float dtau, float rdt, float S1,
-                                                   float S0, float inv_mu, float l2e_mu, float mu) {
+__device__ __forceinline__ void sc_weights_coef_f(float dtau, float rdt, float S1, float S0,
+                                                  float inv_mu, float l2e_mu, float mu, float &e,
+                                                  float &c) {
   const float d = dtau * inv_mu;
-  float e, beta, gamma;
+  float beta, gamma;
   if (d < 0.5f) {
     float b = -1.0f / 362880.0f;
     b = fmaf(b, d, 1.0f / 40320.0f);
@@ -535,7 +536,14 @@ __device__ __forceinline__ float sc_step_weights_f(float I, float dtau, float rd
     beta = 1.0f - u;
     gamma = u - e;
   }
-  return fmaf(e, I, fmaf(beta, S1, gamma * S0));
+  c = fmaf(beta, S1, gamma * S0);
+}
+
+__device__ __forceinline__ float sc_step_weights_f(float I, float dtau, float rdt, float S1,
+                                                   float S0, float inv_mu, float l2e_mu, float mu) {
+  float e, c;
+  sc_weights_coef_f(dtau, rdt, S1, S0, inv_mu, l2e_mu, mu, e, c);
+  return fmaf(e, I, c);
 }
 
 // The layer as an affine map I -> e I + c (FP64), for sweeps that compose
@@ -569,12 +577,13 @@ __device__ __forceinline__ double sc_step_d(double I, double dtau, double S1, do
 // q1 = w1/du^2 and q21 = (w2 - du w1)/du^3, free of cancellation; dd > 0.
 // r_s = 1/(dtau_u + dtau_d) and r_d = 1/dtau_d, r_u = 1/dtau_u are shared
 // by the angles.
-__device__ __forceinline__ float sc_para_f(float I, float dtau_u, float dtau_d, float r_u,
-                                           float r_d, float r_s, float S_up, float S_loc,
-                                           float S_dn, float inv_mu, float l2e_mu, float mu) {
+__device__ __forceinline__ void sc_para_coef_f(float dtau_u, float dtau_d, float r_u, float r_d,
+                                               float r_s, float S_up, float S_loc, float S_dn,
+                                               float inv_mu, float l2e_mu, float mu, float &e,
+                                               float &c) {
   const float du = dtau_u * inv_mu, dd = dtau_d * inv_mu;
   const float i_s = mu * r_s;   // 1 / (du + dd)
-  float e, w0, gam, alp;
+  float w0, gam, alp;
   if (du < 0.5f) {
     // Horner in -du; coefficients 1/(m+1)!, 1/(m! (m+2)), -1/(m! (m+2)(m+3)), m = 9 .. 0
     const float x = -du;
@@ -618,14 +627,27 @@ __device__ __forceinline__ float sc_para_f(float I, float dtau_u, float dtau_d, 
     gam = fmaf(dd, w1, w2) * (mu * r_u) * i_s;
     alp = fmaf(-du, w1, w2) * (mu * r_d) * i_s;
   }
-  return fmaf(e, I, fmaf(w0, S_loc, fmaf(gam, S_up - S_loc, alp * (S_dn - S_loc))));
+  c = fmaf(w0, S_loc, fmaf(gam, S_up - S_loc, alp * (S_dn - S_loc)));
 }
 
-__device__ __forceinline__ double sc_para_d(double I, double dtau_u, double dtau_d, double S_up,
-                                            double S_loc, double S_dn, double mu) {
-  if (dtau_u == 0.0) return I;
+__device__ __forceinline__ float sc_para_f(float I, float dtau_u, float dtau_d, float r_u,
+                                           float r_d, float r_s, float S_up, float S_loc,
+                                           float S_dn, float inv_mu, float l2e_mu, float mu) {
+  float e, c;
+  sc_para_coef_f(dtau_u, dtau_d, r_u, r_d, r_s, S_up, S_loc, S_dn, inv_mu, l2e_mu, mu, e, c);
+  return fmaf(e, I, c);
+}
+
+__device__ __forceinline__ void sc_para_coef_d(double dtau_u, double dtau_d, double S_up,
+                                               double S_loc, double S_dn, double mu, double &e,
+                                               double &c) {
+  if (dtau_u == 0.0) {
+    e = 1.0;
+    c = 0.0;
+    return;
+  }
   const double du = dtau_u / mu, dd = dtau_d / mu;
-  double e, w0, gam, alp;
+  double w0, gam, alp;
   if (du < 0.5) {
     // the series of the FP32 step, to m = 16 (FP64 accuracy at du = 1/2)
     const double x = -du;
@@ -690,16 +712,23 @@ __device__ __forceinline__ double sc_para_d(double I, double dtau_u, double dtau
     gam = (w2 + dd * w1) / (du * (du + dd));
     alp = (w2 - du * w1) / (dd * (du + dd));
   }
-  return e * I + w0 * S_loc + gam * (S_up - S_loc) + alp * (S_dn - S_loc);
+  c = w0 * S_loc + gam * (S_up - S_loc) + alp * (S_dn - S_loc);
+}
+
+__device__ __forceinline__ double sc_para_d(double I, double dtau_u, double dtau_d, double S_up,
+                                            double S_loc, double S_dn, double mu) {
+  double e, c;
+  sc_para_coef_d(dtau_u, dtau_d, S_up, S_loc, S_dn, mu, e, c);
+  return e * I + c;
 }
 
 // ------------------------------------------------------------ column kernel
 // Workgroup = C waves over one 64-point tile of one set; wave c sweeps layer
 // chunk c: stage 1 (opacity, Sect. 2.3) from the slot registers, dtau
 // (trapezoid over the layer), Planck, and the recurrence for every angle.
-// Even chunks go bottom to top; with the linear source odd chunks compose
-// their layers' maps top down, so neighbouring chunks read the rows of their
-// shared boundary level at about the same time.  Then the chunks' affine
+// Even chunks go bottom to top; odd chunks compose their layers' maps top
+// down, so neighbouring chunks read the rows of their shared boundary level
+// at about the same time.  Then the chunks' affine
 // maps are combined through LDS and Eq. 8 applied.
 // BIG: the table spans 4 GiB or more, so each species gets its own buffer
 // resource; otherwise one resource covers the table and the species offset
@@ -708,8 +737,23 @@ __device__ __forceinline__ double sc_para_d(double I, double dtau_u, double dtau
 // per-species guards), otherwise tv.S <= NS species with uniform guards.
 // PARA: parabolic source (each step also needs the downwind level, so a
 // chunk below the top reads one level past its end).
+// Angle tiers compiled: up to 3 angles (registers for exactly 3), else up
+// to 8.  A request runs the kernel of its tier.
+constexpr int kMuTierSmall = 3;
+
+// Occupancy floor per instantiation: the FP32 parabolic sweep with an exact
+// species count and the small angle tier fits in 72 VGPRs (7 waves per SIMD)
+// without spilling when asked to, where the compiler otherwise takes 73-74
+// (6 waves).  Everything else keeps the compiler's choice.
+template <typename Real, int NSS, int MAXMU, bool PARA>
+constexpr int column_min_waves() {
+  return (PARA && !std::is_same<Real, double>::value && NSS < 0 && MAXMU <= kMuTierSmall) ? 7
+                                                                                          : 1;
+}
+
 template <typename Real, typename TT, int NSS, int MAXMU, bool FROM_CHI, bool BIG, bool PARA>
-__global__ __launch_bounds__(512) void k_column(TableView tv, const ColSeg *__restrict__ segs,
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(
+    column_min_waves<Real, NSS, MAXMU, PARA>()))) void k_column(TableView tv, const ColSeg *__restrict__ segs,
                                                 int n_segs, ColSeg seg0, int64_t total_wgs,
                                                 const void *__restrict__ recs_v,
                                                 const void *__restrict__ chi_in_v,
@@ -882,17 +926,18 @@ __global__ __launch_bounds__(512) void k_column(TableView tv, const ColSeg *__re
       return planck_f(nu_hi, nu_lo, c1nu3_f, r.pl_hi, r.pl_lo);
   };
 
-  // Odd chunks (linear source) compose their layers' maps from the top
-  // down, so that the rows at each chunk boundary are read by the two chunks
-  // that share it at about the same time (the second read is an L2 hit)
-  // instead of at opposite ends of the sweep.
-  const bool down = !PARA && (chunk & 1) != 0;
+  // Odd chunks compose their layers' maps from the top down, so that the
+  // rows at each chunk boundary are read by the two chunks that share it at
+  // about the same time (the second read is an L2 hit) instead of at
+  // opposite ends of the sweep.  With the parabolic source the sweep starts
+  // at l_end, the downwind level of the chunk's top layer.
+  const bool down = (chunk & 1) != 0;
   if (down && l0 < nlay) {
-    if constexpr (!FROM_CHI) fetch(rec[l1], rec[l1].mask >> 8);
+    if constexpr (!FROM_CHI) fetch(rec[l_end], rec[l_end].mask >> 8);
     Real A[MAXMU];   // transmission of the layers composed so far
 #pragma unroll
     for (int k = 0; k < MAXMU; ++k) A[k] = (Real)1;
-    for (int l = l1; l >= l0; --l) {
+    for (int l = l_end; l >= l0; --l) {
       const Rec r = rec[l];
       const Real chi = opacity(r, l);
       if constexpr (!FROM_CHI) {
@@ -903,29 +948,70 @@ __global__ __launch_bounds__(512) void k_column(TableView tv, const ColSeg *__re
         }
       }
       const Real Sl = source(r);
-      if (l < l1) {
+      if (l < l_end) {
         // layer l -> l+1: lower level l (S0 = Sl), upper level l+1 (S1 = S_prev)
         const Real dtau = (chi + chi_prev) * r.hdz + r.dtc;
-        tau += dtau;
-        if constexpr (kF64) {
+        if constexpr (!PARA) {
+          tau += dtau;
+          if constexpr (kF64) {
 #pragma unroll
-          for (int k = 0; k < MAXMU; ++k)
-            if (k < nmu) {
-              double e, c;
-              sc_coef_d(dtau, S_prev, Sl, a_mud[k], e, c);
-              I[k] = fma(A[k], c, I[k]);
-              A[k] *= e;
-            }
+            for (int k = 0; k < MAXMU; ++k)
+              if (k < nmu) {
+                double e, c;
+                sc_coef_d(dtau, S_prev, Sl, a_mud[k], e, c);
+                I[k] = fma(A[k], c, I[k]);
+                A[k] *= e;
+              }
+          } else {
+            const float D = Sl - S_prev, rD = D * frcp(dtau);
+#pragma unroll
+            for (int k = 0; k < MAXMU; ++k)
+              if (k < nmu) {
+                float e, uD;
+                sc_coef_f(dtau, rD, D, a_inv[k], a_l2e[k], a_mu[k], e, uD);
+                I[k] = fmaf(A[k], fmaf(-e, Sl, S_prev) + uD, I[k]);
+                A[k] *= e;
+              }
+          }
         } else {
-          const float D = Sl - S_prev, rD = D * frcp(dtau);
+          if (l < l1) {
+            tau += dtau;
+            // upwind level l, local l+1, downwind l+2 (S_pp, across the layer
+            // of optical depth dtau_last) once the sweep has been there; a
+            // transparent downwind layer leaves the linear coefficients
+            const bool has_dn = l + 2 <= l_end;
+            if constexpr (kF64) {
 #pragma unroll
-          for (int k = 0; k < MAXMU; ++k)
-            if (k < nmu) {
-              float e, uD;
-              sc_coef_f(dtau, rD, D, a_inv[k], a_l2e[k], a_mu[k], e, uD);
-              I[k] = fmaf(A[k], fmaf(-e, Sl, S_prev) + uD, I[k]);
-              A[k] *= e;
+              for (int k = 0; k < MAXMU; ++k)
+                if (k < nmu) {
+                  double e, c;
+                  if (has_dn && dtau_last > 0.0)
+                    sc_para_coef_d(dtau, dtau_last, Sl, S_prev, S_pp, a_mud[k], e, c);
+                  else
+                    sc_coef_d(dtau, S_prev, Sl, a_mud[k], e, c);
+                  I[k] = fma(A[k], c, I[k]);
+                  A[k] *= e;
+                }
+            } else {
+              const float r_u = frcp(dtau), r_d = frcp(dtau_last),
+                          r_s = frcp(dtau + dtau_last);
+              const bool para = has_dn && dtau_last > 0.0f;
+#pragma unroll
+              for (int k = 0; k < MAXMU; ++k)
+                if (k < nmu) {
+                  float e, c;
+                  if (para)
+                    sc_para_coef_f(dtau, dtau_last, r_u, r_d, r_s, Sl, S_prev, S_pp, a_inv[k],
+                                   a_l2e[k], a_mu[k], e, c);
+                  else
+                    sc_weights_coef_f(dtau, r_u, S_prev, Sl, a_inv[k], a_l2e[k], a_mu[k], e, c);
+                  I[k] = fmaf(A[k], c, I[k]);
+                  A[k] *= e;
+                }
             }
+          }
+          S_pp = S_prev;
+          dtau_last = dtau;
         }
       }
       chi_prev = chi;
@@ -1073,9 +1159,6 @@ static ColumnKernel ck() {
                       (int)sizeof(Real)};
 }
 
-// Angle tiers compiled: up to 3 angles (registers for exactly 3), else up
-// to 8.  A request runs the kernel of its tier.
-constexpr int kMuTierSmall = 3;
 int column_mu_class(int n_mu) { return n_mu > kMuTierSmall ? 8 : kMuTierSmall; }
 
 template <typename Real, typename TT, bool FROM_CHI, bool PARA>
