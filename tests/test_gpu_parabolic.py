@@ -75,6 +75,29 @@ def test_c1_parabolic_all_chunkings(ctx, dtype, tol):
 
 
 @pytest.mark.parametrize("dtype,tol", [("f64", 1e-12), ("f32", 1e-5)])
+def test_parabolic_angle_counts(ctx, dtype, tol):
+    """Both compiled angle tiers (up to 3, and 4 to 8 angles) with upward-only
+    (one chunk) and alternating upward / downward layer chunks."""
+    tab = tu.c1_table()
+    cols = wl.c1_columns()[1:4]
+    spec = wl.c1_obs(tab)
+    T = hr2.Tables(ctx, tab, dtype)
+    obs = hr2.Obs(ctx, T, spec.window, spec.resolving_power, spec.edges_cm)
+    for n_mu in (1, 2, 4, 5, 8):
+        refs = [oracle.forward(tab, c, spec.window, spec.resolving_power, spec.edges_cm, n_mu,
+                               order=2) for c in cols]
+        for chunks in (1, 2, 3, 8):
+            say(f"C1 {dtype} parabolic: n_mu={n_mu} chunks={chunks}")
+            bins, fplus = run_forward(ctx, T, obs, cols, n_mu, chunks)
+            for s, ref in enumerate(refs):
+                e_f, _ = tu.max_rel_err(fplus[s], ref["fplus"])
+                e_b, _ = tu.max_rel_err(bins[s], ref["bins"])
+                assert e_f <= tol and e_b <= tol, (dtype, n_mu, chunks, s, e_f, e_b)
+    obs.close()
+    T.close()
+
+
+@pytest.mark.parametrize("dtype,tol", [("f64", 1e-12), ("f32", 1e-5)])
 def test_multispecies_windows_parabolic(ctx, dtype, tol):
     tab = tu.small_multi_table()
     T = hr2.Tables(ctx, tab, dtype)
@@ -109,12 +132,15 @@ def test_stage_rt_parabolic(ctx, dtype, tol):
     st = oracle.column_state(tab, col)
     nu = tab.nu0_cm + oracle.window_indices(w) * tab.dnu_cm
     for n_mu in (1, 2, 3, 4, 8):
-        hr2.rt_emission(ctx, T, col, w, chi_in.reshape(-1), n_mu, fplus)
-        torch.cuda.synchronize()
         ref = oracle.rt_emission(chi_ref, st["dz"], col.T_K, nu, n_mu, order=2)
-        e, _ = tu.max_rel_err(fplus.cpu().numpy(), ref)
-        say(f"  stage {dtype} n_mu={n_mu}: F+ {e:.2e}")
-        assert e <= tol
+        for chunks in (0, 1, 2, 5):
+            ctx.set_option(hr2.OPT_CHUNKS, chunks)
+            hr2.rt_emission(ctx, T, col, w, chi_in.reshape(-1), n_mu, fplus)
+            torch.cuda.synchronize()
+            ctx.set_option(hr2.OPT_CHUNKS, 0)
+            e, _ = tu.max_rel_err(fplus.cpu().numpy(), ref)
+            say(f"  stage {dtype} n_mu={n_mu} chunks={chunks}: F+ {e:.2e}")
+            assert e <= tol, (n_mu, chunks, e)
     say("isothermal column: pi B whatever the opacity")
     iso = wl.Column(col.p_bar, np.full(col.n_levels, 1234.0), col.x, col.log_g, col.scale)
     hr2.rt_emission(ctx, T, iso, w, chi_in.reshape(-1), 3, fplus)

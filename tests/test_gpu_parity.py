@@ -108,15 +108,19 @@ def test_stage_calls(ctx, dtype, tol):
     say(f"stage calls {dtype}: rt_emission from the oracle's chi")
     chi_in = torch.from_numpy(chi_ref.astype(np.float64 if dtype == "f64" else np.float32)).cuda()
     fplus = torch.empty(w.count, dtype=T.real, device="cuda")
+    st = oracle.column_state(tab, col)
+    nu = tab.nu0_cm + oracle.window_indices(w) * tab.dnu_cm
     for n_mu in (1, 2, 3, 4, 5, 8):
-        hr2.rt_emission(ctx, T, col, w, chi_in.reshape(-1), n_mu, fplus)
-        torch.cuda.synchronize()
-        st = oracle.column_state(tab, col)
-        nu = tab.nu0_cm + oracle.window_indices(w) * tab.dnu_cm
         ref = oracle.rt_emission(chi_ref, st["dz"], col.T_K, nu, n_mu)
-        e, _ = tu.max_rel_err(fplus.cpu().numpy(), ref)
-        say(f"  n_mu={n_mu}: F+ {e:.2e}")
-        assert e <= tol
+        # automatic, upward only, and alternating upward / downward chunks
+        for chunks in (0, 1, 2, 5):
+            ctx.set_option(hr2.OPT_CHUNKS, chunks)
+            hr2.rt_emission(ctx, T, col, w, chi_in.reshape(-1), n_mu, fplus)
+            torch.cuda.synchronize()
+            ctx.set_option(hr2.OPT_CHUNKS, 0)
+            e, _ = tu.max_rel_err(fplus.cpu().numpy(), ref)
+            say(f"  n_mu={n_mu} chunks={chunks}: F+ {e:.2e}")
+            assert e <= tol, (n_mu, chunks, e)
     say(f"stage calls {dtype}: convolve_bin from the oracle's F+")
     edges = wl.snapped_edges(tab, w, wl.log_edges(2030.0, 3430.0, 37))
     obs = hr2.Obs(ctx, T, w, 250.0, edges)
