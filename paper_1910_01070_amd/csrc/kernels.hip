@@ -1606,16 +1606,24 @@ __global__ __launch_bounds__(256) void k_obs_norm_f32(int64_t N, double nu_first
   invz_out[t] = (float)(1.0 / z);
 }
 
+// k_obs_weights: workgroup size and lanes per stored weight
+constexpr int kObsWeightThreads = 256;
+constexpr int kObsLanes = 4;
+
 template <typename Real>
-__global__ __launch_bounds__(256) void k_obs_weights(int n_bins, int64_t nnz,
+__global__ __launch_bounds__(kObsWeightThreads) void k_obs_weights(int n_bins, int64_t nnz,
                                                      const int64_t *edge_idx, const int32_t *h,
                                                      int64_t i0, const Real *q, const Real *invz,
                                                      double dnu, const int64_t *kstart,
                                                      const int32_t *mlo, Real *K) {
-  // one thread per stored weight: find its bin, then sum the bin's
-  // Gaussians that reach this point
-  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (e >= nnz) return;
+  // four lanes per stored weight: find its bin, then each lane sums every
+  // fourth of the bin's Gaussians that reach this point (in the order of i),
+  // and a fixed two-step butterfly adds the four partial sums
+  const int64_t e_raw = (int64_t)blockIdx.x * (kObsWeightThreads / kObsLanes) +
+                        (threadIdx.x / kObsLanes);
+  const int part = threadIdx.x % kObsLanes;
+  const bool live = e_raw < nnz;
+  const int64_t e = live ? e_raw : nnz - 1;   // spare lanes still join the butterfly
   int lo = 0, hi = n_bins;   // largest j with kstart[j] <= e
   while (hi - lo > 1) {
     const int mid = (lo + hi) >> 1;
@@ -1646,15 +1654,17 @@ __global__ __launch_bounds__(256) void k_obs_weights(int n_bins, int64_t nnz,
     }
     return fma(ci * gk, ak <= hi_i ? zi : (Real)0, acc);
   };
-  // the terms are added in the order of i; eight points' loads and
-  // exponentials are issued together
+  // four of this lane's points' loads and exponentials are issued together
   Real acc = (Real)0;
-  int64_t i = ia;
-  for (; i + 7 <= ib; i += 8) {
+  int64_t i = ia + part;
+  for (; i + 3 * kObsLanes <= ib; i += 4 * kObsLanes) {
 #pragma unroll
-    for (int u = 0; u < 8; ++u) acc = term(i + u, acc);
+    for (int u = 0; u < 4; ++u) acc = term(i + u * kObsLanes, acc);
   }
-  for (; i <= ib; ++i) acc = term(i, acc);
+  for (; i <= ib; i += kObsLanes) acc = term(i, acc);
+#pragma unroll
+  for (int off = 1; off < kObsLanes; off <<= 1) acc += __shfl_xor(acc, off, 64);
+  if (!live || part != 0) return;
   K[e] = acc * (Real)(1.0 / (double)(b - a));
 }
 
@@ -1664,11 +1674,12 @@ hipError_t launch_obs_build(bool fp64, int64_t N, double nu_first, double dnu_ef
                             const int64_t *kstart_dev, const int32_t *mlo_dev, void *K_dev,
                             hipStream_t stream) {
   const dim3 g1((unsigned)((n_pts + 3) / 4));
-  const dim3 g2((unsigned)((nnz + 255) / 256));
+  const int64_t per_wg = kObsWeightThreads / kObsLanes;
+  const dim3 g2((unsigned)((nnz + per_wg - 1) / per_wg));
   if (fp64) {
     hipLaunchKernelGGL(k_obs_norm_f64, g1, dim3(256), 0, stream, N, nu_first, dnu_eff, denom,
                        h_dev, i0, n_pts, (double *)q_scratch, (double *)invz_scratch);
-    hipLaunchKernelGGL(k_obs_weights<double>, g2, dim3(256), 0, stream, n_bins, nnz,
+    hipLaunchKernelGGL(k_obs_weights<double>, g2, dim3(kObsWeightThreads), 0, stream, n_bins, nnz,
                        edge_idx_dev, h_dev, i0, (const double *)q_scratch,
                        (const double *)invz_scratch, dnu_eff, kstart_dev, mlo_dev,
                        (double *)K_dev);
@@ -1676,7 +1687,7 @@ hipError_t launch_obs_build(bool fp64, int64_t N, double nu_first, double dnu_ef
     hipLaunchKernelGGL(k_obs_norm_f32, dim3((unsigned)((n_pts + 255) / 256)), dim3(256), 0,
                        stream, N, nu_first, dnu_eff, denom, h_dev, i0, n_pts, (float *)q_scratch,
                        (float *)invz_scratch);
-    hipLaunchKernelGGL(k_obs_weights<float>, g2, dim3(256), 0, stream, n_bins, nnz, edge_idx_dev,
+    hipLaunchKernelGGL(k_obs_weights<float>, g2, dim3(kObsWeightThreads), 0, stream, n_bins, nnz, edge_idx_dev,
                        h_dev, i0, (const float *)q_scratch, (const float *)invz_scratch, dnu_eff,
                        kstart_dev, mlo_dev, (float *)K_dev);
   }
