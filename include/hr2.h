@@ -248,7 +248,9 @@ hr2_status hr2_rt_emission(hr2_ctx *ctx, const hr2_tables *tables, const hr2_col
  * window point; snapped edges must be strictly increasing.  The convolution
  * and binning are linear, so the layout is held as one banded weight row per
  * bin (the composite of trapezoid weights and renormalised Gaussians), built
- * on the device.  Blocks until built.  Errors: HR2_E_INVALID_ARG,
+ * on the device; with FP64 tables the Gaussians' normalisations are summed
+ * tap by tap, otherwise they come from a closed form (Euler-Maclaurin) that
+ * equals those sums within 1e-9 relative.  Blocks until built.  Errors: HR2_E_INVALID_ARG,
  * HR2_E_OUT_OF_RANGE (window, or a snapped edge outside it), HR2_E_NO_MEMORY. */
 hr2_status hr2_obs_create(hr2_ctx *ctx, const hr2_tables *tables, hr2_window window,
                           double resolving_power, int n_bins, const double *bin_edges_cm,
