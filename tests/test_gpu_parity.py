@@ -393,6 +393,47 @@ def test_abi_errors_leave_outputs_untouched(ctx):
     assert ei.value.status == hr2.E_INVALID_ARG
 
 
+@pytest.mark.parametrize("dtype,tol", [("f64", 1e-12), ("f32", 1e-5)])
+def test_degenerate_sizes(ctx, dtype, tol):
+    """An empty batch and an empty window are refused before anything runs;
+    the smallest windows (two and three points in one bin), one-layer and
+    two-layer columns, one angle, and one full tile plus a one-point tail
+    match the oracle through every chunking."""
+    tab = tu.small_multi_table()
+    T = hr2.Tables(ctx, tab, dtype)
+    w0 = wl.Window(10, 200, 1)
+    nu0, d0 = oracle.window_grid(tab, w0)
+    obs0 = hr2.Obs(ctx, T, w0, 300.0, [nu0 + 20 * d0, nu0 + 150 * d0])
+    bins0 = torch.full((obs0.n_bins,), 7.0, dtype=T.real, device="cuda")
+    with pytest.raises(hr2.HR2Error) as ei:
+        hr2.forward_batch(ctx, T, obs0, [], 3, bins0)
+    assert ei.value.status == hr2.E_INVALID_ARG
+    torch.cuda.synchronize()
+    assert torch.all(bins0 == 7.0)
+    obs0.close()
+    with pytest.raises(hr2.HR2Error) as ei:
+        hr2.Obs(ctx, T, wl.Window(10, 0, 1), 300.0, [nu0, nu0 + d0])
+    assert ei.value.status == hr2.E_OUT_OF_RANGE
+    cases = [(wl.Window(500, 2, 1), 2, 1), (wl.Window(77, 3, 5), 2, 3),
+             (wl.Window(5, 65, 3), 3, 1), (wl.Window(1000, 65, 1), 41, 8)]
+    for w, L, n_mu in cases:
+        cols = tu.small_columns(tab, 2, seed=L + w.count, n_levels=L)
+        nu_first, dnu = oracle.window_grid(tab, w)
+        edges = [nu_first, nu_first + (w.count - 1) * dnu]
+        obs = hr2.Obs(ctx, T, w, 300.0, edges)
+        refs = [oracle.forward(tab, c, w, 300.0, edges, n_mu) for c in cols]
+        for chunks in (0, 1, 3):
+            bins, fplus = run_forward(ctx, T, obs, cols, n_mu, chunks)
+            for s, ref in enumerate(refs):
+                e_f, _ = tu.max_rel_err(fplus[s], ref["fplus"])
+                e_b, _ = tu.max_rel_err(bins[s], ref["bins"])
+                assert e_f <= tol and e_b <= tol, (w, L, n_mu, chunks, s, e_f, e_b)
+        say(f"{dtype} window {w} L={L} n_mu={n_mu}: ok")
+        obs.close()
+    ctx.set_option(hr2.OPT_CHUNKS, 0)
+    T.close()
+
+
 # ------------------------------------------------------------------- C2 / C4
 
 
