@@ -68,24 +68,22 @@ __device__ __forceinline__ rsrc_t make_rsrc(const void *base, int64_t bytes) {
                                            0x00020000);
 }
 // soff: a uniform byte offset added by the hardware (scalar operand).
-template <typename TT> __device__ __forceinline__ TT buf_load(rsrc_t r, uint32_t off, uint32_t soff);
-template <>
-__device__ __forceinline__ float buf_load<float>(rsrc_t r, uint32_t off, uint32_t soff) {
-  return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, off, soff, 0));
-}
-template <>
-__device__ __forceinline__ _Float16 buf_load<_Float16>(rsrc_t r, uint32_t off, uint32_t soff) {
-  const unsigned short u = __builtin_amdgcn_raw_buffer_load_b16(r, off, soff, 0);
-  return __builtin_bit_cast(_Float16, u);
-}
-template <>
-__device__ __forceinline__ uint16_t buf_load<uint16_t>(rsrc_t r, uint32_t off, uint32_t soff) {
-  return __builtin_amdgcn_raw_buffer_load_b16(r, off, soff, 0);
-}
-template <>
-__device__ __forceinline__ double buf_load<double>(rsrc_t r, uint32_t off, uint32_t soff) {
-  const auto v = __builtin_amdgcn_raw_buffer_load_b64(r, off, soff, 0);
-  return __builtin_bit_cast(double, v);
+// CPOL: the load's cache-policy bits (0, or kCpolStream for rows read once).
+constexpr int kCpolStream = 2;   // nt: non-temporal
+template <typename TT, int CPOL = 0>
+__device__ __forceinline__ TT buf_load(rsrc_t r, uint32_t off, uint32_t soff) {
+  if constexpr (std::is_same<TT, float>::value) {
+    return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, off, soff, CPOL));
+  } else if constexpr (std::is_same<TT, _Float16>::value) {
+    const unsigned short u = __builtin_amdgcn_raw_buffer_load_b16(r, off, soff, CPOL);
+    return __builtin_bit_cast(_Float16, u);
+  } else if constexpr (std::is_same<TT, uint16_t>::value) {
+    return __builtin_amdgcn_raw_buffer_load_b16(r, off, soff, CPOL);
+  } else {
+    static_assert(std::is_same<TT, double>::value, "table element type");
+    const auto v = __builtin_amdgcn_raw_buffer_load_b64(r, off, soff, CPOL);
+    return __builtin_bit_cast(double, v);
+  }
 }
 
 __device__ __forceinline__ float fexp2(float x) { return __builtin_amdgcn_exp2f(x); }
@@ -723,20 +721,6 @@ __device__ __forceinline__ double sc_para_d(double I, double dtau_u, double dtau
 }
 
 // ------------------------------------------------------------ column kernel
-// Workgroup = C waves over one 64-point tile of one set; wave c sweeps layer
-// chunk c: stage 1 (opacity, Sect. 2.3) from the slot registers, dtau
-// (trapezoid over the layer), Planck, and the recurrence for every angle.
-// Even chunks go bottom to top; odd chunks compose their layers' maps top
-// down, so neighbouring chunks read the rows of their shared boundary level
-// at about the same time.  Then the chunks' affine
-// maps are combined through LDS and Eq. 8 applied.
-// BIG: the table spans 4 GiB or more, so each species gets its own buffer
-// resource; otherwise one resource covers the table and the species offset
-// rides in the scalar offset operand.
-// NS: species slots compiled; a negative NS means exactly -NS species (no
-// per-species guards), otherwise tv.S <= NS species with uniform guards.
-// PARA: parabolic source (each step also needs the downwind level, so a
-// chunk below the top reads one level past its end).
 // Angle tiers compiled: up to 3 angles (registers for exactly 3), else up
 // to 8.  A request runs the kernel of its tier.
 constexpr int kMuTierSmall = 3;
@@ -751,7 +735,27 @@ constexpr int column_min_waves() {
                                                                                           : 1;
 }
 
-template <typename Real, typename TT, int NSS, int MAXMU, bool FROM_CHI, bool BIG, bool PARA>
+// Workgroup = C waves over one 64-point tile of one set; wave c sweeps layer
+// chunk c: stage 1 (opacity, Sect. 2.3) from the slot registers, dtau
+// (trapezoid over the layer), Planck, and the recurrence for every angle.
+// Even chunks go bottom to top; odd chunks compose their layers' maps top
+// down, so neighbouring chunks read the rows of their shared boundary level
+// at about the same time.  Then the chunks' affine maps are combined through
+// LDS and Eq. 8 applied.
+// BIG: the table spans 4 GiB or more, so each species gets its own buffer
+// resource; otherwise one resource covers the table and the species offset
+// rides in the scalar offset operand.
+// NS: species slots compiled; a negative NS means exactly -NS species (no
+// per-species guards), otherwise tv.S <= NS species with uniform guards.
+// PARA: parabolic source (each step also needs the downwind level, so a
+// chunk below the top reads one level past its end).
+// STREAM: the table rows are loaded non-temporal.  For launches of one set,
+// whose rows are read once: the row stream (376 MB at C2) then no longer
+// flushes the small working set of the neighbouring kernels (records, layout
+// weights, F+) from the caches.  Batches share rows across sets through the
+// caches and keep the default policy.
+template <typename Real, typename TT, int NSS, int MAXMU, bool FROM_CHI, bool BIG, bool PARA,
+          bool STREAM>
 __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(
     column_min_waves<Real, NSS, MAXMU, PARA>()))) void k_column(TableView tv, const ColSeg *__restrict__ segs,
                                                 int n_segs, ColSeg seg0, int64_t total_wgs,
@@ -867,8 +871,9 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(
 #pragma unroll
         for (int q = 0; q < NS; ++q) {
           if (q < S) {
-            const TT v = BIG ? buf_load<TT>(rs[BIG ? q : 0], off, 0)
-                             : buf_load<TT>(rs[0], off, (uint32_t)(q * sp_bytes));
+            constexpr int kPol = STREAM ? kCpolStream : 0;
+            const TT v = BIG ? buf_load<TT, kPol>(rs[BIG ? q : 0], off, 0)
+                             : buf_load<TT, kPol>(rs[0], off, (uint32_t)(q * sp_bytes));
             if constexpr (kF64)
               slot[q][k] = (Real)v;
             else
@@ -1152,52 +1157,59 @@ struct ColumnKernel {
   int real_bytes;
 };
 
-template <typename Real, typename TT, int NS, int MAXMU, bool FROM_CHI, bool PARA,
+template <typename Real, typename TT, int NS, int MAXMU, bool FROM_CHI, bool PARA, bool STREAM,
           bool BIG = false>
 static ColumnKernel ck() {
-  return ColumnKernel{&k_column<Real, TT, NS, MAXMU, FROM_CHI, BIG, PARA>, MAXMU,
+  return ColumnKernel{&k_column<Real, TT, NS, MAXMU, FROM_CHI, BIG, PARA, STREAM>, MAXMU,
                       (int)sizeof(Real)};
 }
 
 int column_mu_class(int n_mu) { return n_mu > kMuTierSmall ? 8 : kMuTierSmall; }
 
-template <typename Real, typename TT, bool FROM_CHI, bool PARA>
+template <typename Real, typename TT, bool FROM_CHI, bool PARA, bool STREAM>
 static ColumnKernel pick_ns(const TableView &tv, int max_mu) {
   const int S = tv.S;
   if constexpr (FROM_CHI) {
-    if (max_mu <= kMuTierSmall) return ck<Real, TT, 1, kMuTierSmall, true, PARA>();
-    return ck<Real, TT, 1, 8, true, PARA>();
+    if (max_mu <= kMuTierSmall) return ck<Real, TT, 1, kMuTierSmall, true, PARA, false>();
+    return ck<Real, TT, 1, 8, true, PARA, false>();
   } else {
     const int64_t table_bytes = (int64_t)tv.S * tv.nT * tv.nP * tv.pitch * (int64_t)sizeof(TT);
-    if (table_bytes >= 0xFFFFFFFFll) return ck<Real, TT, kMaxSpecies, 8, false, PARA, true>();
+    if (table_bytes >= 0xFFFFFFFFll)
+      return ck<Real, TT, kMaxSpecies, 8, false, PARA, false, true>();
     if (max_mu <= kMuTierSmall) {
-      if (S <= 1) return ck<Real, TT, -1, kMuTierSmall, false, PARA>();
-      if (S == 8) return ck<Real, TT, -8, kMuTierSmall, false, PARA>();
-      if (S <= 8) return ck<Real, TT, 8, kMuTierSmall, false, PARA>();
-      return ck<Real, TT, kMaxSpecies, kMuTierSmall, false, PARA>();
+      if (S <= 1) return ck<Real, TT, -1, kMuTierSmall, false, PARA, STREAM>();
+      if (S == 8) return ck<Real, TT, -8, kMuTierSmall, false, PARA, STREAM>();
+      if (S <= 8) return ck<Real, TT, 8, kMuTierSmall, false, PARA, STREAM>();
+      return ck<Real, TT, kMaxSpecies, kMuTierSmall, false, PARA, STREAM>();
     }
-    if (S <= 1) return ck<Real, TT, -1, 8, false, PARA>();
-    if (S <= 8) return ck<Real, TT, 8, 8, false, PARA>();
-    return ck<Real, TT, kMaxSpecies, 8, false, PARA>();
+    if (S <= 1) return ck<Real, TT, -1, 8, false, PARA, STREAM>();
+    if (S <= 8) return ck<Real, TT, 8, 8, false, PARA, STREAM>();
+    return ck<Real, TT, kMaxSpecies, 8, false, PARA, STREAM>();
   }
 }
 
-template <bool PARA>
+template <bool PARA, bool STREAM>
 static ColumnKernel pick_dtype(const TableView &tv, int max_mu, bool from_chi) {
   if (from_chi) {
-    if (tv.dtype == HR2_TABLE_F64) return pick_ns<double, double, true, PARA>(tv, max_mu);
-    return pick_ns<float, float, true, PARA>(tv, max_mu);
+    if (tv.dtype == HR2_TABLE_F64) return pick_ns<double, double, true, PARA, false>(tv, max_mu);
+    return pick_ns<float, float, true, PARA, false>(tv, max_mu);
   }
   switch (tv.dtype) {
-    case HR2_TABLE_F64: return pick_ns<double, double, false, PARA>(tv, max_mu);
-    case HR2_TABLE_F16: return pick_ns<float, _Float16, false, PARA>(tv, max_mu);
-    case HR2_TABLE_BF16: return pick_ns<float, uint16_t, false, PARA>(tv, max_mu);
-    default: return pick_ns<float, float, false, PARA>(tv, max_mu);
+    case HR2_TABLE_F64: return pick_ns<double, double, false, PARA, STREAM>(tv, max_mu);
+    case HR2_TABLE_F16: return pick_ns<float, _Float16, false, PARA, STREAM>(tv, max_mu);
+    case HR2_TABLE_BF16: return pick_ns<float, uint16_t, false, PARA, STREAM>(tv, max_mu);
+    default: return pick_ns<float, float, false, PARA, STREAM>(tv, max_mu);
   }
 }
 
-static ColumnKernel pick_column(const TableView &tv, int max_mu, bool from_chi, bool para) {
-  return para ? pick_dtype<true>(tv, max_mu, from_chi) : pick_dtype<false>(tv, max_mu, from_chi);
+// stream_rows: non-temporal row loads (from_chi reads no table rows)
+static ColumnKernel pick_column(const TableView &tv, int max_mu, bool from_chi, bool para,
+                                bool stream_rows) {
+  if (stream_rows && !from_chi)
+    return para ? pick_dtype<true, true>(tv, max_mu, false)
+                : pick_dtype<false, true>(tv, max_mu, false);
+  return para ? pick_dtype<true, false>(tv, max_mu, from_chi)
+              : pick_dtype<false, false>(tv, max_mu, from_chi);
 }
 
 static size_t column_shmem(const ColumnKernel &k, int chunks) {
@@ -1207,9 +1219,9 @@ static size_t column_shmem(const ColumnKernel &k, int chunks) {
 hipError_t launch_column(const TableView &tv, const ColSeg *segs_dev, int n_segs,
                          const ColSeg *seg0_host, int64_t total_wgs, int chunks, const void *recs,
                          const void *chi_in, void *out, int max_mu, bool opacity_from_memory,
-                         bool para, hipStream_t stream) {
+                         bool para, bool stream_rows, hipStream_t stream) {
   if (total_wgs <= 0) return hipSuccess;
-  const ColumnKernel k = pick_column(tv, max_mu, opacity_from_memory, para);
+  const ColumnKernel k = pick_column(tv, max_mu, opacity_from_memory, para, stream_rows);
   const ColSeg seg0 = seg0_host ? *seg0_host : ColSeg{};
   hipLaunchKernelGGL(k.fn, dim3((unsigned)total_wgs), dim3(64 * chunks),
                      column_shmem(k, chunks), stream, tv, segs_dev, seg0_host ? 0 : n_segs, seg0,
@@ -1219,7 +1231,8 @@ hipError_t launch_column(const TableView &tv, const ColSeg *segs_dev, int n_segs
 
 int column_wave_capacity(const TableView &tv, int max_mu, bool opacity_from_memory, int chunks,
                          bool para) {
-  const ColumnKernel k = pick_column(tv, max_mu, opacity_from_memory, para);
+  // the streaming variants differ only in the loads' cache policy
+  const ColumnKernel k = pick_column(tv, max_mu, opacity_from_memory, para, false);
   int blocks = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, (const void *)k.fn, 64 * chunks,
                                                    column_shmem(k, chunks)) != hipSuccess ||

@@ -305,7 +305,7 @@ bool hr2_server::launch_step(StepSlot &sl, std::vector<Req *> &reqs) {
   const ConvSeg *dvs = (const ConvSeg *)((unsigned char *)sl.desc.ptr + round256(bytes_c));
   for (const Group &gq : groups)
     if (launch_column(tv, dcs + gq.first, (int)gq.count, nullptr, gq.wgs, gq.chunks, base,
-                      nullptr, base, gq.max_mu, false, para, s) != hipSuccess)
+                      nullptr, base, gq.max_mu, false, para, false, s) != hipSuccess)
       return false;
   if (launch_convolve_bin(fp64, dvs, (int)vs.size(), nullptr, conv_wgs, base, base, s) != hipSuccess)
     return false;
