@@ -268,7 +268,12 @@ hr2_status hr2_convolve_bin(hr2_ctx *ctx, const hr2_obs *obs, const void *fplus_
  * columns, validated on the host, staged to the device).  bins_dev: device
  * hr2_real[n_sets][n_bins].  fplus_dev: NULL, or device
  * hr2_real[n_sets][nu_count] that receives the unscaled F+ of each set.
- * Each set's result does not depend on the other sets of the call. */
+ * Each set's result does not depend on the other sets of the call.  A call
+ * of one set whose table rows would overflow the 256 MB last-level cache
+ * (estimated at one new row per level and species) loads them non-temporal,
+ * which leaves the other kernels' small working set cached; the results are
+ * the same either way.  The same holds for the _dev, ln L and parameter-
+ * vector entry points below. */
 hr2_status hr2_forward_batch(hr2_ctx *ctx, const hr2_tables *tables, const hr2_obs *obs,
                              int n_sets, const hr2_column *cols, int n_mu,
                              void *bins_dev, void *fplus_dev, void *stream);
