@@ -139,8 +139,12 @@ typedef enum {
   HR2_OPT_NU_PER_LANE = 1, /* wavenumbers per lane: 0 = auto, 1 (only 1 is built) */
   HR2_OPT_TIMING = 2,      /* n > 0: bracket the kernels of every n-th forward-batch
                               call with HIP events (0 = off)                        */
-  HR2_OPT_SOURCE = 3       /* 1 = linear source (default), 2 = parabolic; servers
+  HR2_OPT_SOURCE = 3,      /* 1 = linear source (default), 2 = parabolic; servers
                               take the value their context has at creation          */
+  HR2_OPT_ROW_POLICY = 4   /* table-row loads of one-set calls: 0 = auto (non-temporal
+                              when the call's rows would overflow the last-level
+                              cache), 1 = always non-temporal, 2 = always cached.
+                              Batches always load cached.  Results do not change. */
 } hr2_option;
 hr2_status hr2_ctx_set_option(hr2_ctx *ctx, hr2_option opt, int value);
 

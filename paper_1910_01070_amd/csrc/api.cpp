@@ -241,6 +241,11 @@ extern "C" hr2_status hr2_ctx_set_option(hr2_ctx *ctx, hr2_option opt, int value
         return set_error(HR2_E_INVALID_ARG, "source order must be 1 (linear) or 2 (parabolic)");
       ctx->opt_source = value;
       return HR2_OK;
+    case HR2_OPT_ROW_POLICY:
+      if (value < 0 || value > 2)
+        return set_error(HR2_E_INVALID_ARG, "row policy must be 0 (auto), 1 or 2");
+      ctx->opt_row_policy = value;
+      return HR2_OK;
   }
   return set_error(HR2_E_INVALID_ARG, "unknown option");
 }
@@ -938,7 +943,9 @@ hr2_status run_forward(hr2_ctx *ctx, const hr2_tables *t, const hr2_obs *o, cons
   const double row_bytes_est = (double)t->view.S *
                                (double)std::min<int64_t>((int64_t)t->view.nT * t->view.nP, L) *
                                (double)w.nu_count * (double)t->view.tab_elem;
-  const bool stream_rows = B == 1 && row_bytes_est > kLastLevelCacheBytes;
+  const bool stream_rows =
+      B == 1 && (ctx->opt_row_policy == 1 ||
+                 (ctx->opt_row_policy == 0 && row_bytes_est > kLastLevelCacheBytes));
   HIP_TRY(launch_column(t->view, nullptr, 1, &seg, total_wgs, chunks, ctx->recs.ptr, nullptr,
                         fplus, n_mu, false, ctx->opt_source == 2, stream_rows, s));
   ConvSeg cs{};

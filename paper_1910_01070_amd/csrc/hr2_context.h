@@ -35,6 +35,7 @@ struct hr2_ctx {
   size_t pinned_cap = 0;
   int opt_chunks = 0;
   int opt_source = 1;              // 1 linear, 2 parabolic short characteristics
+  int opt_row_policy = 0;          // one-set calls: 0 auto, 1 non-temporal, 2 cached
   int timing_every = 0;            // time every n-th forward call (0 = off)
   int64_t timing_calls = 0;
   std::vector<hipEvent_t> tev;     // 4 events per timed call

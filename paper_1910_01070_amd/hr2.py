@@ -25,7 +25,7 @@ STATUS_NAMES = {0: "HR2_OK", 1: "HR2_NOT_READY", -1: "HR2_E_INVALID_ARG",
                 -5: "HR2_E_NOT_FOUND", -6: "HR2_E_UNSUPPORTED", -7: "HR2_E_CANCELLED"}
 DTYPES = {"f32": 0, "f16": 1, "bf16": 2, "f64": 3}
 REQ_PENDING, REQ_RUNNING, REQ_DONE, REQ_ERROR, REQ_CANCELLED = range(5)
-OPT_CHUNKS, OPT_NU_PER_LANE, OPT_TIMING, OPT_SOURCE = 0, 1, 2, 3
+OPT_CHUNKS, OPT_NU_PER_LANE, OPT_TIMING, OPT_SOURCE, OPT_ROW_POLICY = 0, 1, 2, 3, 4
 
 _DP = POINTER(c_double)
 

@@ -434,6 +434,32 @@ def test_degenerate_sizes(ctx, dtype, tol):
     T.close()
 
 
+def test_row_policy_leaves_results_unchanged(ctx):
+    """HR2_OPT_ROW_POLICY only changes how one-set calls load table rows:
+    non-temporal and cached loads give bit-identical spectra and bins."""
+    tab = tu.small_multi_table()
+    T = hr2.Tables(ctx, tab, "f32")
+    w = wl.Window(13, 1001, 2)
+    nu_first, dnu = oracle.window_grid(tab, w)
+    obs = hr2.Obs(ctx, T, w, 400.0, wl.snapped_edges(
+        tab, w, wl.log_edges(nu_first + 0.2 * (w.count - 1) * dnu,
+                             nu_first + 0.8 * (w.count - 1) * dnu, 9)))
+    col = tu.small_columns(tab, 1, seed=31)
+    out = {}
+    for policy in (1, 2, 0):
+        ctx.set_option(hr2.OPT_ROW_POLICY, policy)
+        out[policy] = run_forward(ctx, T, obs, col, 3, 2)
+    ctx.set_option(hr2.OPT_CHUNKS, 0)
+    for policy in (2, 0):
+        assert np.array_equal(out[1][0], out[policy][0])
+        assert np.array_equal(out[1][1], out[policy][1])
+    with pytest.raises(hr2.HR2Error) as ei:
+        ctx.set_option(hr2.OPT_ROW_POLICY, 3)
+    assert ei.value.status == hr2.E_INVALID_ARG
+    obs.close()
+    T.close()
+
+
 # ------------------------------------------------------------------- C2 / C4
 
 
