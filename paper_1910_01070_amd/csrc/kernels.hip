@@ -210,10 +210,11 @@ __device__ const double *theta_tail(const ParamView &pv, const double *th) {
   return th + 3 + pv.K * pv.q + 1 + pv.n_free;
 }
 
-// 256-thread workgroups, each staging its set: at C2 (101 levels, 12 items
-// per level) five per set; shorter barriers and more CUs per set than one
-// workgroup of 1024 (8.1 instead of 10.1 us per C2 spectrum)
-constexpr int kLevelThreads = 256;
+// 128-thread workgroups, each staging its set: at C2 (101 levels, 12 items
+// per level) ten per set; shorter barriers and more CUs per set than larger
+// workgroups (per C2 spectrum: 1024 threads 10.1 us, 256 threads 7.7 us,
+// 128 threads 7.0-7.3 us; 64 threads 8.3-8.4 us)
+constexpr int kLevelThreads = 128;
 
 template <typename Real>
 __global__ __launch_bounds__(kLevelThreads) void k_levels(TableView tv, ColumnsView cv,
