@@ -390,6 +390,51 @@ def test_p10_isothermal_constant_table_optical_depth():
         assert abs(dtau.sum() / hydro - 1) < 1e-3
 
 
+def _planck_inverse(nu, S):
+    """The temperature whose Planck intensity at wavenumber nu is S."""
+    return H * C * nu / (KB * np.log1p(2 * H * C * C * nu ** 3 / S))
+
+
+@pytest.mark.parametrize("n_mu", [1, 2, 3, 5])
+def test_layer_optical_depth_is_the_integral_of_a_linear_opacity(n_mu):
+    """Sect. 2.8 ("calculation of the optical depths"), reading: a layer's
+    optical depth is the integral of chi over its geometric thickness with chi
+    varying linearly between the two levels.  Pin: take chi exactly linear in
+    height, chi(z) = c0 + c1 z, so the optical depth above height z is the
+    closed form c0 (Z - z) + c1 (Z^2 - z^2) / 2 (Z: the top), and choose the
+    level temperatures by inverting Planck's law so that S = B_nu(T) is exactly
+    linear in that optical depth, S = a + b tau.  The linear-source scheme is
+    exact for such a source (Eq. 4-7), so the oracle's RT entry, which forms
+    every layer's optical depth from chi at the levels and the thicknesses
+    itself, must return the closed-form flux of Eq. 8 with Eq. 1:
+    F+ = 2 pi sum_k w_k mu_k (a + b mu_k (1 - exp(-tau_0 / mu_k))).
+    Chi is steep across every layer (it falls by a factor 1.5-6 over the
+    column), so a rectangle rule, a missing half or the wrong level would move
+    both the optical depths at the levels and the total."""
+    rng = np.random.default_rng(41 + n_mu)
+    t, wt = np.polynomial.legendre.leggauss(n_mu)
+    mu, w = 0.5 * (t + 1.0), 0.5 * wt
+    nu = 2300.0
+    for L in (2, 3, 6, 25, 80):
+        for _ in range(4):
+            dz = 10.0 ** rng.uniform(5.0, 7.0, L - 1)       # cm, bottom layer first
+            z = np.concatenate([[0.0], np.cumsum(dz)])      # level heights
+            Z = z[-1]
+            tau_tot = 10.0 ** rng.uniform(-0.5, 0.9)
+            grad = rng.uniform(0.5, 5.0)
+            kappa = tau_tot / (Z * (1.0 + grad / 2.0))
+            c0, c1 = kappa * (1.0 + grad), -kappa * grad / Z
+            chi = c0 + c1 * z
+            tau = c0 * (Z - z) + c1 * (Z * Z - z * z) / 2.0
+            assert abs(tau[0] / tau_tot - 1) < 1e-12 and tau[-1] == 0.0
+            S_top, S_bot = planck_ref(nu, rng.uniform(500.0, 900.0)), planck_ref(nu, 2200.0)
+            a, b = S_top, (S_bot - S_top) / tau[0]
+            T = _planck_inverse(nu, a + b * tau)
+            got = oracle.rt_emission(chi[:, None], dz, T, np.array([nu]), n_mu)[0]
+            want = 2 * np.pi * np.sum(w * mu * (a + b * mu * (1.0 - np.exp(-tau[0] / mu))))
+            assert abs(got / want - 1) < 1e-12, (L, n_mu, got, want)
+
+
 # ------------------------------------------------------- Eq. 17, binning
 
 
