@@ -174,11 +174,13 @@ hr2_status hr2_ctx_collect_timing(hr2_ctx *ctx, double ms[3], int64_t *n_calls);
  *                       float (double for F64) in every case.
  * Copies everything to the device; host arrays may be freed on return.  One
  * species block (n_T * n_p rows of n_nu rounded up to 64 entries, in the
- * storage type) and one CIA pair block must each stay below 4 GiB; the
- * whole table may be larger.
+ * storage type) must stay below 4 GiB, and so must the CIA blocks of both
+ * pairs together (n_cia * n_T rows); the whole table may be larger.  These
+ * sizes are checked before anything is read or allocated.
  * Errors: HR2_E_INVALID_ARG (NULL, NaN/Inf, non-monotone axis, counts out of
- * [1, HR2_MAX_SPECIES], n_cia not 0/2), HR2_E_OUT_OF_RANGE (a block of 4 GiB
- * or more), HR2_E_NO_MEMORY, HR2_E_DEVICE. */
+ * [1, HR2_MAX_SPECIES], n_cia not 0/2), HR2_E_OUT_OF_RANGE (a species block,
+ * or the CIA blocks together, of 4 GiB or more), HR2_E_NO_MEMORY,
+ * HR2_E_DEVICE. */
 typedef struct {
   int n_species, n_T, n_p;
   const double *T_K;
@@ -293,7 +295,12 @@ hr2_status hr2_forward_batch(hr2_ctx *ctx, const hr2_tables *tables, const hr2_o
  * An invalid set's bins and F+ are NaN; other sets are unaffected.
  * This call may be captured into a HIP graph once it has been made with the
  * same sizes outside capture (so no staging copy or scratch growth is
- * needed; otherwise it returns HR2_E_UNSUPPORTED under capture). */
+ * needed; otherwise it returns HR2_E_UNSUPPORTED under capture).  A captured
+ * graph writes the context's scratch (level records, F+ when fplus_dev is
+ * NULL): order its replays against other calls on the same context (same
+ * stream, or events), since neither waits for the other.  Once a call has
+ * been captured on a context, scratch that a later, larger call replaces is
+ * kept until hr2_ctx_destroy, so an older graph never writes freed memory. */
 hr2_status hr2_forward_batch_dev(hr2_ctx *ctx, const hr2_tables *tables, const hr2_obs *obs,
                                  int n_sets, int n_levels, const double *p_dev,
                                  const double *T_dev, const double *x_dev,
@@ -312,9 +319,11 @@ hr2_status hr2_forward_batch_dev(hr2_ctx *ctx, const hr2_tables *tables, const h
  *
  * hr2_obs_set_data attaches observed data to a layout: D[n_bins] (finite)
  * and sigma[n_bins] (finite, > 0), host FP64, copied (the caller keeps its
- * arrays).  It may be called again to replace the data; it waits for the
- * device first.  Errors: HR2_E_INVALID_ARG (NULL, non-finite, sigma <= 0),
- * HR2_E_NO_MEMORY. */
+ * arrays).  It may be called again to replace the data; it first waits for
+ * the calls already enqueued through the context that created the layout
+ * (not for the rest of the device, and not for replays of captured graphs,
+ * which the caller orders).  Errors: HR2_E_INVALID_ARG (NULL, non-finite,
+ * sigma <= 0), HR2_E_NO_MEMORY. */
 hr2_status hr2_obs_set_data(hr2_obs *obs, const double *D, const double *sigma);
 
 /* ln L of n_sets host columns (as hr2_forward_batch): lnl_dev is device

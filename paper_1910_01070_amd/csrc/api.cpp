@@ -45,25 +45,28 @@ namespace hr2 {
 
 hr2_status DevBuf::ensure(size_t bytes) {
   if (bytes <= cap) return HR2_OK;
-  if (ptr != nullptr) {
-    // the old buffer may still be read by enqueued work of this context
-    HIP_TRY(hipDeviceSynchronize());
-    HIP_TRY(hipFree(ptr));
-    ptr = nullptr;
-    cap = 0;
-  }
   size_t want = std::max<size_t>(bytes, 4096);
   want = (want + 255) & ~size_t(255);
-  if (hipMalloc(&ptr, want) != hipSuccess) {
-    ptr = nullptr;
+  void *fresh = nullptr;
+  if (hipMalloc(&fresh, want) != hipSuccess) {
     (void)hipGetLastError();
     return set_error(HR2_E_NO_MEMORY, "device allocation of " + std::to_string(want) + " bytes failed");
   }
+  // the old buffer may still be read by enqueued work or a captured graph:
+  // keep it until the owner frees it at a safe point
+  if (ptr != nullptr) retired.push_back(ptr);
+  ptr = fresh;
   cap = want;
   return HR2_OK;
 }
 
+void DevBuf::free_retired() {
+  for (void *p : retired) (void)hipFree(p);
+  retired.clear();
+}
+
 void DevBuf::release() {
+  free_retired();
   if (ptr) (void)hipFree(ptr);
   ptr = nullptr;
   cap = 0;
@@ -135,10 +138,32 @@ static bool capturing(hipStream_t stream) {
   return cs != hipStreamCaptureStatusNone;
 }
 
+// Scratch superseded by growth is freed once every earlier call of the
+// context has completed (calls are ordered through scratch_event, so the
+// last call's event covers all of them), never after a call was captured.
+static void free_retired_scratch(hr2_ctx *ctx) {
+  DevBuf *bufs[] = {&ctx->recs, &ctx->fplus, &ctx->cols, &ctx->terms, &ctx->unpacked};
+  bool any = false;
+  for (DevBuf *b : bufs) any |= !b->retired.empty();
+  if (!any || ctx->captured) return;
+  if (ctx->scratch_used) {
+    const hipError_t q = hipEventQuery(ctx->scratch_event);
+    if (q != hipSuccess) {
+      (void)hipGetLastError();   // not ready (or failed): try again on a later call
+      return;
+    }
+  }
+  for (DevBuf *b : bufs) b->free_retired();
+}
+
 hr2_status ctx_begin(hr2_ctx *ctx, hipStream_t stream) {
   HIP_TRY(hipSetDevice(ctx->device));
-  if (ctx->scratch_used && !capturing(stream))
-    HIP_TRY(hipStreamWaitEvent(stream, ctx->scratch_event, 0));
+  if (capturing(stream)) {
+    ctx->captured = true;
+    return HR2_OK;
+  }
+  free_retired_scratch(ctx);
+  if (ctx->scratch_used) HIP_TRY(hipStreamWaitEvent(stream, ctx->scratch_event, 0));
   return HR2_OK;
 }
 
@@ -370,9 +395,11 @@ extern "C" hr2_status hr2_tables_create(hr2_ctx *ctx, const hr2_tables_desc *d, 
   // inside one CIA pair block), in the storage type
   const double elem = d->dtype == HR2_TABLE_F64 ? 8.0 : (d->dtype == HR2_TABLE_F32 ? 4.0 : 2.0);
   const double cia_elem = d->dtype == HR2_TABLE_F64 ? 8.0 : 4.0;
-  if ((double)nT * nP * pitch * elem >= 4294967296.0 ||
-      (double)nT * pitch * cia_elem >= 4294967296.0)
+  if ((double)nT * nP * pitch * elem >= 4294967296.0)
     return set_error(HR2_E_OUT_OF_RANGE, "one species block of the table must stay below 4 GiB");
+  // the column kernel reads both CIA pairs through one buffer resource
+  if ((double)nc * nT * pitch * cia_elem >= 4294967296.0)
+    return set_error(HR2_E_OUT_OF_RANGE, "the CIA pair blocks together must stay below 4 GiB");
   HIP_TRY(hipSetDevice(ctx->device));
   auto *t = new hr2_tables();
   t->ctx = ctx;
@@ -743,16 +770,21 @@ extern "C" hr2_status hr2_obs_set_data(hr2_obs *o, const double *D, const double
     buf[j] = D[j];
     buf[nb + j] = sigma[j] * sigma[j];
   }
-  HIP_TRY(hipSetDevice(o->ctx->device));
+  hr2_ctx *ctx = o->ctx;
+  HIP_TRY(hipSetDevice(ctx->device));
   if (o->d_D == nullptr) {
     void *p = nullptr;
     HIP_TRY(hipMalloc(&p, buf.size() * sizeof(double)));
     o->d_D = (double *)p;
     o->d_s2 = o->d_D + nb;
   }
-  // the previous data may still be read by queued work on any stream
-  HIP_TRY(hipDeviceSynchronize());
-  HIP_TRY(hipMemcpy(o->d_D, buf.data(), buf.size() * sizeof(double), hipMemcpyHostToDevice));
+  // the previous data may still be read by the context's enqueued calls: wait
+  // for the last of them (they are ordered through scratch_event), not for
+  // the whole device, then copy on the context's own stream
+  if (ctx->scratch_used) HIP_TRY(hipEventSynchronize(ctx->scratch_event));
+  HIP_TRY(hipMemcpyAsync(o->d_D, buf.data(), buf.size() * sizeof(double), hipMemcpyHostToDevice,
+                         ctx->internal));
+  HIP_TRY(hipStreamSynchronize(ctx->internal));
   return HR2_OK;
 }
 

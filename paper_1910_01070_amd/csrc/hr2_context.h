@@ -11,11 +11,16 @@
 
 namespace hr2 {
 
-// Grow-only device buffer.
+// Grow-only device buffer.  Growing allocates the new buffer first and keeps
+// the superseded one in `retired` (enqueued work or a captured graph may
+// still read it); free_retired() frees those once the owner knows that
+// nothing can read them any more.  Nothing here synchronises the device.
 struct DevBuf {
   void *ptr = nullptr;
   size_t cap = 0;
+  std::vector<void *> retired;
   hr2_status ensure(size_t bytes);
+  void free_retired();
   void release();
 };
 
@@ -40,6 +45,9 @@ struct hr2_ctx {
   int64_t timing_calls = 0;
   std::vector<hipEvent_t> tev;     // 4 events per timed call
   size_t tev_used = 0;             // events recorded since the last collection
+  bool captured = false;           // a call on this context ran under stream capture: a
+                                   // graph may hold its scratch, so superseded scratch
+                                   // is kept until hr2_ctx_destroy
   hr2::DevBuf recs, fplus, cols, terms, unpacked;
 };
 

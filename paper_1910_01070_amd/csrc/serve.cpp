@@ -290,6 +290,9 @@ bool hr2_server::launch_step(StepSlot &sl, std::vector<Req *> &reqs) {
   }
   const size_t bytes_c = cs.size() * sizeof(ColSeg), bytes_v = vs.size() * sizeof(ConvSeg);
   const size_t total = round256(bytes_c) + bytes_v;
+  // this slot's previous step has completed, so nothing reads its old
+  // descriptor buffers any more
+  sl.desc.free_retired();
   if (sl.desc.ensure(total) != HR2_OK) return false;
   if (sl.pinned_cap < total) {
     if (sl.pinned) (void)hipHostFree(sl.pinned);

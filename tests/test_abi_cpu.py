@@ -75,6 +75,58 @@ def test_context_without_a_device_reports_device_error():
     assert h.value is None
 
 
+def _no_device():
+    try:
+        import torch
+        return not torch.cuda.is_available()
+    except ImportError:
+        return True
+
+
+def _desc(n_T, n_p, n_nu, dtype, n_cia, keep):
+    T_axis = np.linspace(100.0, 3000.0, n_T)
+    lp = np.linspace(-6.0, 3.0, n_p)
+    dummy = np.zeros(64)   # never read: the sizes are refused first
+    mass = np.array([18.0])
+    keep += [T_axis, lp, dummy, mass]
+    dp = lambda a: a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    d = hr2.TablesDesc()
+    d.n_species, d.n_T, d.n_p = 1, n_T, n_p
+    d.T_K, d.log10_p_bar = dp(T_axis), dp(lp)
+    d.nu0_cm, d.dnu_cm, d.n_nu = 100.0, 0.01, n_nu
+    d.log10_sigma, d.molar_mass = dp(dummy), dp(mass)
+    d.n_cia, d.log10_k_cia = n_cia, dp(dummy)
+    d.he_h2_ratio, d.dtype = 0.17, hr2.DTYPES[dtype]
+    return d
+
+
+@pytest.mark.skipif(not _no_device(), reason="the refusal is checked where no device exists")
+def test_table_blocks_past_4_gib_are_refused_before_any_device_work():
+    """Rows are addressed by 32-bit byte offsets: a species block, and the two
+    CIA pair blocks together (one buffer resource in the column kernel), must
+    stay below 4 GiB.  The sizes are refused before the context is used or an
+    array is read, so a stand-in context (zeroed memory) is enough here: if the
+    check were missing, the call would go on to the device and fail with
+    HR2_E_DEVICE instead."""
+    lib = hr2.load()
+    fake_ctx = ctypes.create_string_buffer(4096)
+    out = ctypes.c_void_p()
+    keep = []
+    # one CIA pair block is 2.15 GB, both together 4.295e9 B >= 4 GiB; the
+    # FP16 species block (256 x 2 rows) is 2.15 GB
+    n_nu = (1 << 21) + 64
+    d = _desc(256, 2, n_nu, "f16", 2, keep)
+    assert lib.hr2_tables_create(fake_ctx, ctypes.byref(d), ctypes.byref(out)) == hr2.E_OUT_OF_RANGE
+    assert "CIA" in hr2.last_error() and out.value is None
+    # the same table without CIA gets past the size checks (and then needs a device)
+    d = _desc(256, 2, n_nu, "f16", 0, keep)
+    assert lib.hr2_tables_create(fake_ctx, ctypes.byref(d), ctypes.byref(out)) == hr2.E_DEVICE
+    # an FP32 species block of 256 x 2 rows of that length is 4.295e9 B
+    d = _desc(256, 2, n_nu, "f32", 0, keep)
+    assert lib.hr2_tables_create(fake_ctx, ctypes.byref(d), ctypes.byref(out)) == hr2.E_OUT_OF_RANGE
+    assert "species block" in hr2.last_error()
+
+
 def test_binding_fails_loudly_without_the_library(monkeypatch, tmp_path):
     monkeypatch.setattr(hr2, "_lib", None)
     monkeypatch.setattr(hr2, "LIB_PATH", str(tmp_path / "missing.so"))
