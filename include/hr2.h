@@ -106,7 +106,8 @@ enum {
   HR2_MAX_LEVELS = 1024,
   HR2_MAX_MU = 8,
   HR2_MAX_ORDER = 8,          /* finite-element order q */
-  HR2_MAX_TNODES = 128        /* temperature nodes K_e q + 1 */
+  HR2_MAX_TNODES = 128,       /* temperature nodes K_e q + 1 */
+  HR2_NOALLOC_SCRATCH_BYTES = 32 << 20   /* fixed device array of hr2_forward_batch_dev_noalloc */
 };
 
 typedef struct hr2_ctx hr2_ctx;
@@ -307,6 +308,35 @@ hr2_status hr2_forward_batch_dev(hr2_ctx *ctx, const hr2_tables *tables, const h
                                  const double *log_g_dev, const double *scale_dev,
                                  const double *cloud_dev, int n_mu, void *bins_dev,
                                  void *fplus_dev, int *set_status_dev, void *stream);
+
+/* For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.  The same
+ * as hr2_forward_batch_dev (same arguments, kernels and results, bit for
+ * bit), except that its scratch lives in one fixed device array of
+ * HR2_NOALLOC_SCRATCH_BYTES (32 MiB) per GPU instead of the context's
+ * grow-only buffers: the level records (128 bytes per set and level, 256
+ * with F64 tables, rounded up to 256 bytes in all) and, when fplus_dev is
+ * NULL, the unscaled F+ (4 bytes per set and window point, 8 with F64
+ * tables).  Every GPU the library runs on holds its array from the first
+ * context made on it until the process ends.  The call allocates nothing
+ * (no hipMalloc, hipFree or allocating library routine, no timing events)
+ * and needs no staging copy, so it may be captured into a HIP graph at any
+ * time.  The kernels write every byte of the array they read, so nothing
+ * in it has to start at zero; it keeps the last call's contents.
+ * All calls on one GPU share its array: calls that overlap on one GPU
+ * (other streams, other contexts of the device) race on it, so the caller
+ * must order them (one stream, or events).  The other entry points do not
+ * use it.  Errors: as hr2_forward_batch_dev, plus HR2_E_OUT_OF_RANGE
+ * (before anything is enqueued) when the call's scratch exceeds the array
+ * (e.g. more than 55 sets of a 150,000-point window without an F+ buffer),
+ * and HR2_E_DEVICE when the array's address could not be looked up. */
+hr2_status hr2_forward_batch_dev_noalloc(hr2_ctx *ctx, const hr2_tables *tables,
+                                         const hr2_obs *obs, int n_sets, int n_levels,
+                                         const double *p_dev, const double *T_dev,
+                                         const double *x_dev, const double *log_g_dev,
+                                         const double *scale_dev, const double *cloud_dev,
+                                         int n_mu, void *bins_dev, void *fplus_dev,
+                                         int *set_status_dev, void *stream);
 
 /* ---- likelihood: the forward model fused with ln L (Sect. 3.1, Eq. 19;
  * error inflation of Sect. 3.3, Eq. 22-23) ----

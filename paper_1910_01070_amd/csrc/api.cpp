@@ -224,6 +224,12 @@ extern "C" hr2_status hr2_ctx_create(int hip_device, hr2_ctx **out) {
     hr2_ctx_destroy(ctx);
     return hip_error(e, "context setup");
   }
+  // the allocation-free entry point's fixed array: its address on this device
+  const hr2_status sst = noalloc_scratch_init(hip_device);
+  if (sst != HR2_OK) {
+    hr2_ctx_destroy(ctx);
+    return sst;
+  }
   *out = ctx;
   return HR2_OK;
 }
@@ -789,7 +795,7 @@ extern "C" hr2_status hr2_obs_set_data(hr2_obs *o, const double *D, const double
 }
 
 // ------------------------------------------------------------ stage calls
-namespace {
+namespace hr2 {
 
 size_t real_size(const hr2_tables *t) {
   return t->view.dtype == HR2_TABLE_F64 ? sizeof(double) : sizeof(float);
@@ -797,6 +803,10 @@ size_t real_size(const hr2_tables *t) {
 size_t rec_size(const hr2_tables *t) {
   return t->view.dtype == HR2_TABLE_F64 ? sizeof(LevelRecD) : sizeof(LevelRecF);
 }
+
+}  // namespace hr2
+
+namespace {
 
 // Stage one host column and build its level records (B = 1).
 hr2_status one_column_records(hr2_ctx *ctx, const hr2_tables *t, const hr2_column *col,
@@ -906,11 +916,6 @@ static hipEvent_t timing_event(hr2_ctx *ctx, int k) {
   return ctx->tev[at];
 }
 
-// Likelihood outputs of a forward call (NULL: bins only).
-struct LikeArgs {
-  const double *log10_eps;   // device [B] or NULL
-  double *lnl;               // device [B]
-};
 
 // MI355X Infinity Cache (the last-level cache in front of HBM)
 constexpr double kLastLevelCacheBytes = 256.0 * 1024 * 1024;
@@ -930,18 +935,29 @@ hr2_status run_forward(hr2_ctx *ctx, const hr2_tables *t, const hr2_obs *o, cons
   hr2_status st = ctx->recs.ensure(rec_bytes);
   if (st != HR2_OK) return st;
   if (like && (st = ctx->terms.ensure(term_bytes)) != HR2_OK) return st;
-  if (fplus == nullptr) {
-    if ((st = ctx->fplus.ensure(fp_bytes)) != HR2_OK) return st;
-    fplus = ctx->fplus.ptr;
-  }
-  const bool this_call = ctx->timing_every > 0 && !capturing(s) &&
+  if (fplus == nullptr && (st = ctx->fplus.ensure(fp_bytes)) != HR2_OK) return st;
+  FwdScratch scr;
+  scr.recs = ctx->recs.ptr;
+  scr.fplus = ctx->fplus.ptr;
+  scr.terms = (double *)ctx->terms.ptr;
+  return launch_forward(ctx, t, o, cv, n_mu, bins, fplus, status, s, scr, like, theta);
+}
+
+hr2_status launch_forward(hr2_ctx *ctx, const hr2_tables *t, const hr2_obs *o,
+                          const ColumnsView &cv, int n_mu, void *bins, void *fplus, int *status,
+                          hipStream_t s, const FwdScratch &scr, const LikeArgs *like,
+                          const ThetaArgs *theta) {
+  const hr2_window &w = o->window;
+  const int B = cv.B, L = cv.L;
+  if (fplus == nullptr) fplus = scr.fplus;
+  const bool this_call = scr.timing && ctx->timing_every > 0 && !capturing(s) &&
                          (ctx->timing_calls++ % ctx->timing_every) == 0;
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
   if (this_call)
     for (int k = 0; k < 4; ++k) ev[k] = timing_event(ctx, k);
   const bool timed = ev[0] && ev[1] && ev[2] && ev[3];
   if (timed) HIP_TRY(hipEventRecord(ev[0], s));
-  HIP_TRY(launch_levels(t->view, cv, ctx->recs.ptr, status, t->view.dtype == HR2_TABLE_F64, s,
+  HIP_TRY(launch_levels(t->view, cv, scr.recs, status, t->view.dtype == HR2_TABLE_F64, s,
                         theta));
   const int64_t base_waves = (int64_t)B * ((w.nu_count + 63) / 64);
   const int chunks = ctx->opt_chunks ? std::min(ctx->opt_chunks, std::max(1, L - 1))
@@ -978,7 +994,7 @@ hr2_status run_forward(hr2_ctx *ctx, const hr2_tables *t, const hr2_obs *o, cons
   const bool stream_rows =
       B == 1 && (ctx->opt_row_policy == 1 ||
                  (ctx->opt_row_policy == 0 && row_bytes_est > kLastLevelCacheBytes));
-  HIP_TRY(launch_column(t->view, nullptr, 1, &seg, total_wgs, chunks, ctx->recs.ptr, nullptr,
+  HIP_TRY(launch_column(t->view, nullptr, 1, &seg, total_wgs, chunks, scr.recs, nullptr,
                         fplus, n_mu, false, ctx->opt_source == 2, stream_rows, s));
   ConvSeg cs{};
   cs.item_begin = 0;
@@ -997,7 +1013,7 @@ hr2_status run_forward(hr2_ctx *ctx, const hr2_tables *t, const hr2_obs *o, cons
     cs.D = o->d_D;
     cs.s2 = o->d_s2;
     cs.log10_eps = like->log10_eps;
-    cs.terms = (double *)ctx->terms.ptr;
+    cs.terms = scr.terms;
   }
   if (timed) HIP_TRY(hipEventRecord(ev[2], s));
   cs.items_per_wg = conv_items_per_wg(o->nnz, o->n_bins);

@@ -66,6 +66,37 @@ ColumnsView columns_view(const void *dev, int n_sets, int L, int S);
 int auto_chunks(const TableView &tv, int64_t base_waves, int n_levels, int n_mu, bool from_chi,
                 bool para);
 
+// Likelihood outputs of a forward call (NULL: bins only).
+struct LikeArgs {
+  const double *log10_eps;   // device [B] or NULL
+  double *lnl;               // device [B]
+};
+
+// Device scratch of one forward call: level records, F+ (used when the
+// caller passes none) and the likelihood's per-bin terms.
+struct FwdScratch {
+  void *recs = nullptr;
+  void *fplus = nullptr;
+  double *terms = nullptr;
+  bool timing = true;   // the call may record timing events (event creation)
+};
+
+// Bytes of one level record for these tables, and of one spectrum element.
+size_t rec_size(const hr2_tables *t);
+size_t real_size(const hr2_tables *t);
+
+// The launch sequence of the forward model (levels -> column -> convolve/bin
+// [-> ln L]) on the given scratch; allocates nothing itself (timing events
+// are created only when scr.timing is set).
+hr2_status launch_forward(hr2_ctx *ctx, const hr2_tables *t, const hr2_obs *o,
+                          const ColumnsView &cv, int n_mu, void *bins, void *fplus, int *status,
+                          hipStream_t s, const FwdScratch &scr, const LikeArgs *like,
+                          const ThetaArgs *theta);
+
+// The fixed device array of the allocation-free entry point: looks up its
+// address on `device` (which must be current) once per device.
+hr2_status noalloc_scratch_init(int device);
+
 struct ObsPlan {
   int64_t N = 0, i0 = 0, n_pts = 0, nnz = 0;
   double first = 0, dnu = 0, R = 0;

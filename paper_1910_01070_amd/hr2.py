@@ -87,7 +87,7 @@ EXPORTS = [
     "hr2_serve_get_stats", "hr2_ctx_collect_timing", "hr2_serve_submit_packed",
     "hr2_serve_debug_hold", "hr2_obs_set_data", "hr2_loglike_batch", "hr2_loglike_batch_dev",
     "hr2_params_create", "hr2_params_destroy", "hr2_params_n_theta", "hr2_params_unpack_dev",
-    "hr2_forward_params_dev",
+    "hr2_forward_params_dev", "hr2_forward_batch_dev_noalloc",
 ]
 
 _lib = None
@@ -140,6 +140,8 @@ def load() -> ctypes.CDLL:
         "hr2_params_n_theta": ([vp], c_int),
         "hr2_params_unpack_dev": ([vp, vp, c_int, vp, vp, vp, vp, vp, vp, vp, vp, vp], c_int),
         "hr2_forward_params_dev": ([vp, vp, vp, vp, c_int, vp, c_int, vp, vp, vp, vp], c_int),
+        "hr2_forward_batch_dev_noalloc": ([vp, vp, vp, c_int, c_int, vp, vp, vp, vp, vp, vp,
+                                           c_int, vp, vp, vp, vp], c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(L, name)
@@ -351,6 +353,24 @@ def forward_batch_dev(ctx: Context, tables: Tables, obs: Obs, p, T, x, log_g, sc
     sp = None if status is None else _dev_ptr(status, torch.int32, B, "status")
     cp = None if cloud is None else _dev_ptr(cloud, f64, 3 * B, "cloud")
     _check(load().hr2_forward_batch_dev(
+        ctx.handle, tables.handle, obs.handle, B, L, _dev_ptr(p, f64, B * L, "p"),
+        _dev_ptr(T, f64, B * L, "T"), _dev_ptr(x, f64, B * tables.n_species, "x"),
+        _dev_ptr(log_g, f64, B, "log_g"), _dev_ptr(scale, f64, B, "scale"), cp, int(n_mu),
+        _dev_ptr(bins, real, B * obs.n_bins, "bins"), fp, sp, _stream(stream)))
+
+
+def forward_batch_dev_noalloc(ctx: Context, tables: Tables, obs: Obs, p, T, x, log_g, scale,
+                              n_mu: int, bins, fplus=None, status=None, stream=None, cloud=None):
+    """forward_batch_dev with the library's scratch in its fixed device array
+    (hr2_forward_batch_dev_noalloc): allocates no device memory."""
+    import torch
+    B, L = p.shape
+    f64 = torch.float64
+    real = tables.real
+    fp = None if fplus is None else _dev_ptr(fplus, real, B * int(obs.window.count), "fplus")
+    sp = None if status is None else _dev_ptr(status, torch.int32, B, "status")
+    cp = None if cloud is None else _dev_ptr(cloud, f64, 3 * B, "cloud")
+    _check(load().hr2_forward_batch_dev_noalloc(
         ctx.handle, tables.handle, obs.handle, B, L, _dev_ptr(p, f64, B * L, "p"),
         _dev_ptr(T, f64, B * L, "T"), _dev_ptr(x, f64, B * tables.n_species, "x"),
         _dev_ptr(log_g, f64, B, "log_g"), _dev_ptr(scale, f64, B, "scale"), cp, int(n_mu),

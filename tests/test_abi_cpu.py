@@ -55,6 +55,9 @@ def test_null_arguments_without_a_device():
                                  None) == hr2.E_INVALID_ARG
     assert lib.hr2_loglike_batch_dev(None, None, None, 1, 2, None, None, None, None, None, None,
                                      None, 3, None, None, None, None) == hr2.E_INVALID_ARG
+    assert lib.hr2_forward_batch_dev_noalloc(None, None, None, 1, 2, None, None, None, None,
+                                             None, None, 3, None, None, None,
+                                             None) == hr2.E_INVALID_ARG
     assert lib.hr2_params_create(None, None, None, None) == hr2.E_INVALID_ARG
     assert lib.hr2_params_n_theta(None) == 0
     lib.hr2_params_destroy(None)
