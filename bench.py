@@ -146,6 +146,14 @@ def main():
     ap.add_argument("--rates", default="", help="c5: comma-separated arrival rates to sweep")
     ap.add_argument("--strided-frac", type=float, default=0.5,
                     help="c5: share of requests on 1 cm^-1 windows (stride 10)")
+    ap.add_argument("--no-north-star", action="store_true",
+                    help="c2: skip the serving / plain FP32 / batch comparison legs")
+    ap.add_argument("--ns-rate", type=float, default=2000.0,
+                    help="c2 north-star leg: arrival rate of the short serving trace")
+    ap.add_argument("--ns-duration", type=float, default=2.0,
+                    help="c2 north-star leg: length of the short serving trace, s")
+    ap.add_argument("--ns-plain", type=int, default=200,
+                    help="c2 north-star leg: requests timed on the plain FP32 path")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
@@ -292,6 +300,9 @@ def main():
         res["binding_roof"] = {"hbm_us": hbm_us, "valu_issue_us": valu_us,
                                "bound": "valu" if valu_us >= hbm_us else "hbm",
                                "kernel_us": col_ms * 1e3, "frac": roof_us / (col_ms * 1e3)}
+    default_c2 = default_launch and args.chunks == 0
+    if default_c2 and not args.no_north_star:
+        res["north_star"] = north_star_legs(ctx, T, tab, args)
     if not args.no_cpu_baseline:
         log("timing the oracle on the host")
         res["cpu_baseline"] = cpu_baseline(tab, cols[0], spec, n_mu, args.cpu_budget_s)
@@ -343,6 +354,19 @@ def run_oracle_timing(args):
         res[f"c2_s_per_spectrum_{tag}"] = med(f2, 1 if n == 1 else 3)
         res[f"c3_s_per_batch_of_512_{tag}"] = med(f3, 1)
     oracle.set_threads(all_threads)
+    # C5: the first 20 requests of the 2000 req/s serving trace, every set
+    # (FP64 source table, all threads), as layer-nu points per second
+    trace = wl.c5_trace_packed(t2, rate_hz=2000.0, duration_s=10.0)[:20]
+    log(f"oracle on the C5 sample: {sum(r.n_sets for r in trace)} sets of 20 requests")
+    t0 = time.perf_counter()
+    for r in trace:
+        for i in range(r.n_sets):
+            c = wl.Column(r.p[i], r.T[i], r.x[i], r.log_g[i], r.scale[i])
+            oracle.forward(t2, c, r.obs.window, r.obs.resolving_power, r.obs.edges_cm, 3)
+    el = time.perf_counter() - t0
+    res["c5_sample_layer_nu_per_s_all_threads"] = sum(r.layer_nu for r in trace) / el
+    res["c5_sample"] = {"requests": 20, "sets": sum(r.n_sets for r in trace),
+                        "layer_nu": sum(r.layer_nu for r in trace), "seconds": el}
     print(json.dumps(res))
 
 
@@ -419,40 +443,35 @@ def run_c3(args):
 
 
 def run_c4(args):
-    """C2 columns in batches of 1, 64 and 512 with FP32, FP16 and BF16 tables,
-    and the per-spectrum error of the first sets against the library's FP64
-    tables (whose parity with the FP64 oracle is the test suite's job)."""
+    """C2 columns in batches of 1, 64 and 512 with FP32, FP16 and BF16 tables;
+    every spectrum of every batch against the FP64 oracle on the FP64 source
+    table (per-spectrum max relative error over the 400 bins)."""
     import torch
+    import oracle
     import workloads as wl
     from paper_1910_01070_amd import hr2
     tab = wl.c2_table(n_nu=args.n_nu)
     spec = wl.c2_obs(tab)
     ctx = hr2.Context(0)
+    batches = (1, 64, 512)
+    all_cols = wl.c4_columns(max(batches))   # every batch is a prefix of this list
+    log(f"FP64 oracle on the source table: {len(all_cols)} spectra")
+    t0 = time.perf_counter()
+    refs = []
+    for i, c in enumerate(all_cols):
+        refs.append(oracle.forward(tab, c, spec.window, spec.resolving_power, spec.edges_cm,
+                                   3)["bins"])
+        if (i + 1) % 64 == 0:
+            log(f"  {i + 1} spectra, {time.perf_counter() - t0:.0f} s")
+    refs = np.array(refs)
     rows = []
-    n_err = 4
-    err_cols = wl.c4_columns(n_err)
-    log("FP64-table reference of the error sample")
-    T64 = hr2.Tables(ctx, tab, "f64")
-    obs64 = hr2.Obs(ctx, T64, spec.window, spec.resolving_power, spec.edges_cm)
-    ref = torch.empty(n_err * obs64.n_bins, dtype=torch.float64, device="cuda")
-    hr2.forward_batch(ctx, T64, obs64, err_cols, 3, ref)
-    torch.cuda.synchronize()
-    refs = ref.cpu().numpy().reshape(n_err, obs64.n_bins)
-    obs64.close()
-    T64.close()
     errors = {}
     for dt in ("f32", "f16", "bf16"):
         T = hr2.Tables(ctx, tab, dt)
         obs = hr2.Obs(ctx, T, spec.window, spec.resolving_power, spec.edges_cm)
-        bins = torch.empty(n_err * obs.n_bins, dtype=torch.float32, device="cuda")
-        hr2.forward_batch(ctx, T, obs, err_cols, 3, bins)
-        torch.cuda.synchronize()
-        got = bins.cpu().numpy().reshape(n_err, obs.n_bins).astype(np.float64)
-        errors[dt] = [float(np.max(np.abs(got[i] - refs[i]) / np.abs(refs[i])))
-                      for i in range(n_err)]
-        log(dt, "per-spectrum max rel err over 400 bins:", errors[dt])
-        for B in (1, 64, 512):
-            cols = wl.c4_columns(B)
+        errors[dt] = {}
+        for B in batches:
+            cols = all_cols[:B]
             p, Tk, x, lg, sc = _dev_columns(cols)
             bins = torch.empty(B * obs.n_bins, dtype=torch.float32, device="cuda")
             steps = max(3, min(args.steps, 2000 // B))
@@ -464,15 +483,22 @@ def run_c4(args):
                 hr2.forward_batch_dev(ctx, T, obs, p, Tk, x, lg, sc, 3, bins)
             torch.cuda.synchronize()
             dt_s = (time.perf_counter() - t0) / steps
+            got = bins.cpu().numpy().reshape(B, obs.n_bins).astype(np.float64)
+            err = np.max(np.abs(got - refs[:B]) / np.abs(refs[:B]), axis=1)
+            errors[dt][str(B)] = [float(f"{e:.3e}") for e in err]
             layer_nu = (cols[0].n_levels - 1) * spec.window.count
             rows.append({"table": dt, "batch": B, "ms_per_launch": dt_s * 1e3,
-                         "spectra_per_s": B / dt_s, "layer_nu_per_s": B * layer_nu / dt_s})
+                         "spectra_per_s": B / dt_s, "layer_nu_per_s": B * layer_nu / dt_s,
+                         "max_rel_err_vs_fp64_oracle": float(err.max()),
+                         "median_rel_err_vs_fp64_oracle": float(np.median(err))})
             log(rows[-1])
             del p, Tk, x, lg, sc, bins
         obs.close()
         T.close()
     print(json.dumps({"workload": "C4 reduced precision (C2 columns, batches)", "rows": rows,
-                      "per_spectrum_max_rel_err_vs_fp64_tables": errors}))
+                      "per_spectrum_max_rel_err_vs_fp64_oracle": errors,
+                      "error_kind": "max over the 400 bins of |GPU - oracle| / |oracle|, the "
+                                    "oracle in FP64 on the FP64 source table"}))
 
 
 def run_params(args):
@@ -558,11 +584,67 @@ def _serve_trace(hr2, srv, trace):
     return np.array(lat), done_t, sub_t, fails[0], t_sub_end
 
 
+def serve_leg(ctx, T16, tab, rate, duration, strided_frac=0.5):
+    """One Poisson trace against a fresh server on resident reduced-precision
+    tables; returns (row of results, trace)."""
+    import workloads as wl
+    from paper_1910_01070_amd import hr2
+    trace = wl.c5_trace_packed(tab, rate_hz=rate, duration_s=duration, strided_frac=strided_frac)
+    srv = hr2.Server(ctx, T16, 16 << 30, 512)
+    r = trace[0]   # warm the kernels once
+    t = srv.submit_packed(r.obs.window, r.obs.resolving_power, r.obs.edges_cm, r.p, r.T,
+                          r.x, r.log_g, r.scale)
+    srv.poll(t, r.n_sets * r.obs.n_bins, wait_s=60.0)
+    lat, done_t, sub_t, fails, t_sub_end = _serve_trace(hr2, srv, trace)
+    stats = srv.stats()
+    srv.close()
+    span = max(done_t) - min(sub_t)
+    work = sum(rq.layer_nu for rq in trace)
+    strided = sum(rq.layer_nu for rq in trace if rq.obs.window.stride > 1)
+    row = {
+        "rate_req_per_s": rate, "duration_s": duration, "requests": len(trace),
+        "failed": fails, "offered_layer_nu_per_s": work / duration,
+        "served_layer_nu_per_s": work / span,
+        "served_requests_per_s": len(lat) / span,
+        "latency_s": {"p50": float(np.percentile(lat, 50)),
+                      "p99": float(np.percentile(lat, 99)), "kind": "arrival to done"},
+        "drain_s_after_last_arrival": max(done_t) - min(sub_t) - t_sub_end,
+        "steps": stats.steps, "max_admitted": stats.max_inflight,
+        "peak_bytes": stats.peak_bytes, "strided_work_frac": strided / work}
+    return row, trace
+
+
+def plain_leg(ctx, T32, sample):
+    """The plain FP32 path on the same requests: one request at a time, its
+    layout built and its sets run in one synchronous hr2_forward_batch call."""
+    import torch
+    import workloads as wl
+    from paper_1910_01070_amd import hr2
+    lat = []
+    t0 = time.perf_counter()
+    for rq in sample:
+        t1 = time.perf_counter()
+        obs = hr2.Obs(ctx, T32, rq.obs.window, rq.obs.resolving_power, rq.obs.edges_cm)
+        cols = [wl.Column(rq.p[i], rq.T[i], rq.x[i], rq.log_g[i], rq.scale[i])
+                for i in range(rq.n_sets)]
+        bins = torch.empty(rq.n_sets * obs.n_bins, dtype=torch.float32, device="cuda")
+        hr2.forward_batch(ctx, T32, obs, cols, 3, bins)
+        torch.cuda.synchronize()
+        obs.close()
+        lat.append(time.perf_counter() - t1)
+    t_plain = time.perf_counter() - t0
+    return {"requests": len(sample),
+            "layer_nu_per_s": sum(rq.layer_nu for rq in sample) / t_plain,
+            "requests_per_s": len(sample) / t_plain,
+            "service_time_s": {"p50": float(np.percentile(lat, 50)),
+                               "p99": float(np.percentile(lat, 99)),
+                               "kind": "one request alone, layout build to bins on the host"}}
+
+
 def run_c5(args):
     """Poisson arrivals of uneven requests against the FP16-table server;
     then the plain FP32 one-request-at-a-time path on a sample of them.
     With --rates, a sweep of arrival rates (one fresh server each) instead."""
-    import torch
     import workloads as wl
     from paper_1910_01070_amd import hr2
     tab = wl.c2_table(n_nu=args.n_nu)
@@ -572,29 +654,8 @@ def run_c5(args):
     rows = []
     for rate in rates:
         log(f"trace at {rate:g} req/s for {args.duration:g} s")
-        trace = wl.c5_trace_packed(tab, rate_hz=rate, duration_s=args.duration,
-                                   strided_frac=args.strided_frac)
-        srv = hr2.Server(ctx, T16, 16 << 30, 512)
-        r = trace[0]   # warm the kernels once
-        t = srv.submit_packed(r.obs.window, r.obs.resolving_power, r.obs.edges_cm, r.p, r.T,
-                              r.x, r.log_g, r.scale)
-        srv.poll(t, r.n_sets * r.obs.n_bins, wait_s=60.0)
-        lat, done_t, sub_t, fails, t_sub_end = _serve_trace(hr2, srv, trace)
-        stats = srv.stats()
-        srv.close()
-        span = max(done_t) - min(sub_t)
-        work = sum(rq.layer_nu for rq in trace)
-        strided = sum(rq.layer_nu for rq in trace if rq.obs.window.stride > 1)
-        rows.append({
-            "rate_req_per_s": rate, "requests": len(trace), "failed": fails,
-            "offered_layer_nu_per_s": work / args.duration,
-            "served_layer_nu_per_s": work / span,
-            "served_requests_per_s": len(lat) / span,
-            "latency_s": {"p50": float(np.percentile(lat, 50)),
-                          "p99": float(np.percentile(lat, 99))},
-            "drain_s_after_last_arrival": max(done_t) - min(sub_t) - t_sub_end,
-            "steps": stats.steps, "max_admitted": stats.max_inflight,
-            "peak_bytes": stats.peak_bytes, "strided_work_frac": strided / work})
+        row, trace = serve_leg(ctx, T16, tab, rate, args.duration, args.strided_frac)
+        rows.append(row)
         log(rows[-1])
     desc = ("C5 serving trace: Poisson arrivals, 50-200 layers, 20k-150k point windows at 0.1 or "
             "1 cm^-1, R 100-1000, 1-64 sets per request, FP16 tables resident")
@@ -602,25 +663,72 @@ def run_c5(args):
         print(json.dumps({"workload": desc + f", {args.duration:g} s per rate",
                           "rate_sweep": rows}))
         return
-    # the plain FP32 path: one request at a time, synchronous, same requests
     T32 = hr2.Tables(ctx, tab, "f32")
-    sample = trace[: min(len(trace), 200)]
-    t0 = time.perf_counter()
-    for rq in sample:
-        obs = hr2.Obs(ctx, T32, rq.obs.window, rq.obs.resolving_power, rq.obs.edges_cm)
-        cols = [wl.Column(rq.p[i], rq.T[i], rq.x[i], rq.log_g[i], rq.scale[i])
-                for i in range(rq.n_sets)]
-        bins = torch.empty(rq.n_sets * obs.n_bins, dtype=torch.float32, device="cuda")
-        hr2.forward_batch(ctx, T32, obs, cols, 3, bins)
-        torch.cuda.synchronize()
-        obs.close()
-    t_plain = time.perf_counter() - t0
-    plain_rate = sum(rq.layer_nu for rq in sample) / t_plain
+    plain = plain_leg(ctx, T32, trace[: min(len(trace), 200)])
     res = dict(rows[0])
     res["workload"] = desc + f", {args.rate:g} req/s for {args.duration:g} s"
-    res["plain_fp32_one_at_a_time_layer_nu_per_s"] = plain_rate
-    res["speedup_vs_plain_fp32"] = res["served_layer_nu_per_s"] / plain_rate
+    res["plain_fp32_one_at_a_time_layer_nu_per_s"] = plain["layer_nu_per_s"]
+    res["plain_fp32_one_at_a_time"] = plain
+    res["speedup_vs_plain_fp32"] = res["served_layer_nu_per_s"] / plain["layer_nu_per_s"]
     print(json.dumps(res))
+
+
+def batch_leg(ctx, tables_by_dtype, tab, B, steps):
+    """C4 batches: B C2 columns per launch on each table type; spectra/s."""
+    import torch
+    import workloads as wl
+    from paper_1910_01070_amd import hr2
+    spec = wl.c2_obs(tab)
+    cols = wl.c4_columns(B)
+    p, Tk, x, lg, sc = _dev_columns(cols)
+    layer_nu = (cols[0].n_levels - 1) * spec.window.count
+    out = {}
+    for dt, T in tables_by_dtype.items():
+        obs = hr2.Obs(ctx, T, spec.window, spec.resolving_power, spec.edges_cm)
+        bins = torch.empty(B * obs.n_bins, dtype=torch.float32, device="cuda")
+        for _ in range(2):
+            hr2.forward_batch_dev(ctx, T, obs, p, Tk, x, lg, sc, 3, bins)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            hr2.forward_batch_dev(ctx, T, obs, p, Tk, x, lg, sc, 3, bins)
+        torch.cuda.synchronize()
+        dt_s = (time.perf_counter() - t0) / steps
+        out[dt] = {"ms_per_launch": dt_s * 1e3, "spectra_per_s": B / dt_s,
+                   "layer_nu_per_s": B * layer_nu / dt_s}
+        obs.close()
+    return out
+
+
+def north_star_legs(ctx, T32, tab, args):
+    """What the target compares, on the same box as the headline: the
+    batched reduced-precision serving path (a short C5 trace on FP16 tables)
+    against the plain FP32 path one request at a time on the same requests,
+    and 64-set batches with FP32 vs FP16 tables."""
+    from paper_1910_01070_amd import hr2
+    T16 = hr2.Tables(ctx, tab, "f16")
+    log(f"north star: C5 trace at {args.ns_rate:g} req/s for {args.ns_duration:g} s, FP16 tables")
+    serving, trace = serve_leg(ctx, T16, tab, args.ns_rate, args.ns_duration)
+    log(serving)
+    sample = trace[: min(len(trace), args.ns_plain)]
+    log(f"north star: plain FP32 path on {len(sample)} of the same requests")
+    plain = plain_leg(ctx, T32, sample)
+    log(plain)
+    log("north star: 64-set batches, FP32 vs FP16 tables")
+    batches = batch_leg(ctx, {"f32": T32, "f16": T16}, tab, 64, 10)
+    log(batches)
+    T16.close()
+    return {
+        "serving_fp16_continuous_batching": serving,
+        "plain_fp32_one_request_at_a_time": plain,
+        "serving_speedup_vs_plain_fp32": serving["served_layer_nu_per_s"] / plain["layer_nu_per_s"],
+        "batch64": batches,
+        "batch64_fp16_vs_fp32": batches["f16"]["spectra_per_s"] / batches["f32"]["spectra_per_s"],
+        "workload": ("C5: Poisson arrivals of uneven requests (50-200 layers, 20k-150k point "
+                     "windows at 0.1 or 1 cm^-1, R 100-1000, 1-64 sets), FP16 tables resident, "
+                     "16 GB budget; plain path: the same requests' first ones, FP32 tables, "
+                     "one synchronous hr2_forward_batch each; batch64: 64 C2 columns per launch"),
+    }
 
 
 if __name__ == "__main__":

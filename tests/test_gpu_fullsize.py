@@ -1,0 +1,155 @@
+"""Full-size parity: every wavenumber point and every bin of the C2 spectrum
+in the exact launch bench.py times, the reduced-precision (C4) tables on
+every point and bin, and a 64-set C4 batch, every set and every bin, against
+the FP64 oracle.  Each spectrum's error is printed.
+
+Tolerances (per spectrum, max relative error, 1e-30 * max floor): FP32
+tables 1e-5 on F+ and bins; FP16/BF16 tables 1e-5 against the oracle run on
+the dequantised table (the arithmetic) and 1e-3 on bins against the oracle
+on the FP64 source (the quantisation)."""
+import functools
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as wl
+from tests import hr2_testutil as tu
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from paper_1910_01070_amd import hr2  # noqa: E402
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    c = hr2.Context(0)
+    yield c
+    torch.cuda.synchronize()
+    c.close()
+
+
+@pytest.fixture(scope="module")
+def c2():
+    say("generating the C2 table (8 x 27 x 19 x 150000)")
+    return tu.c2_table()
+
+
+@functools.lru_cache(maxsize=None)
+def _dequantised(dtype):
+    return tu.dequantised(tu.c2_table(), dtype)
+
+
+@functools.lru_cache(maxsize=None)
+def _oracle_c4_batch(table_kind, n_sets):
+    """Oracle spectra (F+, bins) of the first n_sets C4 columns on the FP64
+    source (table_kind 'source') or on a dequantised table ('f16', 'bf16')."""
+    tab = tu.c2_table() if table_kind == "source" else _dequantised(table_kind)
+    spec = wl.c2_obs(tu.c2_table())
+    out = []
+    for c in wl.c4_columns(n_sets):
+        r = oracle.forward(tab, c, spec.window, spec.resolving_power, spec.edges_cm, 3)
+        out.append((r["fplus"], r["bins"]))
+    return out
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+
+
+def _bench_launch(ctx, T, obs, cols):
+    """The bench's step: hr2_forward_batch_dev with the columns in HBM, the
+    caller's F+ buffer, default chunking and row policy."""
+    B = len(cols)
+    p, Tk, x = (_dev(np.stack([getattr(c, k) for c in cols])) for k in ("p_bar", "T_K", "x"))
+    lg, sc = _dev([c.log_g for c in cols]), _dev([c.scale for c in cols])
+    bins = torch.empty(B * obs.n_bins, dtype=torch.float32, device="cuda")
+    fplus = torch.empty(B * obs.window.count, dtype=torch.float32, device="cuda")
+    status = torch.full((B,), 7, dtype=torch.int32, device="cuda")
+    ctx.set_option(hr2.OPT_CHUNKS, 0)
+    ctx.set_option(hr2.OPT_ROW_POLICY, 0)
+    hr2.forward_batch_dev(ctx, T, obs, p, Tk, x, lg, sc, 3, bins, fplus, status)
+    torch.cuda.synchronize()
+    assert int(status.abs().sum()) == 0
+    return (bins.cpu().numpy().reshape(B, obs.n_bins).astype(np.float64),
+            fplus.cpu().numpy().reshape(B, obs.window.count).astype(np.float64))
+
+
+def test_c2_fp32_every_point_and_bin(ctx, c2):
+    """C2, FP32 tables, the bench's launch: all 150,000 F+ points and all 400
+    bins against the whole-spectrum oracle."""
+    spec = wl.c2_obs(c2)
+    col = wl.c2_column()
+    T = hr2.Tables(ctx, c2, "f32")
+    obs = hr2.Obs(ctx, T, spec.window, spec.resolving_power, spec.edges_cm)
+    say("C2 f32: one set through hr2_forward_batch_dev")
+    bins, fplus = _bench_launch(ctx, T, obs, [col])
+    ref = oracle.forward(c2, col, spec.window, spec.resolving_power, spec.edges_cm, 3)
+    e_f, nf = tu.max_rel_err(fplus[0], ref["fplus"])
+    e_b, nb = tu.max_rel_err(bins[0], ref["bins"])
+    say(f"  C2 f32: F+ {e_f:.2e} over {fplus.shape[1]} points (floored {nf}), "
+        f"bins {e_b:.2e} over {bins.shape[1]} bins (floored {nb})")
+    assert e_f <= 1e-5 and e_b <= 1e-5
+    obs.close()
+    T.close()
+
+
+@pytest.mark.parametrize("dtype", ["f16", "bf16"])
+def test_c4_one_set_every_point_and_bin(ctx, c2, dtype):
+    """C4 tables on the C2 spectrum: every point and bin against the oracle on
+    the dequantised table (1e-5) and every bin against the FP64 source (1e-3);
+    the F+ error against the source is printed."""
+    spec = wl.c2_obs(c2)
+    col = wl.c2_column()
+    T = hr2.Tables(ctx, c2, dtype)
+    obs = hr2.Obs(ctx, T, spec.window, spec.resolving_power, spec.edges_cm)
+    bins, fplus = _bench_launch(ctx, T, obs, [col])
+    deq = oracle.forward(_dequantised(dtype), col, spec.window, spec.resolving_power,
+                         spec.edges_cm, 3)
+    src = oracle.forward(c2, col, spec.window, spec.resolving_power, spec.edges_cm, 3)
+    e_fd, _ = tu.max_rel_err(fplus[0], deq["fplus"])
+    e_bd, _ = tu.max_rel_err(bins[0], deq["bins"])
+    e_fs, _ = tu.max_rel_err(fplus[0], src["fplus"])
+    e_bs, _ = tu.max_rel_err(bins[0], src["bins"])
+    say(f"  C2 {dtype}: vs dequantised F+ {e_fd:.2e} bins {e_bd:.2e}; "
+        f"vs FP64 source F+ {e_fs:.2e} bins {e_bs:.2e}")
+    assert e_fd <= 1e-5 and e_bd <= 1e-5
+    assert e_bs <= 1e-3
+    obs.close()
+    T.close()
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f16", "bf16"])
+def test_c4_batch_of_64_every_set_and_bin(ctx, c2, dtype):
+    """A 64-set C4 batch in one launch: every set's 400 bins and 150,000 F+
+    points against the oracle (FP32: the source, 1e-5; FP16/BF16: the
+    dequantised table, 1e-5, and bins against the source, 1e-3)."""
+    B = 64
+    spec = wl.c2_obs(c2)
+    cols = wl.c4_columns(B)
+    T = hr2.Tables(ctx, c2, dtype)
+    obs = hr2.Obs(ctx, T, spec.window, spec.resolving_power, spec.edges_cm)
+    say(f"C4 {dtype}: batch of {B}")
+    bins, fplus = _bench_launch(ctx, T, obs, cols)
+    src = _oracle_c4_batch("source", B)
+    deq = src if dtype == "f32" else _oracle_c4_batch(dtype, B)
+    worst = [0.0, 0.0, 0.0]
+    for s in range(B):
+        e_f, _ = tu.max_rel_err(fplus[s], deq[s][0])
+        e_b, _ = tu.max_rel_err(bins[s], deq[s][1])
+        e_bs, _ = tu.max_rel_err(bins[s], src[s][1])
+        say(f"  set {s:2d}: F+ {e_f:.2e} bins {e_b:.2e}" +
+            ("" if dtype == "f32" else f" (vs dequantised), bins vs FP64 source {e_bs:.2e}"))
+        worst = [max(worst[0], e_f), max(worst[1], e_b), max(worst[2], e_bs)]
+    say(f"  C4 {dtype} batch of {B}: worst F+ {worst[0]:.2e}, bins {worst[1]:.2e}, "
+        f"bins vs source {worst[2]:.2e}")
+    assert worst[0] <= 1e-5 and worst[1] <= 1e-5
+    assert worst[2] <= (1e-5 if dtype == "f32" else 1e-3)
+    obs.close()
+    T.close()

@@ -176,3 +176,87 @@ def test_shutdown_with_work_in_flight(env):
         srv.submit(r.obs.window, r.obs.resolving_power, r.obs.edges_cm, r.cols, r.n_mu)
     srv.close()   # cancels what is pending, waits for what is launched
     torch.cuda.synchronize()
+
+
+# C5: the first 20 requests of the seeded 2000 req/s serving trace (FP16
+# tables, every set of every request), served as one burst, against the
+# FP64 oracle on every bin.
+
+C5_SAMPLE = 20
+_c5_cache = {}
+
+
+def _c5_served():
+    """Serve the sample once per process: (requests, bins per request,
+    solo results of the first three requests)."""
+    if "served" in _c5_cache:
+        return _c5_cache["served"]
+    tab = tu.c2_table()
+    trace = wl.c5_trace_packed(tab, rate_hz=2000.0, duration_s=10.0)[:C5_SAMPLE]
+    ctx = hr2.Context(0)
+    T16 = hr2.Tables(ctx, tab, "f16")
+    srv = hr2.Server(ctx, T16, 16 << 30, 512)
+    say(f"C5 sample: {len(trace)} requests, {sum(r.n_sets for r in trace)} sets, "
+        f"{sum(r.layer_nu for r in trace):.3e} layer-nu points")
+    srv.hold(True)
+    tickets = [srv.submit_packed(r.obs.window, r.obs.resolving_power, r.obs.edges_cm, r.p, r.T,
+                                 r.x, r.log_g, r.scale) for r in trace]
+    srv.hold(False)
+    outs = []
+    for r, t in zip(trace, tickets):
+        st, out, info = srv.poll(t, r.n_sets * r.obs.n_bins, wait_s=120.0)
+        assert st == hr2.OK and info.state == hr2.REQ_DONE, (st, hr2.last_error())
+        outs.append(out.reshape(r.n_sets, r.obs.n_bins).astype(np.float64))
+    solo = []
+    for r in trace[:3]:
+        t = srv.submit_packed(r.obs.window, r.obs.resolving_power, r.obs.edges_cm, r.p, r.T, r.x,
+                              r.log_g, r.scale)
+        st, out, _ = srv.poll(t, r.n_sets * r.obs.n_bins, wait_s=120.0)
+        assert st == hr2.OK
+        solo.append(out.reshape(r.n_sets, r.obs.n_bins).astype(np.float64))
+    stats = srv.stats()
+    say(f"  steps {stats.steps}, most requests in one step {stats.max_step_requests}")
+    srv.close()
+    T16.close()
+    ctx.close()
+    _c5_cache["served"] = (trace, outs, solo)
+    return _c5_cache["served"]
+
+
+def _c5_against(table, label, tol):
+    import time
+    trace, outs, solo = _c5_served()
+    for a, b in zip(solo, outs):
+        assert np.array_equal(a, b), "a request's bins differ alone and in the mix"
+    worst, work = 0.0, 0
+    t0 = time.perf_counter()
+    for q, (r, got) in enumerate(zip(trace, outs)):
+        errs = []
+        for s in range(r.n_sets):
+            col = wl.Column(r.p[s], r.T[s], r.x[s], r.log_g[s], r.scale[s])
+            ref = oracle.forward(table, col, r.obs.window, r.obs.resolving_power, r.obs.edges_cm,
+                                 r.n_mu)["bins"]
+            errs.append(tu.max_rel_err(got[s], ref)[0])
+        work += r.layer_nu
+        worst = max(worst, max(errs))
+        say(f"  request {q:2d} ({r.n_sets} sets, {r.p.shape[1] - 1} layers, "
+            f"{r.obs.window.count} points, stride {r.obs.window.stride}, {r.obs.n_bins} bins): "
+            f"per-set max rel err vs {label}: " + " ".join(f"{e:.1e}" for e in errs))
+    dt = time.perf_counter() - t0
+    say(f"  C5 sample vs {label}: worst {worst:.2e}; oracle {work / dt:.3e} layer-nu/s "
+        f"({oracle.max_threads()} threads)")
+    assert worst <= tol
+
+
+@pytest.mark.timeout(900)
+def test_c5_sample_vs_oracle_on_dequantised_table():
+    """Every set and bin of 20 served FP16 requests against the oracle on the
+    dequantised table: the arithmetic, to 1e-5."""
+    _c5_against(tu.dequantised(tu.c2_table(), "f16"), "dequantised FP16 table", 1e-5)
+
+
+@pytest.mark.timeout(900)
+def test_c5_sample_vs_oracle_on_fp64_source():
+    """The same 20 requests against the oracle on the FP64 source table: the
+    quantisation, to 1e-3."""
+    _c5_against(tu.c2_table(), "FP64 source table", 1e-3)
