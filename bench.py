@@ -466,10 +466,12 @@ def run_c4(args):
     refs = np.array(refs)
     rows = []
     errors = {}
-    for dt in ("f32", "f16", "bf16"):
-        T = hr2.Tables(ctx, tab, dt)
+    for label, dt, offset in (("f32", "f32", "row"), ("f16", "f16", "row"),
+                              ("bf16", "bf16", "row"), ("f16/species-offset", "f16", "species"),
+                              ("bf16/species-offset", "bf16", "species")):
+        T = hr2.Tables(ctx, tab, dt, offset)
         obs = hr2.Obs(ctx, T, spec.window, spec.resolving_power, spec.edges_cm)
-        errors[dt] = {}
+        errors[label] = {}
         for B in batches:
             cols = all_cols[:B]
             p, Tk, x, lg, sc = _dev_columns(cols)
@@ -485,9 +487,9 @@ def run_c4(args):
             dt_s = (time.perf_counter() - t0) / steps
             got = bins.cpu().numpy().reshape(B, obs.n_bins).astype(np.float64)
             err = np.max(np.abs(got - refs[:B]) / np.abs(refs[:B]), axis=1)
-            errors[dt][str(B)] = [float(f"{e:.3e}") for e in err]
+            errors[label][str(B)] = [float(f"{e:.3e}") for e in err]
             layer_nu = (cols[0].n_levels - 1) * spec.window.count
-            rows.append({"table": dt, "batch": B, "ms_per_launch": dt_s * 1e3,
+            rows.append({"table": label, "batch": B, "ms_per_launch": dt_s * 1e3,
                          "spectra_per_s": B / dt_s, "layer_nu_per_s": B * layer_nu / dt_s,
                          "max_rel_err_vs_fp64_oracle": float(err.max()),
                          "median_rel_err_vs_fp64_oracle": float(np.median(err))})

@@ -94,6 +94,11 @@ typedef enum {
 } hr2_status;
 
 typedef enum {
+  HR2_OFFSET_ROW = 0,      /* one log2 offset per table row (default) */
+  HR2_OFFSET_SPECIES = 1   /* one log2 offset per species */
+} hr2_offset_mode;
+
+typedef enum {
   HR2_TABLE_F32 = 0,   /* log2-sigma rows minus a per-row offset, float    */
   HR2_TABLE_F16 = 1,   /* same, IEEE binary16 (one RNE rounding from FP64) */
   HR2_TABLE_BF16 = 2,  /* same, bfloat16 (RNE to float, then RNE to bf16)  */
@@ -173,13 +178,19 @@ hr2_status hr2_ctx_collect_timing(hr2_ctx *ctx, double ms[3], int64_t *n_calls);
  *                       log10_sigma * log2(10) values (FP64); F64 keeps
  *                       log10_sigma * log2(10) with no offset.  CIA rows are
  *                       float (double for F64) in every case.
+ *   offset_mode         HR2_OFFSET_ROW (0, the default above) or
+ *                       HR2_OFFSET_SPECIES (1): every row of a species uses
+ *                       the midpoint of the whole species' log2 range (a
+ *                       coarser rule kept for comparison: the stored values
+ *                       are larger, so FP16/BF16 rounding errors grow).
+ *                       CIA rows keep per-row offsets; ignored for F64.
  * Copies everything to the device; host arrays may be freed on return.  One
  * species block (n_T * n_p rows of n_nu rounded up to 64 entries, in the
  * storage type) must stay below 4 GiB, and so must the CIA blocks of both
  * pairs together (n_cia * n_T rows); the whole table may be larger.  These
  * sizes are checked before anything is read or allocated.
  * Errors: HR2_E_INVALID_ARG (NULL, NaN/Inf, non-monotone axis, counts out of
- * [1, HR2_MAX_SPECIES], n_cia not 0/2), HR2_E_OUT_OF_RANGE (a species block,
+ * [1, HR2_MAX_SPECIES], n_cia not 0/2, offset_mode not 0/1), HR2_E_OUT_OF_RANGE (a species block,
  * or the CIA blocks together, of 4 GiB or more), HR2_E_NO_MEMORY,
  * HR2_E_DEVICE. */
 typedef struct {
@@ -194,6 +205,7 @@ typedef struct {
   const double *log10_k_cia;
   double he_h2_ratio;
   hr2_table_dtype dtype;
+  int offset_mode;   /* hr2_offset_mode; zero-initialise for the default */
 } hr2_tables_desc;
 
 hr2_status hr2_tables_create(hr2_ctx *ctx, const hr2_tables_desc *desc, hr2_tables **out);
@@ -452,14 +464,17 @@ hr2_status hr2_forward_params_dev(hr2_ctx *ctx, const hr2_tables *tables, const 
                                   double *lnl_dev, int *set_status_dev, void *stream);
 
 /* ---- serving: continuous batching of uneven forward-model requests ----
- * A scheduler thread owns one stream.  Requests (each n_sets columns sharing
- * n_levels, its own window, resolving power and bins) are admitted while
- * their device footprint fits the budget and a slot is free; every step
- * launches the opacity+RT work of all admitted, not yet launched requests as
- * one launch, then their convolution/binning, then copies bins to pinned
- * host memory.  Requests arriving meanwhile join the next step.  Per-set
- * arithmetic does not depend on the other requests in a step, so a result is
- * bit-identical alone and in the mix. */
+ * A scheduler thread owns two streams.  Requests (each n_sets columns
+ * sharing n_levels, its own window, resolving power and bins) are admitted
+ * while their device footprint fits the budget and a slot is free; every
+ * step takes all admitted, not yet launched requests and runs them with one
+ * upload of their columns and bin plans, one level-record launch, one pair
+ * of observation-layout launches, one opacity+RT launch per kernel variant
+ * (chunking and angle tier), one convolution/binning launch and one copy of
+ * all their bins to pinned host memory.  Requests arriving meanwhile join
+ * the next step; up to two steps are in flight.  Per-set arithmetic does not
+ * depend on the other requests in a step, so a result is bit-identical
+ * alone and in the mix. */
 typedef struct {
   hr2_window window;
   double resolving_power;
@@ -483,7 +498,11 @@ typedef struct {
 } hr2_request_info;
 
 /* hbm_budget_bytes: cap on the device bytes held by admitted requests
- * (level records, F+, layouts, bins); max_slots: cap on admitted requests.
+ * (level records, F+, layouts and their build scratch); max_slots: cap on
+ * admitted requests.  Each of the two step streams also keeps a grow-only
+ * stage outside the budget for the inputs and bins of the step it runs
+ * (per request 8 (2 L + S + 5) n_sets + 28 n_bins bytes of inputs and
+ * 4 n_sets n_bins bytes of bins, 8 with F64 tables, each rounded up to 256).
  * Errors: HR2_E_INVALID_ARG, HR2_E_DEVICE. */
 hr2_status hr2_serve_create(hr2_ctx *ctx, const hr2_tables *tables, size_t hbm_budget_bytes,
                             int max_slots, hr2_server **out);

@@ -277,6 +277,7 @@ extern "C" hr2_status hr2_ctx_set_option(hr2_ctx *ctx, hr2_option opt, int value
         return set_error(HR2_E_INVALID_ARG, "row policy must be 0 (auto), 1 or 2");
       ctx->opt_row_policy = value;
       return HR2_OK;
+
   }
   return set_error(HR2_E_INVALID_ARG, "unknown option");
 }
@@ -303,10 +304,11 @@ inline uint16_t to_bf16(double y) {
 }
 
 // Convert rows of log10 values to stored log2 values minus the row offset
-// (midpoint of the row's log2 range); returns false on a non-finite input.
+// (midpoint of the row's log2 range, or fixed_off[r] when given); returns
+// false on a non-finite input.
 template <typename TT>
 bool convert_rows(const double *src, int64_t n_rows, int64_t n_nu, int64_t pitch, bool offset,
-                  TT *dst, double *off) {
+                  TT *dst, double *off, const double *fixed_off = nullptr) {
   bool ok = true;
   const int n_thr = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
   std::vector<std::thread> pool;
@@ -322,7 +324,7 @@ bool convert_rows(const double *src, int64_t n_rows, int64_t n_nu, int64_t pitch
           lo = std::min(lo, y);
           hi = std::max(hi, y);
         }
-        const double o = offset ? 0.5 * (lo + hi) : 0.0;
+        const double o = !offset ? 0.0 : (fixed_off ? fixed_off[r] : 0.5 * (lo + hi));
         off[r] = o;
         TT *d = dst + r * pitch;
         for (int64_t k = 0; k < n_nu; ++k) {
@@ -341,9 +343,47 @@ bool convert_rows(const double *src, int64_t n_rows, int64_t n_nu, int64_t pitch
   return ok;
 }
 
+// Midpoint of each species' log2 range (rows_per_species rows each), copied
+// to every row of the species; false on a non-finite input.
+bool species_offsets(const double *src, int n_species, int64_t rows_per_species, int64_t n_nu,
+                     std::vector<double> &row_off) {
+  row_off.assign((size_t)n_species * rows_per_species, 0.0);
+  const int64_t n_rows = (int64_t)n_species * rows_per_species;
+  const int n_thr = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+  std::vector<double> lo(n_rows, INFINITY), hi(n_rows, -INFINITY);
+  std::vector<char> ok(n_thr, 1);
+  std::vector<std::thread> pool;
+  for (int t = 0; t < n_thr; ++t) {
+    pool.emplace_back([=, &lo, &hi, &ok]() {
+      for (int64_t r = t; r < n_rows; r += n_thr) {
+        const double *a = src + r * n_nu;
+        for (int64_t k = 0; k < n_nu; ++k) {
+          const double y = a[k] * kLog2of10;
+          if (!std::isfinite(y)) ok[t] = 0;
+          lo[r] = std::min(lo[r], y);
+          hi[r] = std::max(hi[r], y);
+        }
+      }
+    });
+  }
+  for (auto &th : pool) th.join();
+  for (char c : ok)
+    if (!c) return false;
+  for (int q = 0; q < n_species; ++q) {
+    double l = INFINITY, h = -INFINITY;
+    for (int64_t r = 0; r < rows_per_species; ++r) {
+      l = std::min(l, lo[q * rows_per_species + r]);
+      h = std::max(h, hi[q * rows_per_species + r]);
+    }
+    for (int64_t r = 0; r < rows_per_species; ++r) row_off[q * rows_per_species + r] = 0.5 * (l + h);
+  }
+  return true;
+}
+
 template <typename TT>
 hr2_status upload_table(const double *src, int64_t n_rows, int64_t n_nu, int64_t pitch,
-                        bool offset, void **dptr, double *off, size_t *bytes_out) {
+                        bool offset, void **dptr, double *off, size_t *bytes_out,
+                        const double *fixed_off = nullptr) {
   const size_t bytes = (size_t)n_rows * pitch * sizeof(TT);
   if (hipMalloc(dptr, bytes) != hipSuccess) {
     *dptr = nullptr;
@@ -357,7 +397,8 @@ hr2_status upload_table(const double *src, int64_t n_rows, int64_t n_nu, int64_t
   for (int64_t r0 = 0; r0 < n_rows; r0 += rows_per_block) {
     const int64_t nr = std::min(rows_per_block, n_rows - r0);
     buf.resize((size_t)nr * pitch);
-    if (!convert_rows<TT>(src + r0 * n_nu, nr, n_nu, pitch, offset, buf.data(), off + r0))
+    if (!convert_rows<TT>(src + r0 * n_nu, nr, n_nu, pitch, offset, buf.data(), off + r0,
+                          fixed_off ? fixed_off + r0 : nullptr))
       return set_error(HR2_E_INVALID_ARG, "table holds a non-finite value");
     HIP_TRY(hipMemcpy((TT *)*dptr + r0 * pitch, buf.data(), (size_t)nr * pitch * sizeof(TT),
                       hipMemcpyHostToDevice));
@@ -394,6 +435,8 @@ extern "C" hr2_status hr2_tables_create(hr2_ctx *ctx, const hr2_tables_desc *d, 
       return set_error(HR2_E_INVALID_ARG, "molar masses must be positive");
   if (d->dtype < HR2_TABLE_F32 || d->dtype > HR2_TABLE_F64)
     return set_error(HR2_E_INVALID_ARG, "unknown table dtype");
+  if (d->offset_mode != HR2_OFFSET_ROW && d->offset_mode != HR2_OFFSET_SPECIES)
+    return set_error(HR2_E_INVALID_ARG, "offset_mode must be 0 (per row) or 1 (per species)");
 
   const int S = d->n_species, nT = d->n_T, nP = d->n_p, nc = d->n_cia;
   const int64_t n_nu = d->n_nu, pitch = (n_nu + 63) / 64 * 64;
@@ -416,23 +459,30 @@ extern "C" hr2_status hr2_tables_create(hr2_ctx *ctx, const hr2_tables_desc *d, 
   t->off_cia.assign((size_t)std::max(nc, 1) * nT, 0.0);
   const bool f64 = d->dtype == HR2_TABLE_F64;
   const int64_t rows = (int64_t)S * nT * nP;
-  hr2_status st;
-  switch (d->dtype) {
-    case HR2_TABLE_F64:
-      st = upload_table<double>(d->log10_sigma, rows, n_nu, pitch, false, &t->d_tab,
-                                t->off.data(), &t->bytes);
-      break;
-    case HR2_TABLE_F16:
-      st = upload_table<_Float16>(d->log10_sigma, rows, n_nu, pitch, true, &t->d_tab,
+  hr2_status st = HR2_OK;
+  std::vector<double> sp_off;
+  const bool per_species = d->offset_mode == HR2_OFFSET_SPECIES && !f64;
+  if (per_species && !species_offsets(d->log10_sigma, S, (int64_t)nT * nP, n_nu, sp_off))
+    st = set_error(HR2_E_INVALID_ARG, "table holds a non-finite value");
+  const double *fixed = per_species ? sp_off.data() : nullptr;
+  if (st == HR2_OK) {
+    switch (d->dtype) {
+      case HR2_TABLE_F64:
+        st = upload_table<double>(d->log10_sigma, rows, n_nu, pitch, false, &t->d_tab,
                                   t->off.data(), &t->bytes);
-      break;
-    case HR2_TABLE_BF16:
-      st = upload_table<uint16_t>(d->log10_sigma, rows, n_nu, pitch, true, &t->d_tab,
-                                  t->off.data(), &t->bytes);
-      break;
-    default:
-      st = upload_table<float>(d->log10_sigma, rows, n_nu, pitch, true, &t->d_tab, t->off.data(),
-                               &t->bytes);
+        break;
+      case HR2_TABLE_F16:
+        st = upload_table<_Float16>(d->log10_sigma, rows, n_nu, pitch, true, &t->d_tab,
+                                    t->off.data(), &t->bytes, fixed);
+        break;
+      case HR2_TABLE_BF16:
+        st = upload_table<uint16_t>(d->log10_sigma, rows, n_nu, pitch, true, &t->d_tab,
+                                    t->off.data(), &t->bytes, fixed);
+        break;
+      default:
+        st = upload_table<float>(d->log10_sigma, rows, n_nu, pitch, true, &t->d_tab,
+                                 t->off.data(), &t->bytes, fixed);
+    }
   }
   if (st == HR2_OK && nc > 0) {
     if (f64)
@@ -583,24 +633,28 @@ ColumnsView columns_view(const void *dev, int n_sets, int L, int S) {
 // W * steps / capacity (the resident-wave throughput); pick the C with the
 // smaller of the two maxima (small penalty per chunk for the combine).
 // Depends on the request and the device only.
-int auto_chunks(const TableView &tv, int64_t base_waves, int n_levels, int n_mu,
-                bool from_chi, bool para) {
-  // capacities depend on the kernel variant and the device only: cache them
+// Resident waves of the column kernel variant for (tables, angles, chunks)
+// on the current device; they depend on the variant and the device only, so
+// they are cached.
+int cached_wave_capacity(const TableView &tv, int n_mu, bool from_chi, int c, bool para) {
   static std::mutex mu;
   static std::map<std::tuple<int, int, int, int, int, bool, int, bool>, int> cache;
   int dev = 0;
   (void)hipGetDevice(&dev);
-  auto capacity = [&](int c) {
-    const int big = (int64_t)tv.S * tv.nT * tv.nP * tv.pitch * tv.tab_elem >= 0xFFFFFFFFll;
-    const auto key =
-        std::make_tuple(dev, tv.dtype, tv.S, big, column_mu_class(n_mu), from_chi, c, para);
-    std::lock_guard<std::mutex> lk(mu);
-    auto it = cache.find(key);
-    if (it != cache.end()) return it->second;
-    const int v = column_wave_capacity(tv, n_mu, from_chi, c, para);
-    cache.emplace(key, v);
-    return v;
-  };
+  const int big = (int64_t)tv.S * tv.nT * tv.nP * tv.pitch * tv.tab_elem >= 0xFFFFFFFFll;
+  const auto key =
+      std::make_tuple(dev, tv.dtype, tv.S, big, column_mu_class(n_mu), from_chi, c, para);
+  std::lock_guard<std::mutex> lk(mu);
+  auto it = cache.find(key);
+  if (it != cache.end()) return it->second;
+  const int v = column_wave_capacity(tv, n_mu, from_chi, c, para);
+  cache.emplace(key, v);
+  return v;
+}
+
+int auto_chunks(const TableView &tv, int64_t base_waves, int n_levels, int n_mu,
+                bool from_chi, bool para) {
+  auto capacity = [&](int c) { return cached_wave_capacity(tv, n_mu, from_chi, c, para); };
   int best = 1;
   double best_cost = 1e300;
   for (int c = 1; c <= 8 && c <= n_levels - 1; ++c) {
@@ -957,9 +1011,37 @@ hr2_status launch_forward(hr2_ctx *ctx, const hr2_tables *t, const hr2_obs *o,
     for (int k = 0; k < 4; ++k) ev[k] = timing_event(ctx, k);
   const bool timed = ev[0] && ev[1] && ev[2] && ev[3];
   if (timed) HIP_TRY(hipEventRecord(ev[0], s));
+  const int64_t base_waves = (int64_t)B * ((w.nu_count + 63) / 64);
+  // Small windows in a batch that fills the device on its own: the whole
+  // forward model in one launch, one workgroup per set (records and F+ in
+  // LDS).  Columns and bins only; the same arithmetic as the three kernels.
+  if (theta == nullptr && like == nullptr && ctx->opt_chunks == 0 && ctx->opt_source == 1 &&
+      set_forward_fits(t->view, L, w.nu_count) && conv_items_per_wg(o->nnz, o->n_bins) == 4 &&
+      base_waves >= cached_wave_capacity(t->view, n_mu, false, 1, false)) {
+    SetFwdArgs a{};
+    a.nu_begin = w.nu_begin;
+    a.nu_count = w.nu_count;
+    a.nu_stride = w.nu_stride;
+    a.n_mu = n_mu;
+    a.n_bins = o->n_bins;
+    a.fplus = (float *)fplus;
+    a.bins = (float *)bins;
+    a.status = status;
+    a.K = (const float *)o->d_K;
+    a.kstart = o->d_kstart;
+    a.mlo = o->d_mlo;
+    a.mlen = o->d_mlen;
+    if (timed) HIP_TRY(hipEventRecord(ev[1], s));
+    HIP_TRY(launch_set_forward(t->view, cv, a, n_mu, s));
+    if (timed) {
+      HIP_TRY(hipEventRecord(ev[2], s));
+      HIP_TRY(hipEventRecord(ev[3], s));
+      ctx->tev_used += 4;
+    }
+    return HR2_OK;
+  }
   HIP_TRY(launch_levels(t->view, cv, scr.recs, status, t->view.dtype == HR2_TABLE_F64, s,
                         theta));
-  const int64_t base_waves = (int64_t)B * ((w.nu_count + 63) / 64);
   const int chunks = ctx->opt_chunks ? std::min(ctx->opt_chunks, std::max(1, L - 1))
                                      : auto_chunks(t->view, base_waves, L, n_mu, false,
                                                    ctx->opt_source == 2);

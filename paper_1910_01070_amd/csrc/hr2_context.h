@@ -65,6 +65,7 @@ void pack_columns(const hr2_tables *t, int n_sets, const hr2_column *cols,
 ColumnsView columns_view(const void *dev, int n_sets, int L, int S);
 int auto_chunks(const TableView &tv, int64_t base_waves, int n_levels, int n_mu, bool from_chi,
                 bool para);
+int cached_wave_capacity(const TableView &tv, int n_mu, bool from_chi, int chunks, bool para);
 
 // Likelihood outputs of a forward call (NULL: bins only).
 struct LikeArgs {

@@ -88,6 +88,31 @@ struct ColumnsView {
   int B, L;
 };
 
+// One segment of a level-kernel launch: the sets of one batch (a request
+// when serving) and where their records go.
+struct LevelSeg {
+  int64_t wg_begin;        // first workgroup of the segment
+  int64_t rec_offset;      // records of set s: recs + rec_offset + s * n_levels
+  ColumnsView cv;
+  int32_t blocks_per_set;  // workgroups per set (from level_blocks_per_set)
+  int32_t pad;
+};
+
+// One segment of an observation-layout build (one layout per segment).
+struct ObsSeg {
+  int64_t norm_wg_begin;     // first workgroup of the segment in the normalisation launch
+  int64_t weight_wg_begin;   // first workgroup in the weights launch
+  int64_t N, i0, n_pts, nnz;
+  double nu_first, dnu, denom;
+  int32_t n_bins, pad;
+  const int64_t *edge_idx;   // [n_bins + 1] snapped edges
+  const int64_t *kstart;     // [n_bins]
+  const int32_t *mlo;        // [n_bins]
+  int32_t *h;                // [n_pts] 5 sigma half widths (written)
+  void *q, *invz;            // [n_pts] scratch (Real)
+  void *K;                   // [nnz] weights (Real, written)
+};
+
 // One segment of a column-kernel launch: a batch of sets sharing levels and
 // a wavenumber window (a forward_batch call, or one request when serving).
 struct ColSeg {
@@ -121,6 +146,19 @@ struct ConvSeg {
   const double *s2;         // [n_bins] sigma_j^2
   const double *log10_eps;  // [n_sets] error inflation exponent, or NULL
   double *terms;            // [n_sets][n_bins] per-bin terms of ln L
+};
+
+// Arguments of the whole-forward-model-per-set launch (small windows).
+struct SetFwdArgs {
+  int64_t nu_begin, nu_count, nu_stride;
+  int32_t n_mu, n_bins;
+  float *fplus;             // [B][nu_count] unscaled F+ (written)
+  float *bins;              // [B][n_bins] (written)
+  int *status;              // [B] or NULL
+  const float *K;           // layout weights
+  const int64_t *kstart;    // [n_bins]
+  const int32_t *mlo;       // [n_bins]
+  const int32_t *mlen;      // [n_bins]
 };
 
 // Angular quadrature constants for n_mu = 1..8 (Eq. 8): row n-1.
@@ -165,6 +203,13 @@ struct ThetaArgs {
 hipError_t launch_levels(const TableView &tv, const ColumnsView &cv, void *recs,
                          int *status, bool fp64, hipStream_t stream,
                          const ThetaArgs *theta = nullptr);
+// Workgroups per set of the segmented level launch for columns of L levels.
+int level_blocks_per_set(const TableView &tv, int L);
+// Several batches in one launch: segs_dev[n_segs] in device memory (ascending
+// wg_begin, blocks_per_set from level_blocks_per_set), records relative to
+// recs_base; total_wgs = the workgroups of all segments.
+hipError_t launch_levels_segs(const TableView &tv, const LevelSeg *segs_dev, int n_segs,
+                              int64_t total_wgs, void *recs_base, bool fp64, hipStream_t stream);
 
 // One workgroup = `chunks` waves = one 64-point tile of one set; every
 // segment of the launch must use that chunk count.
@@ -183,6 +228,15 @@ int column_nu_per_wg(int chunks);
 int column_mu_class(int n_mu);
 int column_wave_capacity(const TableView &tv, int max_mu, bool opacity_from_memory, int chunks,
                          bool para);
+
+// The whole forward model in one launch, one workgroup per set: for FP32,
+// FP16 and BF16 tables of at most eight species (below 4 GiB), columns of at
+// most 64 levels and windows of at most 4096 points (set_forward_fits), a
+// linear source and a layout with short supports (one wave per bin).  Same
+// arithmetic as the level, column (one chunk) and convolve/bin kernels.
+bool set_forward_fits(const TableView &tv, int n_levels, int64_t nu_count);
+hipError_t launch_set_forward(const TableView &tv, const ColumnsView &cv, const SetFwdArgs &args,
+                              int max_mu, hipStream_t stream);
 
 hipError_t launch_opacity_only(const TableView &tv, const void *recs, int n_levels,
                                int64_t nu_begin, int64_t nu_count, int64_t nu_stride,
@@ -216,6 +270,13 @@ hipError_t launch_obs_build(bool fp64, int64_t N, double nu_first, double dnu_ef
                             int64_t i0, int64_t n_pts, void *q_scratch, void *invz_scratch,
                             const int64_t *kstart_dev, const int32_t *mlo_dev, void *K_dev,
                             hipStream_t stream);
+// Workgroups of one layout in the normalisation and the weights launches.
+int64_t obs_norm_workgroups(bool fp64, int64_t n_pts);
+int64_t obs_weight_workgroups(int64_t nnz);
+// Several layouts in two launches: segs_dev[n_segs] in device memory
+// (ascending workgroup offsets from the two functions above).
+hipError_t launch_obs_build_segs(bool fp64, const ObsSeg *segs_dev, int n_segs,
+                                 int64_t norm_wgs, int64_t weight_wgs, hipStream_t stream);
 
 }  // namespace hr2
 

@@ -216,18 +216,19 @@ __device__ const double *theta_tail(const ParamView &pv, const double *th) {
 // 128 threads 7.0-7.3 us; 64 threads 8.3-8.4 us)
 constexpr int kLevelThreads = 128;
 
+// The level records of set s, written to recs_set[0 .. L-1] (global or LDS
+// memory): the items of that set that fall to this workgroup, which is
+// workgroup `part` of the blocks_per_set ones sharing the set.  Every thread
+// of the workgroup calls it (it has barriers).
 template <typename Real>
-__global__ __launch_bounds__(kLevelThreads) void k_levels(TableView tv, ColumnsView cv,
-                                                typename RecOf<Real>::type *recs, int *status,
-                                                int blocks_per_set, ThetaArgs ta) {
+__device__ void level_records(const TableView &tv, const ColumnsView &cv, int s, int part,
+                              int blocks_per_set, typename RecOf<Real>::type *recs_set,
+                              int *status, const ThetaArgs &ta) {
   using Rec = typename RecOf<Real>::type;
   __shared__ double s_T[kMaxAxis], s_lp[kMaxAxis];
   __shared__ double s_pl[HR2_MAX_LEVELS], s_Tl[HR2_MAX_LEVELS];
   __shared__ double s_x[kMaxSpecies], s_m[kMaxSpecies];
   __shared__ CellW s_cell[HR2_MAX_LEVELS];
-  // blocks_per_set workgroups share one set's items; each stages the set
-  const int s = blockIdx.x / blocks_per_set;
-  const int part = blockIdx.x - s * blocks_per_set;
   const int L = cv.L;
   const int S = tv.S;
   // one coalesced pass over the set's inputs and the axes
@@ -323,7 +324,7 @@ __global__ __launch_bounds__(kLevelThreads) void k_levels(TableView tv, ColumnsV
     if (t >= L && t < 2 * L) {
       // the layer above level l: half thickness and cloud optical depth
       const int l = t - L;
-      Rec *r = recs + (int64_t)s * L + l;
+      Rec *r = recs_set + l;
       double hdz = 0.0, dtc = 0.0;
       if (l + 1 < L) {
         const double tbar = 0.5 * (s_Tl[l] + s_Tl[l + 1]);
@@ -342,7 +343,7 @@ __global__ __launch_bounds__(kLevelThreads) void k_levels(TableView tv, ColumnsV
       r->dtc = (Real)dtc;
     } else if (t < L) {
       const int l = t;
-      Rec *r = recs + (int64_t)s * L + l;
+      Rec *r = recs_set + l;
       const CellW c = cell_of(l);
       const bool has_prev = l > 0, has_next = l + 1 < L;
       const CellW cp = has_prev ? cell_of(l - 1) : c;
@@ -398,7 +399,7 @@ __global__ __launch_bounds__(kLevelThreads) void k_levels(TableView tv, ColumnsV
       // keeping its exp2 argument small.
       const int u = t - 2 * L;
       const int l = u / per_level, q = u - l * per_level;
-      Rec *r = recs + (int64_t)s * L + l;
+      Rec *r = recs_set + l;
       const CellW c = cell_of(l);
       const double n = s_pl[l] * 1.0e6 / (kKB * s_Tl[l]);
       if (q < S) {
@@ -426,6 +427,30 @@ __global__ __launch_bounds__(kLevelThreads) void k_levels(TableView tv, ColumnsV
   }
 }
 
+// n_segs == 0: one batch, passed by value in seg0; otherwise the segment
+// holding this workgroup (the last one with wg_begin <= blockIdx.x)
+template <typename Real>
+__global__ __launch_bounds__(kLevelThreads) void k_levels(TableView tv, const LevelSeg *segs,
+                                                int n_segs, LevelSeg seg0,
+                                                typename RecOf<Real>::type *recs_base,
+                                                int *status, ThetaArgs ta) {
+  int sg = 0;
+  for (int lo = 0, hi = n_segs; hi - lo > 1;) {
+    const int mid = (lo + hi) >> 1;
+    if (segs[mid].wg_begin <= (int64_t)blockIdx.x) lo = mid;
+    else hi = mid;
+    sg = lo;
+  }
+  const LevelSeg d = n_segs == 0 ? seg0 : segs[sg];
+  const int blocks_per_set = d.blocks_per_set;
+  // blocks_per_set workgroups share one set's items; each stages the set
+  const int64_t local = (int64_t)blockIdx.x - d.wg_begin;
+  const int s = (int)(local / blocks_per_set);
+  const int part = (int)(local - (int64_t)s * blocks_per_set);
+  level_records<Real>(tv, d.cv, s, part, blocks_per_set,
+                      recs_base + d.rec_offset + (int64_t)s * d.cv.L, status, ta);
+}
+
 hipError_t launch_levels(const TableView &tv, const ColumnsView &cv, void *recs, int *status,
                          bool fp64, hipStream_t stream, const ThetaArgs *theta) {
   ThetaArgs ta{};
@@ -435,12 +460,36 @@ hipError_t launch_levels(const TableView &tv, const ColumnsView &cv, void *recs,
   const int threads = (int)std::min<int64_t>(kLevelThreads, (items + 63) / 64 * 64);
   const int per_set = (int)((items + threads - 1) / threads);
   const dim3 grid((unsigned)((int64_t)cv.B * per_set));
+  LevelSeg seg0{};
+  seg0.wg_begin = 0;
+  seg0.rec_offset = 0;
+  seg0.cv = cv;
+  seg0.blocks_per_set = per_set;
   if (fp64)
-    hipLaunchKernelGGL(k_levels<double>, grid, dim3(threads), 0, stream, tv, cv,
-                       (LevelRecD *)recs, status, per_set, ta);
+    hipLaunchKernelGGL(k_levels<double>, grid, dim3(threads), 0, stream, tv, nullptr, 0, seg0,
+                       (LevelRecD *)recs, status, ta);
   else
-    hipLaunchKernelGGL(k_levels<float>, grid, dim3(threads), 0, stream, tv, cv,
-                       (LevelRecF *)recs, status, per_set, ta);
+    hipLaunchKernelGGL(k_levels<float>, grid, dim3(threads), 0, stream, tv, nullptr, 0, seg0,
+                       (LevelRecF *)recs, status, ta);
+  return hipGetLastError();
+}
+
+int level_blocks_per_set(const TableView &tv, int L) {
+  const int64_t items = (int64_t)L * (2 + tv.S + tv.n_cia);
+  return (int)((items + kLevelThreads - 1) / kLevelThreads);
+}
+
+hipError_t launch_levels_segs(const TableView &tv, const LevelSeg *segs_dev, int n_segs,
+                              int64_t total_wgs, void *recs_base, bool fp64, hipStream_t stream) {
+  if (total_wgs <= 0) return hipSuccess;
+  const ThetaArgs ta{};
+  const LevelSeg seg0{};
+  if (fp64)
+    hipLaunchKernelGGL(k_levels<double>, dim3((unsigned)total_wgs), dim3(kLevelThreads), 0,
+                       stream, tv, segs_dev, n_segs, seg0, (LevelRecD *)recs_base, nullptr, ta);
+  else
+    hipLaunchKernelGGL(k_levels<float>, dim3((unsigned)total_wgs), dim3(kLevelThreads), 0,
+                       stream, tv, segs_dev, n_segs, seg0, (LevelRecF *)recs_base, nullptr, ta);
   return hipGetLastError();
 }
 
@@ -1436,6 +1485,204 @@ hipError_t launch_convolve_bin(bool fp64, const ConvSeg *segs_dev, int n_segs,
   return hipGetLastError();
 }
 
+// ------------------------------------------- whole forward model per set
+// Small windows in large batches (the sampler's many live points on a short
+// spectral range): one workgroup per set runs the whole forward model in
+// one launch.  It builds the set's level records in LDS (the same items as
+// k_levels), sweeps every 64-point tile of the window with the fused
+// opacity + short-characteristics recurrence (one layer chunk; waves take
+// tiles in turn), keeps F+ in LDS (and writes it out), then forms the set's
+// bins one wave per bin from LDS.  The arithmetic is that of k_column with
+// one chunk and of k_convolve_bin's one-wave-per-bin scheme, step for step.
+constexpr int kSetThreads = 1024;
+constexpr int kSetMaxLevels = 64;
+constexpr int kSetMaxNu = 4096;
+
+template <typename TT, int NSS, int MAXMU>
+__global__ __launch_bounds__(kSetThreads) __attribute__((amdgpu_waves_per_eu(8))) void k_set_forward(
+    TableView tv, ColumnsView cv, SetFwdArgs a) {
+  using Rec = LevelRecF;
+  constexpr int NS = NSS < 0 ? -NSS : NSS;
+  constexpr bool kExact = NSS < 0;
+  __shared__ Rec s_rec[kSetMaxLevels];
+  __shared__ float s_fp[kSetMaxNu];
+  const int s = blockIdx.x;
+  const int L = cv.L;
+  level_records<float>(tv, cv, s, 0, 1, s_rec, a.status, ThetaArgs{});
+  __syncthreads();
+
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  const int n_waves = blockDim.x >> 6;
+  const int64_t nu_count = a.nu_count;
+  const int tiles = (int)((nu_count + 63) / 64);
+  const int nmu = a.n_mu;
+  const int64_t sp_bytes = (int64_t)tv.nT * tv.nP * tv.pitch * (int64_t)sizeof(TT);
+  const int64_t pair_bytes = (int64_t)tv.nT * tv.pitch * (int64_t)sizeof(float);
+  const rsrc_t rs = make_rsrc(tv.tab, sp_bytes * tv.S);
+  const rsrc_t rc = make_rsrc(tv.cia, 2 * pair_bytes);
+  const int S = kExact ? NS : tv.S;
+  const bool has_cia = tv.n_cia > 0;
+  float a_mu[MAXMU], a_inv[MAXMU], a_l2e[MAXMU];
+#pragma unroll
+  for (int k = 0; k < MAXMU; ++k) {
+    a_mu[k] = c_ang.mu[nmu - 1][k];
+    a_inv[k] = c_ang.inv_mu[nmu - 1][k];
+    a_l2e[k] = c_ang.l2e_mu[nmu - 1][k];
+  }
+
+  for (int t = wave; t < tiles; t += n_waves) {
+    const int64_t j = (int64_t)t * 64 + lane;
+    const bool active = j < nu_count;
+    const int64_t jj = active ? j : nu_count - 1;
+    const int64_t kidx = a.nu_begin + jj * a.nu_stride;
+    const uint32_t kk = (uint32_t)kidx;
+    const double nu_d = tv.nu0 + (double)kidx * tv.dnu;
+    const float nu_hi = (float)nu_d;
+    const float nu_lo = (float)(nu_d - (double)nu_hi);
+    const float c1nu3_f = (float)(kC1 * nu_d * nu_d * nu_d);
+    const uint32_t kb = kk * (uint32_t)sizeof(TT);
+    const uint32_t kbc = kk * (uint32_t)sizeof(float);
+    float slot[NS][4];
+    float cslot[2][2];
+#pragma unroll
+    for (int q = 0; q < NS; ++q)
+#pragma unroll
+      for (int k = 0; k < 4; ++k) slot[q][k] = 0.0f;
+#pragma unroll
+    for (int q = 0; q < 2; ++q) cslot[q][0] = cslot[q][1] = 0.0f;
+    auto fetch = [&](const Rec &rr, int mask) {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        if (mask & (1 << k)) {
+          const uint32_t off = rr.rowb[k] + kb;
+#pragma unroll
+          for (int q = 0; q < NS; ++q)
+            if (q < S)
+              slot[q][k] = to_float<TT>(buf_load<TT>(rs, off, (uint32_t)(q * sp_bytes)));
+        }
+      }
+      if (has_cia) {
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+          if (mask & (16 << k)) {
+            const uint32_t off = rr.cia_rowb[k] + kbc;
+            cslot[0][k] = buf_load<float>(rc, off, 0);
+            cslot[1][k] = buf_load<float>(rc, off, (uint32_t)pair_bytes);
+          }
+        }
+      }
+    };
+    auto opacity = [&](const Rec &r) -> float {
+      float chi = 0.0f;
+#pragma unroll
+      for (int q = 0; q < NS; ++q) {
+        if (q < S) {
+          const float y = r.w[0] * slot[q][0] + r.w[1] * slot[q][1] + r.w[2] * slot[q][2] +
+                          r.w[3] * slot[q][3];
+          chi = fmaf(r.a_s[q], fexp2(y), chi);
+        }
+      }
+      if (has_cia) {
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+          const float y = r.cia_w[0] * cslot[q][0] + r.cia_w[1] * cslot[q][1];
+          chi = fmaf(r.a_cia[q], fexp2(y), chi);
+        }
+      }
+      return chi;
+    };
+    float I[MAXMU];
+    float chi_prev = 0.0f, S_prev = 0.0f, hdz_prev = 0.0f, dtc_prev = 0.0f;
+    fetch(s_rec[0], __builtin_amdgcn_readfirstlane(s_rec[0].mask) >> 8);
+    for (int l = 0; l < L; ++l) {
+      const Rec r = s_rec[l];
+      const float chi = opacity(r);
+      if (l + 1 < L) {
+        const Rec &rn = s_rec[l + 1];
+        asm volatile("" ::: "memory");
+        fetch(rn, __builtin_amdgcn_readfirstlane(rn.mask));
+      }
+      const float Sl = planck_f(nu_hi, nu_lo, c1nu3_f, r.pl_hi, r.pl_lo);
+      if (l == 0) {
+#pragma unroll
+        for (int k = 0; k < MAXMU; ++k) I[k] = Sl;
+      } else {
+        // trapezoid of chi over the layer, plus its share of a gray cloud
+        const float dtau = (chi_prev + chi) * hdz_prev + dtc_prev;
+        const float D = S_prev - Sl, rD = D * frcp(dtau);
+#pragma unroll
+        for (int k = 0; k < MAXMU; ++k)
+          if (k < nmu) I[k] = sc_step_f(I[k], dtau, rD, Sl, S_prev, D, a_inv[k], a_l2e[k], a_mu[k]);
+      }
+      chi_prev = chi;
+      S_prev = Sl;
+      hdz_prev = r.hdz;
+      dtc_prev = r.dtc;
+    }
+    float F = 0.0f;
+#pragma unroll
+    for (int k = 0; k < MAXMU; ++k)
+      if (k < nmu) F = fmaf(c_ang.cw[nmu - 1][k], I[k], F);
+    if (active) {
+      s_fp[j] = F;
+      a.fplus[(int64_t)s * nu_count + j] = F;
+    }
+  }
+  __syncthreads();
+
+  // Eq. 17 and the binning: one wave per bin, as k_convolve_bin's short-
+  // support scheme, from the F+ in LDS
+  const float sc = (float)cv.scale[s];
+  for (int jb = wave; jb < a.n_bins; jb += n_waves) {
+    float acc = conv_partial<float, 64>(a.K + a.kstart[jb], s_fp + a.mlo[jb], a.mlen[jb], lane);
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+    if (lane == 0) a.bins[(int64_t)s * a.n_bins + jb] = acc * sc;
+  }
+}
+
+template <typename TT, int MAXMU>
+static bool set_forward_kernel(int S, void (**fn)(TableView, ColumnsView, SetFwdArgs)) {
+  if (S == 1) *fn = &k_set_forward<TT, -1, MAXMU>;
+  else if (S <= 8) *fn = &k_set_forward<TT, 8, MAXMU>;
+  else return false;
+  return true;
+}
+
+bool set_forward_fits(const TableView &tv, int n_levels, int64_t nu_count) {
+  return tv.dtype != HR2_TABLE_F64 && tv.S <= 8 && n_levels <= kSetMaxLevels &&
+         nu_count <= kSetMaxNu &&
+         (int64_t)tv.nT * tv.nP * tv.pitch * tv.tab_elem * tv.S < 0xFFFFFFFFll;
+}
+
+hipError_t launch_set_forward(const TableView &tv, const ColumnsView &cv, const SetFwdArgs &args,
+                              int max_mu, hipStream_t stream) {
+  if (cv.B <= 0) return hipSuccess;
+  void (*fn)(TableView, ColumnsView, SetFwdArgs) = nullptr;
+  bool ok;
+  const bool small = max_mu <= kMuTierSmall;
+  switch (tv.dtype) {
+    case HR2_TABLE_F16:
+      ok = small ? set_forward_kernel<_Float16, kMuTierSmall>(tv.S, &fn)
+                 : set_forward_kernel<_Float16, 8>(tv.S, &fn);
+      break;
+    case HR2_TABLE_BF16:
+      ok = small ? set_forward_kernel<uint16_t, kMuTierSmall>(tv.S, &fn)
+                 : set_forward_kernel<uint16_t, 8>(tv.S, &fn);
+      break;
+    case HR2_TABLE_F32:
+      ok = small ? set_forward_kernel<float, kMuTierSmall>(tv.S, &fn)
+                 : set_forward_kernel<float, 8>(tv.S, &fn);
+      break;
+    default:
+      ok = false;
+  }
+  if (!ok) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(fn, dim3((unsigned)cv.B), dim3(kSetThreads), 0, stream, tv, cv, args);
+  return hipGetLastError();
+}
+
 // ln L of set s = the sum of its n_bins terms, in a fixed order (strided
 // per-thread sums, wave butterfly, then the four waves), so repeated calls
 // give identical results.
@@ -1509,46 +1756,65 @@ hipError_t launch_unpack(const ParamView &pv, int n_sets, const double *theta, d
 // window.  Then per bin j with edges a < b: K_j(x) = 1/(b - a) *
 // sum_{i=a}^{b} c_i g_i(x - i) / Z_i, c_i = 1/2 at i = a, b and 1 inside
 // (trapezoid rule over the bin's points, divided by its width).
-// FP64 layouts: the direct sums, one wave per window point.
-__global__ __launch_bounds__(256) void k_obs_norm_f64(int64_t N, double nu_first, double dnu,
-                                                      double denom, int32_t *h, int64_t i0,
-                                                      int64_t n, double *q_out,
-                                                      double *invz_out) {
-  // lanes split the 2h+1 taps, fixed butterfly sum
-  const int64_t t = (int64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int lane = threadIdx.x & 63;
-  if (t >= n) return;
-  const int64_t i = i0 + t;
-  // the 5 sigma cut decides which taps exist: the same FP64 operations as the
-  // host's plan (no contraction into fused multiply-adds), so both find the
-  // same largest k with k dnu <= 5 sigma_i
-  double sig;
-  int hi;
-  {
-#pragma clang fp contract(off)
-    sig = (nu_first + (double)i * dnu) / denom;
-    const double lim = 5.0 * sig;
-    const double hv = floor(lim / dnu);
-    int64_t hh = hv < 1e9 ? (int64_t)hv : (int64_t)1e9;
-    while ((double)(hh + 1) * dnu <= lim) ++hh;
-    while (hh > 0 && (double)hh * dnu > lim) --hh;
-    hi = (int)(hh < N ? hh : N);
+// Each launch covers one or more layouts: n_segs == 0 means the single
+// layout passed by value in seg0, otherwise the segment of the workgroup is
+// the last one whose first workgroup (norm_wg_begin / weight_wg_begin) is at
+// or below it.
+__device__ __forceinline__ ObsSeg obs_seg(const ObsSeg *segs, int n_segs, const ObsSeg &seg0,
+                                          bool weights) {
+  if (n_segs == 0) return seg0;
+  const int64_t g = blockIdx.x;
+  int lo = 0;
+  for (int hi = n_segs; hi - lo > 1;) {
+    const int mid = (lo + hi) >> 1;
+    if ((weights ? segs[mid].weight_wg_begin : segs[mid].norm_wg_begin) <= g) lo = mid;
+    else hi = mid;
   }
-  if (lane == 0) h[t] = hi;
+  return segs[lo];
+}
+
+// The 5 sigma cut decides which taps exist: the same FP64 operations as the
+// host's plan (no contraction into fused multiply-adds), so both find the
+// same largest k with k dnu <= 5 sigma_i.
+__device__ __forceinline__ int obs_half_width(const ObsSeg &d, int64_t i, double &sig) {
+#pragma clang fp contract(off)
+  sig = (d.nu_first + (double)i * d.dnu) / d.denom;
+  const double lim = 5.0 * sig;
+  const double hv = floor(lim / d.dnu);
+  int64_t hh = hv < 1e9 ? (int64_t)hv : (int64_t)1e9;
+  while ((double)(hh + 1) * d.dnu <= lim) ++hh;
+  while (hh > 0 && (double)hh * d.dnu > lim) --hh;
+  return (int)(hh < d.N ? hh : d.N);
+}
+
+// FP64 layouts: the direct sums, one wave per window point (four per
+// workgroup).
+__global__ __launch_bounds__(256) void k_obs_norm_f64(const ObsSeg *segs, int n_segs,
+                                                      ObsSeg seg0) {
+  const ObsSeg d = obs_seg(segs, n_segs, seg0, false);
+  // lanes split the 2h+1 taps, fixed butterfly sum
+  const int64_t t = ((int64_t)blockIdx.x - d.norm_wg_begin) * 4 +
+                    __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (t >= d.n_pts) return;
+  const int64_t i = d.i0 + t;
+  double sig;
+  const int hi = obs_half_width(d, i, sig);
+  if (lane == 0) d.h[t] = hi;
   int64_t klo = -hi, khi = hi;
   if (i + klo < 0) klo = -i;
-  if (i + khi > N - 1) khi = N - 1 - i;
+  if (i + khi > d.N - 1) khi = d.N - 1 - i;
   double z = 0.0;
   for (int64_t k = klo + lane; k <= khi; k += 64) {
-    const double dx = (double)(k < 0 ? -k : k) * dnu;
+    const double dx = (double)(k < 0 ? -k : k) * d.dnu;
     z += exp(-dx * dx / (2.0 * sig * sig));
   }
   const double q = 1.0 / (2.0 * sig * sig);
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) z += __shfl_xor(z, off, 64);
   if (lane == 0) {
-    q_out[t] = q;
-    invz_out[t] = 1.0 / z;
+    ((double *)d.q)[t] = q;
+    ((double *)d.invz)[t] = 1.0 / z;
   }
 }
 
@@ -1580,31 +1846,20 @@ __device__ double gauss_sum_em(double s, double a, double b) {
 // FP32 layouts: one thread per window point.  Z_i in closed form once the
 // profile spans s = sigma_i / dnu >= 4 grid steps, else the direct sum of
 // its at most 41 taps.
-__global__ __launch_bounds__(256) void k_obs_norm_f32(int64_t N, double nu_first, double dnu,
-                                                      double denom, int32_t *h, int64_t i0,
-                                                      int64_t n, float *q_out, float *invz_out) {
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= n) return;
-  const int64_t i = i0 + t;
-  // the 5 sigma cut: the same FP64 operations as the host's plan
+__global__ __launch_bounds__(256) void k_obs_norm_f32(const ObsSeg *segs, int n_segs,
+                                                      ObsSeg seg0) {
+  const ObsSeg d = obs_seg(segs, n_segs, seg0, false);
+  const int64_t t = ((int64_t)blockIdx.x - d.norm_wg_begin) * blockDim.x + threadIdx.x;
+  if (t >= d.n_pts) return;
+  const int64_t i = d.i0 + t;
   double sig;
-  int hi;
-  {
-#pragma clang fp contract(off)
-    sig = (nu_first + (double)i * dnu) / denom;
-    const double lim = 5.0 * sig;
-    const double hv = floor(lim / dnu);
-    int64_t hh = hv < 1e9 ? (int64_t)hv : (int64_t)1e9;
-    while ((double)(hh + 1) * dnu <= lim) ++hh;
-    while (hh > 0 && (double)hh * dnu > lim) --hh;
-    hi = (int)(hh < N ? hh : N);
-  }
-  h[t] = hi;
+  const int hi = obs_half_width(d, i, sig);
+  d.h[t] = hi;
   int64_t klo = -hi, khi = hi;
   if (i + klo < 0) klo = -i;
-  if (i + khi > N - 1) khi = N - 1 - i;
-  const float q = (float)(dnu * dnu * kLog2e / (2.0 * sig * sig));
-  const double s = sig / dnu;
+  if (i + khi > d.N - 1) khi = d.N - 1 - i;
+  const float q = (float)(d.dnu * d.dnu * kLog2e / (2.0 * sig * sig));
+  const double s = sig / d.dnu;
   double z;
   if (s >= 4.0) {
     z = gauss_sum_em(s, (double)klo, (double)khi);
@@ -1616,8 +1871,8 @@ __global__ __launch_bounds__(256) void k_obs_norm_f32(int64_t N, double nu_first
     }
     z = zf;
   }
-  q_out[t] = q;
-  invz_out[t] = (float)(1.0 / z);
+  ((float *)d.q)[t] = q;
+  ((float *)d.invz)[t] = (float)(1.0 / z);
 }
 
 // k_obs_weights: workgroup size and lanes per stored weight
@@ -1625,28 +1880,31 @@ constexpr int kObsWeightThreads = 256;
 constexpr int kObsLanes = 4;
 
 template <typename Real>
-__global__ __launch_bounds__(kObsWeightThreads) void k_obs_weights(int n_bins, int64_t nnz,
-                                                     const int64_t *edge_idx, const int32_t *h,
-                                                     int64_t i0, const Real *q, const Real *invz,
-                                                     double dnu, const int64_t *kstart,
-                                                     const int32_t *mlo, Real *K) {
+__global__ __launch_bounds__(kObsWeightThreads) void k_obs_weights(const ObsSeg *segs,
+                                                                   int n_segs, ObsSeg seg0) {
+  const ObsSeg d = obs_seg(segs, n_segs, seg0, true);
+  const double dnu = d.dnu;
+  const int32_t *h = d.h;
+  const Real *q = (const Real *)d.q, *invz = (const Real *)d.invz;
+  const int64_t i0 = d.i0, nnz = d.nnz;
   // four lanes per stored weight: find its bin, then each lane sums every
   // fourth of the bin's Gaussians that reach this point (in the order of i),
   // and a fixed two-step butterfly adds the four partial sums
-  const int64_t e_raw = (int64_t)blockIdx.x * (kObsWeightThreads / kObsLanes) +
+  const int64_t e_raw = ((int64_t)blockIdx.x - d.weight_wg_begin) *
+                            (kObsWeightThreads / kObsLanes) +
                         (threadIdx.x / kObsLanes);
   const int part = threadIdx.x % kObsLanes;
   const bool live = e_raw < nnz;
   const int64_t e = live ? e_raw : nnz - 1;   // spare lanes still join the butterfly
-  int lo = 0, hi = n_bins;   // largest j with kstart[j] <= e
+  int lo = 0, hi = d.n_bins;   // largest j with kstart[j] <= e
   while (hi - lo > 1) {
     const int mid = (lo + hi) >> 1;
-    if (kstart[mid] <= e) lo = mid;
+    if (d.kstart[mid] <= e) lo = mid;
     else hi = mid;
   }
   const int jb = lo;
-  const int64_t a = edge_idx[jb], b = edge_idx[jb + 1];
-  const int64_t x = mlo[jb] + (e - kstart[jb]);
+  const int64_t a = d.edge_idx[jb], b = d.edge_idx[jb + 1];
+  const int64_t x = d.mlo[jb] + (e - d.kstart[jb]);
   const int hmax = h[b - i0] > h[a - i0] ? h[b - i0] : h[a - i0];
   int64_t ia = x - hmax, ib = x + hmax;
   if (ia < a) ia = a;
@@ -1679,7 +1937,33 @@ __global__ __launch_bounds__(kObsWeightThreads) void k_obs_weights(int n_bins, i
 #pragma unroll
   for (int off = 1; off < kObsLanes; off <<= 1) acc += __shfl_xor(acc, off, 64);
   if (!live || part != 0) return;
-  K[e] = acc * (Real)(1.0 / (double)(b - a));
+  ((Real *)d.K)[e] = acc * (Real)(1.0 / (double)(b - a));
+}
+
+int64_t obs_norm_workgroups(bool fp64, int64_t n_pts) {
+  return fp64 ? (n_pts + 3) / 4 : (n_pts + 255) / 256;
+}
+
+int64_t obs_weight_workgroups(int64_t nnz) {
+  const int64_t per_wg = kObsWeightThreads / kObsLanes;
+  return (nnz + per_wg - 1) / per_wg;
+}
+
+static hipError_t obs_launches(bool fp64, const ObsSeg *segs, int n_segs, const ObsSeg &seg0,
+                               int64_t norm_wgs, int64_t weight_wgs, hipStream_t stream) {
+  if (norm_wgs <= 0 || weight_wgs <= 0) return hipSuccess;
+  if (fp64) {
+    hipLaunchKernelGGL(k_obs_norm_f64, dim3((unsigned)norm_wgs), dim3(256), 0, stream, segs,
+                       n_segs, seg0);
+    hipLaunchKernelGGL(k_obs_weights<double>, dim3((unsigned)weight_wgs),
+                       dim3(kObsWeightThreads), 0, stream, segs, n_segs, seg0);
+  } else {
+    hipLaunchKernelGGL(k_obs_norm_f32, dim3((unsigned)norm_wgs), dim3(256), 0, stream, segs,
+                       n_segs, seg0);
+    hipLaunchKernelGGL(k_obs_weights<float>, dim3((unsigned)weight_wgs),
+                       dim3(kObsWeightThreads), 0, stream, segs, n_segs, seg0);
+  }
+  return hipGetLastError();
 }
 
 hipError_t launch_obs_build(bool fp64, int64_t N, double nu_first, double dnu_eff, double denom,
@@ -1687,25 +1971,32 @@ hipError_t launch_obs_build(bool fp64, int64_t N, double nu_first, double dnu_ef
                             int64_t i0, int64_t n_pts, void *q_scratch, void *invz_scratch,
                             const int64_t *kstart_dev, const int32_t *mlo_dev, void *K_dev,
                             hipStream_t stream) {
-  const dim3 g1((unsigned)((n_pts + 3) / 4));
-  const int64_t per_wg = kObsWeightThreads / kObsLanes;
-  const dim3 g2((unsigned)((nnz + per_wg - 1) / per_wg));
-  if (fp64) {
-    hipLaunchKernelGGL(k_obs_norm_f64, g1, dim3(256), 0, stream, N, nu_first, dnu_eff, denom,
-                       h_dev, i0, n_pts, (double *)q_scratch, (double *)invz_scratch);
-    hipLaunchKernelGGL(k_obs_weights<double>, g2, dim3(kObsWeightThreads), 0, stream, n_bins, nnz,
-                       edge_idx_dev, h_dev, i0, (const double *)q_scratch,
-                       (const double *)invz_scratch, dnu_eff, kstart_dev, mlo_dev,
-                       (double *)K_dev);
-  } else {
-    hipLaunchKernelGGL(k_obs_norm_f32, dim3((unsigned)((n_pts + 255) / 256)), dim3(256), 0,
-                       stream, N, nu_first, dnu_eff, denom, h_dev, i0, n_pts, (float *)q_scratch,
-                       (float *)invz_scratch);
-    hipLaunchKernelGGL(k_obs_weights<float>, g2, dim3(kObsWeightThreads), 0, stream, n_bins, nnz, edge_idx_dev,
-                       h_dev, i0, (const float *)q_scratch, (const float *)invz_scratch, dnu_eff,
-                       kstart_dev, mlo_dev, (float *)K_dev);
-  }
-  return hipGetLastError();
+  ObsSeg d{};
+  d.norm_wg_begin = 0;
+  d.weight_wg_begin = 0;
+  d.N = N;
+  d.i0 = i0;
+  d.n_pts = n_pts;
+  d.nnz = nnz;
+  d.nu_first = nu_first;
+  d.dnu = dnu_eff;
+  d.denom = denom;
+  d.n_bins = n_bins;
+  d.edge_idx = edge_idx_dev;
+  d.kstart = kstart_dev;
+  d.mlo = mlo_dev;
+  d.h = h_dev;
+  d.q = q_scratch;
+  d.invz = invz_scratch;
+  d.K = K_dev;
+  return obs_launches(fp64, nullptr, 0, d, obs_norm_workgroups(fp64, n_pts),
+                      obs_weight_workgroups(nnz), stream);
+}
+
+hipError_t launch_obs_build_segs(bool fp64, const ObsSeg *segs_dev, int n_segs,
+                                 int64_t norm_wgs, int64_t weight_wgs, hipStream_t stream) {
+  const ObsSeg seg0{};
+  return obs_launches(fp64, segs_dev, n_segs, seg0, norm_wgs, weight_wgs, stream);
 }
 
 }  // namespace hr2

@@ -3,14 +3,15 @@
 // A scheduler thread owns two streams and a device arena of the server's
 // byte budget.  Requests are admitted first-in first-out while their
 // footprint fits the arena and a slot is free; each step launches the work
-// of every admitted, not yet launched request: per-request level records
-// and layout builds, then ONE column-kernel launch and ONE convolve/bin
-// launch over all of them (one segment per request), then the bins are
-// copied to pinned host memory.  Up to two steps are in flight, one per
-// stream, so a step admitted while another runs overlaps it on the device.
-// Per-set arithmetic does not depend on the other requests of a step (the
-// layer-chunk count is a function of the request alone), so a result is
-// bit-identical alone and in the mix.
+// of every admitted, not yet launched request as a handful of launches over
+// all of them (one segment per request): one upload of their columns and
+// bin plans, ONE level-record launch, ONE pair of layout-build launches, ONE
+// column-kernel launch per kernel variant, ONE convolve/bin launch, and one
+// download of all their bins to pinned host memory.  Up to two steps are in
+// flight, one per stream, so a step admitted while another runs overlaps it
+// on the device.  Per-set arithmetic does not depend on the other requests
+// of a step (the layer-chunk count is a function of the request alone), so
+// a result is bit-identical alone and in the mix.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -28,6 +29,7 @@
 
 #include "hr2_context.h"
 #include "hr2_internal.h"
+#include "serve_sched.h"
 
 using namespace hr2;
 
@@ -39,56 +41,6 @@ double now_s() {
   return (double)ts.tv_sec + 1e-9 * (double)ts.tv_nsec;
 }
 
-size_t round256(size_t n) { return (n + 255) & ~size_t(255); }
-
-// First-fit allocator over [0, cap) in 256-byte units.
-class Arena {
- public:
-  explicit Arena(size_t cap = 0) { reset(cap); }
-  void reset(size_t cap) {
-    free_.clear();
-    cap_ = cap;
-    used_ = 0;
-    if (cap) free_[0] = cap;
-  }
-  bool alloc(size_t n, size_t *off) {
-    n = round256(n);
-    for (auto it = free_.begin(); it != free_.end(); ++it) {
-      if (it->second < n) continue;
-      *off = it->first;
-      const size_t rest = it->second - n, start = it->first + n;
-      free_.erase(it);
-      if (rest) free_[start] = rest;
-      used_ += n;
-      return true;
-    }
-    return false;
-  }
-  void release(size_t off, size_t n) {
-    n = round256(n);
-    used_ -= n;
-    auto it = free_.emplace(off, n).first;
-    auto nx = std::next(it);
-    if (nx != free_.end() && it->first + it->second == nx->first) {
-      it->second += nx->second;
-      free_.erase(nx);
-    }
-    if (it != free_.begin()) {
-      auto pv = std::prev(it);
-      if (pv->first + pv->second == it->first) {
-        pv->second += it->second;
-        free_.erase(it);
-      }
-    }
-  }
-  size_t used() const { return used_; }
-  size_t cap() const { return cap_; }
-
- private:
-  std::map<size_t, size_t> free_;
-  size_t cap_ = 0, used_ = 0;
-};
-
 struct Req {
   uint64_t ticket = 0;
   hr2_request_info info{};
@@ -96,21 +48,24 @@ struct Req {
   int n_bins = 0, n_sets = 0, L = 0, n_mu = 0, chunks = 1;
   std::vector<double> cols;   // packed p, T, x, log g, scale
   ObsPlan plan;
-  // byte offsets inside the request's device block; [0, upload) is copied
-  // from the pinned image at launch
-  size_t o_cols = 0, o_kstart = 0, o_mlo = 0, o_mlen = 0, o_edges = 0, o_h = 0, upload = 0;
-  size_t o_recs = 0, o_fplus = 0, o_bins = 0, o_K = 0, o_q = 0, o_z = 0, bytes = 0;
-  size_t bins_bytes = 0, pin_bytes = 0;
-  size_t dev_off = 0, pin_off = 0;
+  // byte offsets inside the request's device block (arena)
+  size_t o_h = 0, o_recs = 0, o_fplus = 0, o_K = 0, o_q = 0, o_z = 0, bytes = 0;
+  size_t bins_bytes = 0;
+  // byte offsets inside the stage of the step that launches the request
+  size_t st_cols = 0, st_kstart = 0, st_mlo = 0, st_mlen = 0, st_edges = 0, st_bins = 0;
+  size_t dev_off = 0;
   bool admitted = false;
   std::vector<unsigned char> result;
 };
 
+// One of the two step streams with its stage: descriptors and the inputs of
+// the step's requests (uploaded at once), then their bins (downloaded at
+// once), in device memory and in a pinned host image of the same layout.
 struct StepSlot {
   hipStream_t stream = nullptr;
   hipEvent_t done = nullptr;
-  DevBuf desc;                 // ColSeg[] then ConvSeg[]
-  void *pinned = nullptr;      // host image of the descriptors
+  DevBuf stage;
+  void *pinned = nullptr;
   size_t pinned_cap = 0;
   std::vector<Req *> reqs;
   bool busy = false;
@@ -125,9 +80,7 @@ struct hr2_server {
   size_t budget = 0;
   int max_slots = 1;
   void *arena_dev = nullptr;
-  void *arena_pin = nullptr;
-  size_t pin_cap = 0;
-  Arena dev, pin;
+  Arena dev;
   StepSlot slots[2];
   uint64_t step_seq = 0;
 
@@ -161,6 +114,8 @@ size_t rec_bytes(const hr2_tables *t) {
   return t->view.dtype == HR2_TABLE_F64 ? sizeof(LevelRecD) : sizeof(LevelRecF);
 }
 
+// The request's device block: half widths, level records, F+, layout
+// weights and the layout build's scratch.
 void layout_request(const hr2_tables *t, Req &r) {
   const size_t rs = real_bytes(t);
   size_t o = 0;
@@ -169,33 +124,14 @@ void layout_request(const hr2_tables *t, Req &r) {
     o += round256(std::max<size_t>(n, 1));
     return at;
   };
-  const int S = t->view.S;
-  r.o_cols = take(r.cols.size() * sizeof(double));
-  r.o_kstart = take(r.n_bins * sizeof(int64_t));
-  r.o_mlo = take(r.n_bins * sizeof(int32_t));
-  r.o_mlen = take(r.n_bins * sizeof(int32_t));
-  r.o_edges = take((r.n_bins + 1) * sizeof(int64_t));
-  r.upload = o;
   r.o_h = take(r.plan.n_pts * sizeof(int32_t));   // written by the layout build
   r.o_recs = take((size_t)r.n_sets * r.L * rec_bytes(t));
   r.o_fplus = take((size_t)r.n_sets * r.window.nu_count * rs);
-  r.bins_bytes = (size_t)r.n_sets * r.n_bins * rs;
-  r.o_bins = take(r.bins_bytes);
   r.o_K = take((size_t)r.plan.nnz * rs);
   r.o_q = take((size_t)r.plan.n_pts * rs);
   r.o_z = take((size_t)r.plan.n_pts * rs);
   r.bytes = o;
-  r.pin_bytes = round256(r.upload) + round256(r.bins_bytes);
-  (void)S;
-}
-
-void fill_upload_image(const Req &r, unsigned char *img) {
-  std::memset(img, 0, r.upload);
-  std::memcpy(img + r.o_cols, r.cols.data(), r.cols.size() * sizeof(double));
-  std::memcpy(img + r.o_kstart, r.plan.kstart.data(), r.n_bins * sizeof(int64_t));
-  std::memcpy(img + r.o_mlo, r.plan.mlo.data(), r.n_bins * sizeof(int32_t));
-  std::memcpy(img + r.o_mlen, r.plan.mlen.data(), r.n_bins * sizeof(int32_t));
-  std::memcpy(img + r.o_edges, r.plan.idx.data(), (r.n_bins + 1) * sizeof(int64_t));
+  r.bins_bytes = (size_t)r.n_sets * r.n_bins * rs;
 }
 
 }  // namespace
@@ -204,7 +140,6 @@ void fill_upload_image(const Req &r, unsigned char *img) {
 void hr2_server::release(Req *r) {
   if (r->admitted) {
     dev.release(r->dev_off, r->bytes);
-    pin.release(r->pin_off, r->pin_bytes);
     r->admitted = false;
     --n_admitted;
   }
@@ -216,7 +151,6 @@ bool hr2_server::launch_step(StepSlot &sl, std::vector<Req *> &reqs) {
   const size_t rs = real_bytes(tables), rb = rec_bytes(tables);
   hipStream_t s = sl.stream;
   unsigned char *base = (unsigned char *)arena_dev;
-  unsigned char *pbase = (unsigned char *)arena_pin;
   if (hipSetDevice(ctx->device) != hipSuccess) return false;
   // column launches group the requests by chunk count (= workgroup size)
   // and by angle class (kernel variant), so each request runs exactly the
@@ -226,33 +160,91 @@ bool hr2_server::launch_step(StepSlot &sl, std::vector<Req *> &reqs) {
     const int kb = b->chunks * 16 + column_mu_class(b->n_mu);
     return ka < kb;
   });
-  std::vector<ColSeg> cs(reqs.size());
-  std::vector<ConvSeg> vs(reqs.size());
+  const size_t n = reqs.size();
+  // stage layout: descriptors, then each request's inputs, then the bins
+  size_t o = 0;
+  auto take = [&o](size_t bytes) {
+    const size_t at = o;
+    o += round256(std::max<size_t>(bytes, 1));
+    return at;
+  };
+  const size_t o_lv = take(n * sizeof(LevelSeg)), o_ob = take(n * sizeof(ObsSeg));
+  const size_t o_cs = take(n * sizeof(ColSeg)), o_vs = take(n * sizeof(ConvSeg));
+  for (Req *r : reqs) {
+    r->st_cols = take(r->cols.size() * sizeof(double));
+    r->st_kstart = take(r->n_bins * sizeof(int64_t));
+    r->st_mlo = take(r->n_bins * sizeof(int32_t));
+    r->st_mlen = take(r->n_bins * sizeof(int32_t));
+    r->st_edges = take((r->n_bins + 1) * sizeof(int64_t));
+  }
+  const size_t o_bins = o;
+  for (Req *r : reqs) r->st_bins = take(r->bins_bytes);
+  const size_t total = o;
+  // this slot's previous step has completed, so nothing reads its old stage
+  sl.stage.free_retired();
+  if (sl.stage.ensure(total) != HR2_OK) return false;
+  if (sl.pinned_cap < total) {
+    if (sl.pinned) (void)hipHostFree(sl.pinned);
+    sl.pinned = nullptr;
+    sl.pinned_cap = 0;
+    if (hipHostMalloc(&sl.pinned, total, hipHostMallocDefault) != hipSuccess) return false;
+    sl.pinned_cap = total;
+  }
+  unsigned char *img = (unsigned char *)sl.pinned;
+  unsigned char *dst = (unsigned char *)sl.stage.ptr;
+  LevelSeg *lv = (LevelSeg *)(img + o_lv);
+  ObsSeg *ob = (ObsSeg *)(img + o_ob);
+  ColSeg *cs = (ColSeg *)(img + o_cs);
+  ConvSeg *vs = (ConvSeg *)(img + o_vs);
   struct Group {
     size_t first, count;
     int64_t wgs;
     int chunks, max_mu;
   };
   std::vector<Group> groups;
-  int64_t wg = 0, conv_wgs = 0;
-  for (size_t i = 0; i < reqs.size(); ++i) {
+  int64_t wg = 0, conv_wgs = 0, lev_wgs = 0, norm_wgs = 0, weight_wgs = 0;
+  for (size_t i = 0; i < n; ++i) {
     Req &r = *reqs[i];
+    std::memcpy(img + r.st_cols, r.cols.data(), r.cols.size() * sizeof(double));
+    std::memcpy(img + r.st_kstart, r.plan.kstart.data(), r.n_bins * sizeof(int64_t));
+    std::memcpy(img + r.st_mlo, r.plan.mlo.data(), r.n_bins * sizeof(int32_t));
+    std::memcpy(img + r.st_mlen, r.plan.mlen.data(), r.n_bins * sizeof(int32_t));
+    std::memcpy(img + r.st_edges, r.plan.idx.data(), (r.n_bins + 1) * sizeof(int64_t));
+    unsigned char *blk = base + r.dev_off;
+    const ColumnsView cv = columns_view(dst + r.st_cols, r.n_sets, r.L, tv.S);
+    LevelSeg &l = lv[i];
+    std::memset(&l, 0, sizeof(l));
+    l.wg_begin = lev_wgs;
+    l.rec_offset = (int64_t)((r.dev_off + r.o_recs) / rb);
+    l.cv = cv;
+    l.blocks_per_set = level_blocks_per_set(tv, r.L);
+    lev_wgs += (int64_t)r.n_sets * l.blocks_per_set;
+    ObsSeg &b = ob[i];
+    std::memset(&b, 0, sizeof(b));
+    b.norm_wg_begin = norm_wgs;
+    b.weight_wg_begin = weight_wgs;
+    b.N = r.plan.N;
+    b.i0 = r.plan.i0;
+    b.n_pts = r.plan.n_pts;
+    b.nnz = r.plan.nnz;
+    b.nu_first = r.plan.first;
+    b.dnu = r.plan.dnu;
+    b.denom = r.plan.denom;
+    b.n_bins = r.n_bins;
+    b.edge_idx = (const int64_t *)(dst + r.st_edges);
+    b.kstart = (const int64_t *)(dst + r.st_kstart);
+    b.mlo = (const int32_t *)(dst + r.st_mlo);
+    b.h = (int32_t *)(blk + r.o_h);
+    b.q = blk + r.o_q;
+    b.invz = blk + r.o_z;
+    b.K = blk + r.o_K;
+    norm_wgs += obs_norm_workgroups(fp64, r.plan.n_pts);
+    weight_wgs += obs_weight_workgroups(r.plan.nnz);
     const int mu_class = column_mu_class(r.n_mu);
     if (groups.empty() || groups.back().chunks != r.chunks || groups.back().max_mu != mu_class) {
       groups.push_back(Group{i, 0, 0, r.chunks, mu_class});
       wg = 0;
     }
-    unsigned char *blk = base + r.dev_off;
-    if (hipMemcpyAsync(blk, pbase + r.pin_off, r.upload, hipMemcpyHostToDevice, s) != hipSuccess)
-      return false;
-    const ColumnsView cv = columns_view(blk + r.o_cols, r.n_sets, r.L, tv.S);
-    if (launch_levels(tv, cv, blk + r.o_recs, nullptr, fp64, s) != hipSuccess) return false;
-    if (launch_obs_build(fp64, r.plan.N, r.plan.first, r.plan.dnu, r.plan.denom, r.n_bins,
-                         r.plan.nnz, (const int64_t *)(blk + r.o_edges),
-                         (int32_t *)(blk + r.o_h), r.plan.i0, r.plan.n_pts, blk + r.o_q,
-                         blk + r.o_z, (const int64_t *)(blk + r.o_kstart),
-                         (const int32_t *)(blk + r.o_mlo), blk + r.o_K, s) != hipSuccess)
-      return false;
     ColSeg &c = cs[i];
     std::memset(&c, 0, sizeof(c));
     const int per_wg = column_nu_per_wg(r.chunks);
@@ -260,7 +252,7 @@ bool hr2_server::launch_step(StepSlot &sl, std::vector<Req *> &reqs) {
     c.nu_begin = r.window.nu_begin;
     c.nu_count = r.window.nu_count;
     c.nu_stride = r.window.nu_stride;
-    c.rec_offset = (int64_t)((r.dev_off + r.o_recs) / rb);
+    c.rec_offset = l.rec_offset;
     c.out_offset = (int64_t)((r.dev_off + r.o_fplus) / rs);
     c.out_stride = r.window.nu_count;
     c.n_sets = r.n_sets;
@@ -271,51 +263,44 @@ bool hr2_server::launch_step(StepSlot &sl, std::vector<Req *> &reqs) {
     wg += (int64_t)r.n_sets * c.tiles_per_set;
     groups.back().count += 1;
     groups.back().wgs = wg;
-    if (wg > 0x7fffffff) return false;
+    if (wg > 0x7fffffff || lev_wgs > 0x7fffffff || norm_wgs > 0x7fffffff ||
+        weight_wgs > 0x7fffffff)
+      return false;
     ConvSeg &v = vs[i];
     std::memset(&v, 0, sizeof(v));
     v.item_begin = conv_wgs;
     v.K = blk + r.o_K;
-    v.kstart = (const int64_t *)(blk + r.o_kstart);
-    v.mlo = (const int32_t *)(blk + r.o_mlo);
-    v.mlen = (const int32_t *)(blk + r.o_mlen);
+    v.kstart = b.kstart;
+    v.mlo = b.mlo;
+    v.mlen = (const int32_t *)(dst + r.st_mlen);
     v.in_offset = c.out_offset;
     v.in_stride = r.window.nu_count;
-    v.out_offset = (int64_t)((r.dev_off + r.o_bins) / rs);
+    v.out_offset = (int64_t)(r.st_bins / rs);
     v.scale = cv.scale;
     v.n_sets = r.n_sets;
     v.n_bins = r.n_bins;
     v.items_per_wg = conv_items_per_wg(r.plan.nnz, r.n_bins);
     conv_wgs += conv_workgroups((int64_t)r.n_sets * r.n_bins, v.items_per_wg);
   }
-  const size_t bytes_c = cs.size() * sizeof(ColSeg), bytes_v = vs.size() * sizeof(ConvSeg);
-  const size_t total = round256(bytes_c) + bytes_v;
-  // this slot's previous step has completed, so nothing reads its old
-  // descriptor buffers any more
-  sl.desc.free_retired();
-  if (sl.desc.ensure(total) != HR2_OK) return false;
-  if (sl.pinned_cap < total) {
-    if (sl.pinned) (void)hipHostFree(sl.pinned);
-    sl.pinned = nullptr;
-    if (hipHostMalloc(&sl.pinned, total, hipHostMallocDefault) != hipSuccess) return false;
-    sl.pinned_cap = total;
-  }
-  std::memcpy(sl.pinned, cs.data(), bytes_c);
-  std::memcpy((unsigned char *)sl.pinned + round256(bytes_c), vs.data(), bytes_v);
-  if (hipMemcpyAsync(sl.desc.ptr, sl.pinned, total, hipMemcpyHostToDevice, s) != hipSuccess)
+  if (conv_wgs > 0x7fffffff) return false;
+  if (hipMemcpyAsync(dst, img, o_bins, hipMemcpyHostToDevice, s) != hipSuccess) return false;
+  if (launch_levels_segs(tv, (const LevelSeg *)(dst + o_lv), (int)n, lev_wgs, base, fp64, s) !=
+      hipSuccess)
     return false;
-  const ColSeg *dcs = (const ColSeg *)sl.desc.ptr;
-  const ConvSeg *dvs = (const ConvSeg *)((unsigned char *)sl.desc.ptr + round256(bytes_c));
+  if (launch_obs_build_segs(fp64, (const ObsSeg *)(dst + o_ob), (int)n, norm_wgs, weight_wgs,
+                            s) != hipSuccess)
+    return false;
+  const ColSeg *dcs = (const ColSeg *)(dst + o_cs);
   for (const Group &gq : groups)
     if (launch_column(tv, dcs + gq.first, (int)gq.count, nullptr, gq.wgs, gq.chunks, base,
                       nullptr, base, gq.max_mu, false, para, false, s) != hipSuccess)
       return false;
-  if (launch_convolve_bin(fp64, dvs, (int)vs.size(), nullptr, conv_wgs, base, base, s) != hipSuccess)
+  if (launch_convolve_bin(fp64, (const ConvSeg *)(dst + o_vs), (int)n, nullptr, conv_wgs, base,
+                          dst, s) != hipSuccess)
     return false;
-  for (Req *r : reqs)
-    if (hipMemcpyAsync(pbase + r->pin_off + round256(r->upload), base + r->dev_off + r->o_bins,
-                       r->bins_bytes, hipMemcpyDeviceToHost, s) != hipSuccess)
-      return false;
+  if (hipMemcpyAsync(img + o_bins, dst + o_bins, total - o_bins, hipMemcpyDeviceToHost, s) !=
+      hipSuccess)
+    return false;
   return hipEventRecord(sl.done, s) == hipSuccess;
 }
 
@@ -325,7 +310,7 @@ void hr2_server::finish_step(StepSlot &sl) {
   const double t = now_s();
   for (Req *r : sl.reqs) {
     if (e == hipSuccess) {
-      const unsigned char *src = (const unsigned char *)arena_pin + r->pin_off + round256(r->upload);
+      const unsigned char *src = (const unsigned char *)sl.pinned + r->st_bins;
       r->result.assign(src, src + r->bins_bytes);
       r->info.state = HR2_REQ_DONE;
       r->info.error = HR2_OK;
@@ -377,26 +362,18 @@ void hr2_server::run() {
       if (!any) break;
     }
     // admit first-in first-out while memory and slots allow
-    while (!stop && !pending.empty() && n_admitted < max_slots) {
-      Req *r = pending.front();
-      size_t doff, poff;
-      if (!dev.alloc(r->bytes, &doff)) break;
-      if (!pin.alloc(r->pin_bytes, &poff)) {
-        dev.release(doff, r->bytes);
-        break;
-      }
-      r->dev_off = doff;
-      r->pin_off = poff;
-      r->admitted = true;
-      ++n_admitted;
-      stats.peak_bytes = std::max(stats.peak_bytes, dev.used());
-      stats.max_inflight = std::max<uint64_t>(stats.max_inflight, (uint64_t)n_admitted);
-      r->info.t_admit = now_s();
-      r->info.state = HR2_REQ_RUNNING;
-      fill_upload_image(*r, (unsigned char *)arena_pin + poff);
-      pending.pop_front();
-      admitted.push_back(r);
-    }
+    if (!stop)
+      admit_fifo(
+          pending, dev, max_slots, n_admitted, [](const Req *r) { return r->bytes; },
+          [this](Req *r, size_t off) {
+            r->dev_off = off;
+            r->admitted = true;
+            stats.peak_bytes = std::max(stats.peak_bytes, dev.used());
+            stats.max_inflight = std::max<uint64_t>(stats.max_inflight, (uint64_t)n_admitted);
+            r->info.t_admit = now_s();
+            r->info.state = HR2_REQ_RUNNING;
+            admitted.push_back(r);
+          });
     // launch a step on a free slot
     StepSlot *free_slot = nullptr;
     for (auto &sl : slots)
@@ -486,10 +463,7 @@ extern "C" hr2_status hr2_serve_create(hr2_ctx *ctx, const hr2_tables *t, size_t
   srv->tables = t;
   srv->budget = round256(budget);
   srv->max_slots = max_slots;
-  // pinned staging: inputs and results of the admitted requests
-  srv->pin_cap = std::min<size_t>(std::max<size_t>(srv->budget / 4, size_t(1) << 20), size_t(1) << 30);
   hipError_t e = hipMalloc(&srv->arena_dev, srv->budget);
-  if (e == hipSuccess) e = hipHostMalloc(&srv->arena_pin, srv->pin_cap, hipHostMallocDefault);
   for (auto &sl : srv->slots) {
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&sl.done, hipEventDisableTiming);
@@ -497,7 +471,6 @@ extern "C" hr2_status hr2_serve_create(hr2_ctx *ctx, const hr2_tables *t, size_t
   if (e != hipSuccess) {
     (void)hipGetLastError();
     if (srv->arena_dev) (void)hipFree(srv->arena_dev);
-    if (srv->arena_pin) (void)hipHostFree(srv->arena_pin);
     for (auto &sl : srv->slots) {
       if (sl.stream) (void)hipStreamDestroy(sl.stream);
       if (sl.done) (void)hipEventDestroy(sl.done);
@@ -507,7 +480,6 @@ extern "C" hr2_status hr2_serve_create(hr2_ctx *ctx, const hr2_tables *t, size_t
                      std::string("server setup: ") + hipGetErrorString(e));
   }
   srv->dev.reset(srv->budget);
-  srv->pin.reset(srv->pin_cap);
   srv->thr = std::thread([srv] { srv->run(); });
   *out = srv;
   return HR2_OK;
@@ -541,8 +513,6 @@ extern "C" hr2_status hr2_serve_submit(hr2_server *srv, const hr2_request *q, ui
   if (r->bytes > srv->budget)
     return set_error(HR2_E_NO_MEMORY, "request needs " + std::to_string(r->bytes) +
                                           " device bytes, budget is " + std::to_string(srv->budget));
-  if (r->pin_bytes > srv->pin_cap)
-    return set_error(HR2_E_NO_MEMORY, "request exceeds the pinned staging of the server");
   r->info.state = HR2_REQ_PENDING;
   r->info.t_submit = now_s();
   r->info.n_bins = r->n_bins;
@@ -674,10 +644,9 @@ extern "C" void hr2_serve_destroy(hr2_server *srv) {
       (void)hipStreamDestroy(sl.stream);
     }
     if (sl.done) (void)hipEventDestroy(sl.done);
-    sl.desc.release();
+    sl.stage.release();
     if (sl.pinned) (void)hipHostFree(sl.pinned);
   }
   if (srv->arena_dev) (void)hipFree(srv->arena_dev);
-  if (srv->arena_pin) (void)hipHostFree(srv->arena_pin);
   delete srv;
 }

@@ -15,7 +15,8 @@ from typing import Optional, Sequence
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libhr2.so")
+# HR2_LIB_PATH: another build of the library (the sanitizer test's host-only one)
+LIB_PATH = os.environ.get("HR2_LIB_PATH", os.path.join(HERE, "libhr2.so"))
 
 OK, NOT_READY = 0, 1
 E_INVALID_ARG, E_OUT_OF_RANGE, E_NO_MEMORY, E_DEVICE = -1, -2, -3, -4
@@ -24,8 +25,9 @@ STATUS_NAMES = {0: "HR2_OK", 1: "HR2_NOT_READY", -1: "HR2_E_INVALID_ARG",
                 -2: "HR2_E_OUT_OF_RANGE", -3: "HR2_E_NO_MEMORY", -4: "HR2_E_DEVICE",
                 -5: "HR2_E_NOT_FOUND", -6: "HR2_E_UNSUPPORTED", -7: "HR2_E_CANCELLED"}
 DTYPES = {"f32": 0, "f16": 1, "bf16": 2, "f64": 3}
+OFFSET_MODES = {"row": 0, "species": 1}
 REQ_PENDING, REQ_RUNNING, REQ_DONE, REQ_ERROR, REQ_CANCELLED = range(5)
-OPT_CHUNKS, OPT_NU_PER_LANE, OPT_TIMING, OPT_SOURCE, OPT_ROW_POLICY = 0, 1, 2, 3, 4
+OPT_CHUNKS, OPT_NU_PER_LANE, OPT_TIMING, OPT_SOURCE, OPT_ROW_POLICY = range(5)
 
 _DP = POINTER(c_double)
 
@@ -40,7 +42,8 @@ class TablesDesc(ctypes.Structure):
     _fields_ = [("n_species", c_int), ("n_T", c_int), ("n_p", c_int),
                 ("T_K", _DP), ("log10_p_bar", _DP), ("nu0_cm", c_double), ("dnu_cm", c_double),
                 ("n_nu", c_int64), ("log10_sigma", _DP), ("molar_mass", _DP), ("n_cia", c_int),
-                ("log10_k_cia", _DP), ("he_h2_ratio", c_double), ("dtype", c_int)]
+                ("log10_k_cia", _DP), ("he_h2_ratio", c_double), ("dtype", c_int),
+                ("offset_mode", c_int)]
 
 
 class ColumnC(ctypes.Structure):
@@ -240,7 +243,8 @@ class Context:
 class Tables:
     """Resident cross-section + CIA tables (duck-typed source table)."""
 
-    def __init__(self, ctx: Context, table, dtype: str = "f32"):
+    def __init__(self, ctx: Context, table, dtype: str = "f32", offset: str = "row"):
+        """offset: 'row' (one log2 offset per table row) or 'species'."""
         self.ctx = ctx
         self.dtype_name = dtype
         sig = _f64(table.log10_sigma)
@@ -250,7 +254,7 @@ class Tables:
         d = TablesDesc(S, nT, nP, _ptr(Tax), _ptr(lp), float(table.nu0_cm), float(table.dnu_cm),
                        n_nu, _ptr(sig), _ptr(mass), 0 if cia is None else cia.shape[0],
                        _ptr(cia) if cia is not None else None, float(table.he_h2_ratio),
-                       DTYPES[dtype])
+                       DTYPES[dtype], OFFSET_MODES[offset])
         h = c_void_p()
         _check(load().hr2_tables_create(ctx.handle, ctypes.byref(d), ctypes.byref(h)))
         self.handle = h

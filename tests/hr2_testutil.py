@@ -21,14 +21,19 @@ def max_rel_err(got, ref, floor_frac=1e-30):
     return float(np.max(np.abs(got - ref) / den)), int(np.sum(np.abs(ref) < floor))
 
 
-def dequantised(table: wl.Table, dtype: str) -> wl.Table:
-    """The table as libhr2 stores it (include/hr2.h, hr2_tables_desc.dtype):
-    per row y = log10(sigma) log2(10) - off, off = (min + max)/2 of the row,
-    rounded to the storage type, returned in log10 units for the oracle."""
+def dequantised(table: wl.Table, dtype: str, offset: str = "row") -> wl.Table:
+    """The table as libhr2 stores it (include/hr2.h, hr2_tables_desc.dtype and
+    offset_mode): per row y = log10(sigma) log2(10) - off, off = (min + max)/2
+    of the row ('row') or of the whole species ('species'), rounded to the
+    storage type, returned in log10 units for the oracle.  CIA rows keep
+    per-row offsets in either mode."""
 
     def conv(a):
         y = a * LOG2_10
-        off = 0.5 * (y.min(axis=-1, keepdims=True) + y.max(axis=-1, keepdims=True))
+        if offset == "species":
+            off = 0.5 * (y.min(axis=(1, 2, 3), keepdims=True) + y.max(axis=(1, 2, 3), keepdims=True))
+        else:
+            off = 0.5 * (y.min(axis=-1, keepdims=True) + y.max(axis=-1, keepdims=True))
         q = y - off
         if dtype == "f16":
             q = q.astype(np.float16).astype(np.float64)

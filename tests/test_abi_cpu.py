@@ -128,6 +128,11 @@ def test_table_blocks_past_4_gib_are_refused_before_any_device_work():
     d = _desc(256, 2, n_nu, "f32", 0, keep)
     assert lib.hr2_tables_create(fake_ctx, ctypes.byref(d), ctypes.byref(out)) == hr2.E_OUT_OF_RANGE
     assert "species block" in hr2.last_error()
+    # an unknown offset mode is refused before anything else
+    d = _desc(4, 2, 64, "f16", 0, keep)
+    d.offset_mode = 2
+    assert lib.hr2_tables_create(fake_ctx, ctypes.byref(d), ctypes.byref(out)) == hr2.E_INVALID_ARG
+    assert "offset_mode" in hr2.last_error()
 
 
 def test_binding_fails_loudly_without_the_library(monkeypatch, tmp_path):
@@ -142,6 +147,7 @@ def test_struct_layouts_match_the_header():
     assert ctypes.sizeof(hr2.WindowC) == 24
     assert ctypes.sizeof(hr2.ColumnC) == 72
     assert ctypes.sizeof(hr2.TablesDesc) == 104
+    assert hr2.TablesDesc.offset_mode.offset == 100
     assert ctypes.sizeof(hr2.ServeStats) == 48
     assert ctypes.sizeof(hr2.ParamLayoutC) == 72
 

@@ -42,8 +42,8 @@ def c2():
 
 
 @functools.lru_cache(maxsize=None)
-def _dequantised(dtype):
-    return tu.dequantised(tu.c2_table(), dtype)
+def _dequantised(dtype, offset="row"):
+    return tu.dequantised(tu.c2_table(), dtype, offset)
 
 
 @functools.lru_cache(maxsize=None)
@@ -153,3 +153,33 @@ def test_c4_batch_of_64_every_set_and_bin(ctx, c2, dtype):
     assert worst[2] <= (1e-5 if dtype == "f32" else 1e-3)
     obs.close()
     T.close()
+
+
+@pytest.mark.parametrize("dtype", ["f16", "bf16"])
+def test_c4_species_offset_ablation(ctx, c2, dtype):
+    """The coarser quantisation rule (one log2 offset per species instead of
+    per row; hr2_tables_desc.offset_mode): the arithmetic still matches the
+    oracle on that rule's dequantised table (1e-5 on every point and bin); the
+    bins' error against the FP64 source is printed beside the per-row rule's."""
+    spec = wl.c2_obs(c2)
+    col = wl.c2_column()
+    src = oracle.forward(c2, col, spec.window, spec.resolving_power, spec.edges_cm, 3)
+    errs = {}
+    for offset in ("row", "species"):
+        T = hr2.Tables(ctx, c2, dtype, offset)
+        obs = hr2.Obs(ctx, T, spec.window, spec.resolving_power, spec.edges_cm)
+        bins, fplus = _bench_launch(ctx, T, obs, [col])
+        deq = oracle.forward(_dequantised(dtype, offset), col, spec.window, spec.resolving_power,
+                             spec.edges_cm, 3)
+        e_fd, _ = tu.max_rel_err(fplus[0], deq["fplus"])
+        e_bd, _ = tu.max_rel_err(bins[0], deq["bins"])
+        e_fs, _ = tu.max_rel_err(fplus[0], src["fplus"])
+        e_bs, _ = tu.max_rel_err(bins[0], src["bins"])
+        errs[offset] = (e_bs, e_fs)
+        say(f"  C2 {dtype}, offset per {offset}: vs dequantised F+ {e_fd:.2e} bins {e_bd:.2e}; "
+            f"vs FP64 source F+ {e_fs:.2e} bins {e_bs:.2e}")
+        assert e_fd <= 1e-5 and e_bd <= 1e-5
+        obs.close()
+        T.close()
+    say(f"  {dtype}: bins vs source, per species / per row: "
+        f"{errs['species'][0] / errs['row'][0]:.1f}x")

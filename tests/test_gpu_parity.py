@@ -504,3 +504,62 @@ def test_c3_graph_replay(ctx):
         del junk
     del g
     torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f16", "bf16"])
+def test_whole_forward_per_set(ctx, dtype):
+    """Small windows in batches that fill the device run the whole forward
+    model in one launch, one workgroup per set (levels and F+ in LDS).  It
+    must agree with the three-kernel path (forced by a fixed chunk count) to
+    FP32 rounding, with the oracle at every tested set, for both angle tiers
+    and with an invalid set in the batch."""
+    tab = tu.small_multi_table()
+    T = hr2.Tables(ctx, tab, dtype)
+    ref_tab = tab if dtype == "f32" else tu.dequantised(tab, dtype)
+    w = wl.Window(100, 2000, 1)
+    nu_first, dnu = oracle.window_grid(tab, w)
+    edges = wl.snapped_edges(tab, w, wl.log_edges(nu_first + 100 * dnu, nu_first + 1900 * dnu, 30))
+    obs = hr2.Obs(ctx, T, w, 2000.0, edges)
+    B = 300   # 300 sets x 32 tiles: more waves than the device holds at once
+    cols = tu.small_columns(tab, B, seed=77, n_levels=41)
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+    p = dev(np.stack([c.p_bar for c in cols]))
+    Tk = dev(np.stack([c.T_K for c in cols]))
+    x = dev(np.stack([c.x for c in cols]))
+    lg = dev([c.log_g for c in cols])
+    sc = dev([c.scale for c in cols])
+    bins = torch.empty(B * obs.n_bins, dtype=torch.float32, device="cuda")
+    fplus = torch.empty(B * w.count, dtype=torch.float32, device="cuda")
+    status = torch.full((B,), 7, dtype=torch.int32, device="cuda")
+    for n_mu in (3, 5):
+        out = {}
+        for chunks in (0, 1):
+            ctx.set_option(hr2.OPT_CHUNKS, chunks)
+            hr2.forward_batch_dev(ctx, T, obs, p, Tk, x, lg, sc, n_mu, bins, fplus, status)
+            torch.cuda.synchronize()
+            assert int(status.abs().sum()) == 0
+            out[chunks] = (bins.cpu().numpy().reshape(B, -1).astype(np.float64),
+                           fplus.cpu().numpy().reshape(B, -1).astype(np.float64))
+        ctx.set_option(hr2.OPT_CHUNKS, 0)
+        d_b = np.max(np.abs(out[0][0] - out[1][0]) / np.abs(out[1][0]))
+        d_f = np.max(np.abs(out[0][1] - out[1][1]) / np.abs(out[1][1]))
+        say(f"per-set launch {dtype} n_mu={n_mu}: vs three kernels bins {d_b:.1e}, F+ {d_f:.1e}")
+        assert d_b <= 1e-6 and d_f <= 1e-6
+        for s in (0, 150, B - 1):
+            ref = oracle.forward(ref_tab, cols[s], w, 2000.0, edges, n_mu)
+            e_f, _ = tu.max_rel_err(out[0][1][s], ref["fplus"])
+            e_b, _ = tu.max_rel_err(out[0][0][s], ref["bins"])
+            say(f"  set {s}: F+ {e_f:.2e} bins {e_b:.2e}")
+            assert e_f <= 1e-5 and e_b <= 1e-5
+    say("one invalid set in the batch")
+    Tbad = Tk.clone()
+    Tbad[7, 3] = -10.0
+    hr2.forward_batch_dev(ctx, T, obs, p, Tbad, x, lg, sc, 5, bins, fplus, status)
+    torch.cuda.synchronize()
+    got = bins.cpu().numpy().reshape(B, -1).astype(np.float64)
+    st = status.cpu().numpy()
+    assert st[7] == hr2.E_INVALID_ARG and np.all(np.delete(st, 7) == 0)
+    assert np.all(np.isnan(got[7]))
+    assert np.array_equal(np.delete(got, 7, axis=0), np.delete(out[0][0], 7, axis=0))
+    obs.close()
+    T.close()
