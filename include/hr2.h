@@ -142,7 +142,11 @@ const char *hr2_last_error(void);
  * accuracy at sharp optical-depth contrasts (an opaque cloud top). */
 typedef enum {
   HR2_OPT_CHUNKS = 0,      /* layer chunks per wavenumber tile: 0 = auto, 1 .. 8 */
-  HR2_OPT_NU_PER_LANE = 1, /* wavenumbers per lane: 0 = auto, 1 (only 1 is built) */
+  HR2_OPT_NU_PER_LANE = 1, /* wavenumbers per lane of the one-launch-per-set path
+                              (one-species tables, windows of at most 4096 points,
+                              batches that fill the device): 0 = auto (2), 1 or 2;
+                              the column kernel keeps 1 (2 costs it half its
+                              resident waves)                                        */
   HR2_OPT_TIMING = 2,      /* n > 0: bracket the kernels of every n-th forward-batch
                               call with HIP events (0 = off)                        */
   HR2_OPT_SOURCE = 3,      /* 1 = linear source (default), 2 = parabolic; servers

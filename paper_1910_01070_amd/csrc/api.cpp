@@ -259,8 +259,9 @@ extern "C" hr2_status hr2_ctx_set_option(hr2_ctx *ctx, hr2_option opt, int value
       ctx->opt_chunks = value;
       return HR2_OK;
     case HR2_OPT_NU_PER_LANE:
-      if (value != 0 && value != 1)
-        return set_error(HR2_E_UNSUPPORTED, "only one wavenumber per lane is built");
+      if (value < 0 || value > 2)
+        return set_error(HR2_E_UNSUPPORTED, "wavenumbers per lane must be 0 (auto), 1 or 2");
+      ctx->opt_nu_per_lane = value;
       return HR2_OK;
     case HR2_OPT_TIMING:
       if (value < 0) return set_error(HR2_E_INVALID_ARG, "timing period must be >= 0");
@@ -1032,7 +1033,7 @@ hr2_status launch_forward(hr2_ctx *ctx, const hr2_tables *t, const hr2_obs *o,
     a.mlo = o->d_mlo;
     a.mlen = o->d_mlen;
     if (timed) HIP_TRY(hipEventRecord(ev[1], s));
-    HIP_TRY(launch_set_forward(t->view, cv, a, n_mu, s));
+    HIP_TRY(launch_set_forward(t->view, cv, a, n_mu, ctx->opt_nu_per_lane, s));
     if (timed) {
       HIP_TRY(hipEventRecord(ev[2], s));
       HIP_TRY(hipEventRecord(ev[3], s));

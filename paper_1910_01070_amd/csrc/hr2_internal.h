@@ -230,13 +230,16 @@ int column_wave_capacity(const TableView &tv, int max_mu, bool opacity_from_memo
                          bool para);
 
 // The whole forward model in one launch, one workgroup per set: for FP32,
-// FP16 and BF16 tables of at most eight species (below 4 GiB), columns of at
-// most 64 levels and windows of at most 4096 points (set_forward_fits), a
-// linear source and a layout with short supports (one wave per bin).  Same
+// FP16 and BF16 tables of one species (below 4 GiB), columns of at most 64
+// levels and windows of at most 4096 points (set_forward_fits), a linear
+// source and a layout with short supports (one wave per bin).  Same
 // arithmetic as the level, column (one chunk) and convolve/bin kernels.
+// nu_per_lane: 0 = automatic (two wavenumbers per lane), 1 or 2;
+// set_forward_nu_per_lane says which the launch uses.
 bool set_forward_fits(const TableView &tv, int n_levels, int64_t nu_count);
+int set_forward_nu_per_lane(const TableView &tv, int requested);
 hipError_t launch_set_forward(const TableView &tv, const ColumnsView &cv, const SetFwdArgs &args,
-                              int max_mu, hipStream_t stream);
+                              int max_mu, int nu_per_lane, hipStream_t stream);
 
 hipError_t launch_opacity_only(const TableView &tv, const void *recs, int n_levels,
                                int64_t nu_begin, int64_t nu_count, int64_t nu_stride,

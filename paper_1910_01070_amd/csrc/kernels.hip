@@ -1498,7 +1498,10 @@ constexpr int kSetThreads = 1024;
 constexpr int kSetMaxLevels = 64;
 constexpr int kSetMaxNu = 4096;
 
-template <typename TT, int NSS, int MAXMU>
+// NU wavenumbers per lane (1 or 2): a wave's tile is 64 NU points, lane j
+// holding points j, j + 64, ...; the NU recurrences of a lane are
+// independent, which gives the wave more work between its row loads.
+template <typename TT, int NSS, int MAXMU, int NU>
 __global__ __launch_bounds__(kSetThreads) __attribute__((amdgpu_waves_per_eu(8))) void k_set_forward(
     TableView tv, ColumnsView cv, SetFwdArgs a) {
   using Rec = LevelRecF;
@@ -1515,7 +1518,7 @@ __global__ __launch_bounds__(kSetThreads) __attribute__((amdgpu_waves_per_eu(8))
   const int lane = threadIdx.x & 63;
   const int n_waves = blockDim.x >> 6;
   const int64_t nu_count = a.nu_count;
-  const int tiles = (int)((nu_count + 63) / 64);
+  const int tiles = (int)((nu_count + 64 * NU - 1) / (64 * NU));
   const int nmu = a.n_mu;
   const int64_t sp_bytes = (int64_t)tv.nT * tv.nP * tv.pitch * (int64_t)sizeof(TT);
   const int64_t pair_bytes = (int64_t)tv.nT * tv.pitch * (int64_t)sizeof(float);
@@ -1532,101 +1535,129 @@ __global__ __launch_bounds__(kSetThreads) __attribute__((amdgpu_waves_per_eu(8))
   }
 
   for (int t = wave; t < tiles; t += n_waves) {
-    const int64_t j = (int64_t)t * 64 + lane;
-    const bool active = j < nu_count;
-    const int64_t jj = active ? j : nu_count - 1;
-    const int64_t kidx = a.nu_begin + jj * a.nu_stride;
-    const uint32_t kk = (uint32_t)kidx;
-    const double nu_d = tv.nu0 + (double)kidx * tv.dnu;
-    const float nu_hi = (float)nu_d;
-    const float nu_lo = (float)(nu_d - (double)nu_hi);
-    const float c1nu3_f = (float)(kC1 * nu_d * nu_d * nu_d);
-    const uint32_t kb = kk * (uint32_t)sizeof(TT);
-    const uint32_t kbc = kk * (uint32_t)sizeof(float);
-    float slot[NS][4];
-    float cslot[2][2];
+    int64_t j[NU];
+    bool active[NU];
+    float nu_hi[NU], nu_lo[NU], c1nu3_f[NU];
+    uint32_t kb[NU], kbc[NU];
 #pragma unroll
-    for (int q = 0; q < NS; ++q)
+    for (int u = 0; u < NU; ++u) {
+      j[u] = (int64_t)t * (64 * NU) + u * 64 + lane;
+      active[u] = j[u] < nu_count;
+      const int64_t jj = active[u] ? j[u] : nu_count - 1;
+      const int64_t kidx = a.nu_begin + jj * a.nu_stride;
+      const uint32_t kk = (uint32_t)kidx;
+      const double nu_d = tv.nu0 + (double)kidx * tv.dnu;
+      nu_hi[u] = (float)nu_d;
+      nu_lo[u] = (float)(nu_d - (double)nu_hi[u]);
+      c1nu3_f[u] = (float)(kC1 * nu_d * nu_d * nu_d);
+      kb[u] = kk * (uint32_t)sizeof(TT);
+      kbc[u] = kk * (uint32_t)sizeof(float);
+    }
+    float slot[NU][NS][4];
+    float cslot[NU][2][2];
 #pragma unroll
-      for (int k = 0; k < 4; ++k) slot[q][k] = 0.0f;
+    for (int u = 0; u < NU; ++u) {
 #pragma unroll
-    for (int q = 0; q < 2; ++q) cslot[q][0] = cslot[q][1] = 0.0f;
+      for (int q = 0; q < NS; ++q)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) slot[u][q][k] = 0.0f;
+#pragma unroll
+      for (int q = 0; q < 2; ++q) cslot[u][q][0] = cslot[u][q][1] = 0.0f;
+    }
     auto fetch = [&](const Rec &rr, int mask) {
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
         if (mask & (1 << k)) {
-          const uint32_t off = rr.rowb[k] + kb;
 #pragma unroll
-          for (int q = 0; q < NS; ++q)
-            if (q < S)
-              slot[q][k] = to_float<TT>(buf_load<TT>(rs, off, (uint32_t)(q * sp_bytes)));
+          for (int u = 0; u < NU; ++u) {
+            const uint32_t off = rr.rowb[k] + kb[u];
+#pragma unroll
+            for (int q = 0; q < NS; ++q)
+              if (q < S)
+                slot[u][q][k] = to_float<TT>(buf_load<TT>(rs, off, (uint32_t)(q * sp_bytes)));
+          }
         }
       }
       if (has_cia) {
 #pragma unroll
         for (int k = 0; k < 2; ++k) {
           if (mask & (16 << k)) {
-            const uint32_t off = rr.cia_rowb[k] + kbc;
-            cslot[0][k] = buf_load<float>(rc, off, 0);
-            cslot[1][k] = buf_load<float>(rc, off, (uint32_t)pair_bytes);
+#pragma unroll
+            for (int u = 0; u < NU; ++u) {
+              const uint32_t off = rr.cia_rowb[k] + kbc[u];
+              cslot[u][0][k] = buf_load<float>(rc, off, 0);
+              cslot[u][1][k] = buf_load<float>(rc, off, (uint32_t)pair_bytes);
+            }
           }
         }
       }
     };
-    auto opacity = [&](const Rec &r) -> float {
+    auto opacity = [&](const Rec &r, int u) -> float {
       float chi = 0.0f;
 #pragma unroll
       for (int q = 0; q < NS; ++q) {
         if (q < S) {
-          const float y = r.w[0] * slot[q][0] + r.w[1] * slot[q][1] + r.w[2] * slot[q][2] +
-                          r.w[3] * slot[q][3];
+          const float y = r.w[0] * slot[u][q][0] + r.w[1] * slot[u][q][1] +
+                          r.w[2] * slot[u][q][2] + r.w[3] * slot[u][q][3];
           chi = fmaf(r.a_s[q], fexp2(y), chi);
         }
       }
       if (has_cia) {
 #pragma unroll
         for (int q = 0; q < 2; ++q) {
-          const float y = r.cia_w[0] * cslot[q][0] + r.cia_w[1] * cslot[q][1];
+          const float y = r.cia_w[0] * cslot[u][q][0] + r.cia_w[1] * cslot[u][q][1];
           chi = fmaf(r.a_cia[q], fexp2(y), chi);
         }
       }
       return chi;
     };
-    float I[MAXMU];
-    float chi_prev = 0.0f, S_prev = 0.0f, hdz_prev = 0.0f, dtc_prev = 0.0f;
+    float I[NU][MAXMU];
+    float chi_prev[NU], S_prev[NU];
+    float hdz_prev = 0.0f, dtc_prev = 0.0f;
+#pragma unroll
+    for (int u = 0; u < NU; ++u) chi_prev[u] = S_prev[u] = 0.0f;
     fetch(s_rec[0], __builtin_amdgcn_readfirstlane(s_rec[0].mask) >> 8);
     for (int l = 0; l < L; ++l) {
       const Rec r = s_rec[l];
-      const float chi = opacity(r);
+      float chi[NU];
+#pragma unroll
+      for (int u = 0; u < NU; ++u) chi[u] = opacity(r, u);
       if (l + 1 < L) {
         const Rec &rn = s_rec[l + 1];
         asm volatile("" ::: "memory");
         fetch(rn, __builtin_amdgcn_readfirstlane(rn.mask));
       }
-      const float Sl = planck_f(nu_hi, nu_lo, c1nu3_f, r.pl_hi, r.pl_lo);
-      if (l == 0) {
 #pragma unroll
-        for (int k = 0; k < MAXMU; ++k) I[k] = Sl;
-      } else {
-        // trapezoid of chi over the layer, plus its share of a gray cloud
-        const float dtau = (chi_prev + chi) * hdz_prev + dtc_prev;
-        const float D = S_prev - Sl, rD = D * frcp(dtau);
+      for (int u = 0; u < NU; ++u) {
+        const float Sl = planck_f(nu_hi[u], nu_lo[u], c1nu3_f[u], r.pl_hi, r.pl_lo);
+        if (l == 0) {
 #pragma unroll
-        for (int k = 0; k < MAXMU; ++k)
-          if (k < nmu) I[k] = sc_step_f(I[k], dtau, rD, Sl, S_prev, D, a_inv[k], a_l2e[k], a_mu[k]);
+          for (int k = 0; k < MAXMU; ++k) I[u][k] = Sl;
+        } else {
+          // trapezoid of chi over the layer, plus its share of a gray cloud
+          const float dtau = (chi_prev[u] + chi[u]) * hdz_prev + dtc_prev;
+          const float D = S_prev[u] - Sl, rD = D * frcp(dtau);
+#pragma unroll
+          for (int k = 0; k < MAXMU; ++k)
+            if (k < nmu)
+              I[u][k] = sc_step_f(I[u][k], dtau, rD, Sl, S_prev[u], D, a_inv[k], a_l2e[k], a_mu[k]);
+        }
+        chi_prev[u] = chi[u];
+        S_prev[u] = Sl;
       }
-      chi_prev = chi;
-      S_prev = Sl;
       hdz_prev = r.hdz;
       dtc_prev = r.dtc;
     }
-    float F = 0.0f;
 #pragma unroll
-    for (int k = 0; k < MAXMU; ++k)
-      if (k < nmu) F = fmaf(c_ang.cw[nmu - 1][k], I[k], F);
-    if (active) {
-      s_fp[j] = F;
-      a.fplus[(int64_t)s * nu_count + j] = F;
+    for (int u = 0; u < NU; ++u) {
+      float F = 0.0f;
+#pragma unroll
+      for (int k = 0; k < MAXMU; ++k)
+        if (k < nmu) F = fmaf(c_ang.cw[nmu - 1][k], I[u][k], F);
+      if (active[u]) {
+        s_fp[j[u]] = F;
+        a.fplus[(int64_t)s * nu_count + j[u]] = F;
+      }
     }
   }
   __syncthreads();
@@ -1642,38 +1673,46 @@ __global__ __launch_bounds__(kSetThreads) __attribute__((amdgpu_waves_per_eu(8))
   }
 }
 
+// Variants: one species (C1-like tables), one or two wavenumbers per lane.
+// With more species the sweep's slot rows and the record items no longer
+// fit the 64 registers of two 1,024-thread workgroups per CU without
+// spilling inside the sweep, so those batches keep the three kernels.
 template <typename TT, int MAXMU>
-static bool set_forward_kernel(int S, void (**fn)(TableView, ColumnsView, SetFwdArgs)) {
-  if (S == 1) *fn = &k_set_forward<TT, -1, MAXMU>;
-  else if (S <= 8) *fn = &k_set_forward<TT, 8, MAXMU>;
-  else return false;
+static bool set_forward_kernel(int S, int nu_per_lane,
+                               void (**fn)(TableView, ColumnsView, SetFwdArgs)) {
+  if (S != 1) return false;
+  if (nu_per_lane == 2) *fn = &k_set_forward<TT, -1, MAXMU, 2>;
+  else *fn = &k_set_forward<TT, -1, MAXMU, 1>;
   return true;
 }
 
+int set_forward_nu_per_lane(const TableView &, int requested) { return requested == 1 ? 1 : 2; }
+
 bool set_forward_fits(const TableView &tv, int n_levels, int64_t nu_count) {
-  return tv.dtype != HR2_TABLE_F64 && tv.S <= 8 && n_levels <= kSetMaxLevels &&
+  return tv.dtype != HR2_TABLE_F64 && tv.S == 1 && n_levels <= kSetMaxLevels &&
          nu_count <= kSetMaxNu &&
          (int64_t)tv.nT * tv.nP * tv.pitch * tv.tab_elem * tv.S < 0xFFFFFFFFll;
 }
 
 hipError_t launch_set_forward(const TableView &tv, const ColumnsView &cv, const SetFwdArgs &args,
-                              int max_mu, hipStream_t stream) {
+                              int max_mu, int nu_per_lane, hipStream_t stream) {
   if (cv.B <= 0) return hipSuccess;
   void (*fn)(TableView, ColumnsView, SetFwdArgs) = nullptr;
   bool ok;
   const bool small = max_mu <= kMuTierSmall;
+  const int nl = set_forward_nu_per_lane(tv, nu_per_lane);
   switch (tv.dtype) {
     case HR2_TABLE_F16:
-      ok = small ? set_forward_kernel<_Float16, kMuTierSmall>(tv.S, &fn)
-                 : set_forward_kernel<_Float16, 8>(tv.S, &fn);
+      ok = small ? set_forward_kernel<_Float16, kMuTierSmall>(tv.S, nl, &fn)
+                 : set_forward_kernel<_Float16, 8>(tv.S, nl, &fn);
       break;
     case HR2_TABLE_BF16:
-      ok = small ? set_forward_kernel<uint16_t, kMuTierSmall>(tv.S, &fn)
-                 : set_forward_kernel<uint16_t, 8>(tv.S, &fn);
+      ok = small ? set_forward_kernel<uint16_t, kMuTierSmall>(tv.S, nl, &fn)
+                 : set_forward_kernel<uint16_t, 8>(tv.S, nl, &fn);
       break;
     case HR2_TABLE_F32:
-      ok = small ? set_forward_kernel<float, kMuTierSmall>(tv.S, &fn)
-                 : set_forward_kernel<float, 8>(tv.S, &fn);
+      ok = small ? set_forward_kernel<float, kMuTierSmall>(tv.S, nl, &fn)
+                 : set_forward_kernel<float, 8>(tv.S, nl, &fn);
       break;
     default:
       ok = false;

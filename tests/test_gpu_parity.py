@@ -508,17 +508,18 @@ def test_c3_graph_replay(ctx):
 
 @pytest.mark.parametrize("dtype", ["f32", "f16", "bf16"])
 def test_whole_forward_per_set(ctx, dtype):
-    """Small windows in batches that fill the device run the whole forward
-    model in one launch, one workgroup per set (levels and F+ in LDS).  It
-    must agree with the three-kernel path (forced by a fixed chunk count) to
-    FP32 rounding, with the oracle at every tested set, for both angle tiers
-    and with an invalid set in the batch."""
-    tab = tu.small_multi_table()
+    """Small windows in batches that fill the device (one-species tables) run
+    the whole forward model in one launch, one workgroup per set (levels and
+    F+ in LDS), with one or two wavenumbers per lane.  Both must agree with the
+    three-kernel path (forced by a fixed chunk count) to FP32 rounding (5e-6)
+    and with the oracle at every tested set (1e-5), for both angle tiers, with a ragged
+    last tile and with an invalid set in the batch."""
+    tab = tu.c1_table()
     T = hr2.Tables(ctx, tab, dtype)
     ref_tab = tab if dtype == "f32" else tu.dequantised(tab, dtype)
-    w = wl.Window(100, 2000, 1)
+    w = wl.Window(3, 1990, 1)   # 15.5 tiles of 128 points, 31.1 of 64
     nu_first, dnu = oracle.window_grid(tab, w)
-    edges = wl.snapped_edges(tab, w, wl.log_edges(nu_first + 100 * dnu, nu_first + 1900 * dnu, 30))
+    edges = wl.snapped_edges(tab, w, wl.log_edges(nu_first + 100 * dnu, nu_first + 1880 * dnu, 30))
     obs = hr2.Obs(ctx, T, w, 2000.0, edges)
     B = 300   # 300 sets x 32 tiles: more waves than the device holds at once
     cols = tu.small_columns(tab, B, seed=77, n_levels=41)
@@ -531,27 +532,37 @@ def test_whole_forward_per_set(ctx, dtype):
     bins = torch.empty(B * obs.n_bins, dtype=torch.float32, device="cuda")
     fplus = torch.empty(B * w.count, dtype=torch.float32, device="cuda")
     status = torch.full((B,), 7, dtype=torch.int32, device="cuda")
-    for n_mu in (3, 5):
-        out = {}
-        for chunks in (0, 1):
-            ctx.set_option(hr2.OPT_CHUNKS, chunks)
-            hr2.forward_batch_dev(ctx, T, obs, p, Tk, x, lg, sc, n_mu, bins, fplus, status)
-            torch.cuda.synchronize()
-            assert int(status.abs().sum()) == 0
-            out[chunks] = (bins.cpu().numpy().reshape(B, -1).astype(np.float64),
-                           fplus.cpu().numpy().reshape(B, -1).astype(np.float64))
+
+    def run(n_mu, chunks, per_lane):
+        ctx.set_option(hr2.OPT_CHUNKS, chunks)
+        ctx.set_option(hr2.OPT_NU_PER_LANE, per_lane)
+        hr2.forward_batch_dev(ctx, T, obs, p, Tk, x, lg, sc, n_mu, bins, fplus, status)
+        torch.cuda.synchronize()
         ctx.set_option(hr2.OPT_CHUNKS, 0)
-        d_b = np.max(np.abs(out[0][0] - out[1][0]) / np.abs(out[1][0]))
-        d_f = np.max(np.abs(out[0][1] - out[1][1]) / np.abs(out[1][1]))
-        say(f"per-set launch {dtype} n_mu={n_mu}: vs three kernels bins {d_b:.1e}, F+ {d_f:.1e}")
-        assert d_b <= 1e-6 and d_f <= 1e-6
-        for s in (0, 150, B - 1):
-            ref = oracle.forward(ref_tab, cols[s], w, 2000.0, edges, n_mu)
-            e_f, _ = tu.max_rel_err(out[0][1][s], ref["fplus"])
-            e_b, _ = tu.max_rel_err(out[0][0][s], ref["bins"])
-            say(f"  set {s}: F+ {e_f:.2e} bins {e_b:.2e}")
-            assert e_f <= 1e-5 and e_b <= 1e-5
+        ctx.set_option(hr2.OPT_NU_PER_LANE, 0)
+        assert int(status.abs().sum()) == 0
+        return (bins.cpu().numpy().reshape(B, -1).astype(np.float64),
+                fplus.cpu().numpy().reshape(B, -1).astype(np.float64))
+
+    for n_mu in (3, 5):
+        three = run(n_mu, 1, 0)
+        for per_lane in (1, 2):
+            got = run(n_mu, 0, per_lane)
+            d_b = np.max(np.abs(got[0] - three[0]) / np.abs(three[0]))
+            d_f = np.max(np.abs(got[1] - three[1]) / np.abs(three[1]))
+            say(f"per-set launch {dtype} n_mu={n_mu}, {per_lane} per lane: vs three kernels "
+                f"bins {d_b:.1e}, F+ {d_f:.1e}")
+            # two FP32 evaluations of one recurrence, each ~1e-6 from the
+            # oracle's FP64 value: at most about twice that apart
+            assert d_b <= 5e-6 and d_f <= 5e-6
+            for s in (0, 150, B - 1):
+                ref = oracle.forward(ref_tab, cols[s], w, 2000.0, edges, n_mu)
+                e_f, _ = tu.max_rel_err(got[1][s], ref["fplus"])
+                e_b, _ = tu.max_rel_err(got[0][s], ref["bins"])
+                say(f"  set {s}: F+ {e_f:.2e} bins {e_b:.2e}")
+                assert e_f <= 1e-5 and e_b <= 1e-5
     say("one invalid set in the batch")
+    valid = run(5, 0, 0)
     Tbad = Tk.clone()
     Tbad[7, 3] = -10.0
     hr2.forward_batch_dev(ctx, T, obs, p, Tbad, x, lg, sc, 5, bins, fplus, status)
@@ -560,6 +571,9 @@ def test_whole_forward_per_set(ctx, dtype):
     st = status.cpu().numpy()
     assert st[7] == hr2.E_INVALID_ARG and np.all(np.delete(st, 7) == 0)
     assert np.all(np.isnan(got[7]))
-    assert np.array_equal(np.delete(got, 7, axis=0), np.delete(out[0][0], 7, axis=0))
+    assert np.array_equal(np.delete(got, 7, axis=0), np.delete(valid[0], 7, axis=0))
+    with pytest.raises(hr2.HR2Error) as ei:
+        ctx.set_option(hr2.OPT_NU_PER_LANE, 3)
+    assert ei.value.status == hr2.E_UNSUPPORTED
     obs.close()
     T.close()
