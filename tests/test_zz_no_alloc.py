@@ -104,3 +104,46 @@ def test_noalloc_refuses_a_call_beyond_its_array():
     obs.close()
     T.close()
     ctx.close()
+
+
+def test_noalloc_captured_into_a_graph_without_a_prior_call():
+    """The entry point needs no staging and no scratch growth, so it can be
+    captured into a HIP graph on a fresh context; every replay (with eager
+    work and synchronisations between them) equals the eager call."""
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    ctx = hr2.Context(0)
+    tab = tu.small_multi_table()
+    T = hr2.Tables(ctx, tab, "f32")
+    w = wl.Window(13, 1001, 2)
+    nu_first = tab.nu0_cm + w.begin * tab.dnu_cm
+    dnu = w.stride * tab.dnu_cm
+    edges = wl.snapped_edges(tab, w, wl.log_edges(nu_first + 0.2 * (w.count - 1) * dnu,
+                                                 nu_first + 0.8 * (w.count - 1) * dnu, 9))
+    obs = hr2.Obs(ctx, T, w, 400.0, edges)
+    cols = tu.small_columns(tab, 4, seed=41, n_levels=41)
+    p, Tk, x, lg, sc = _columns(cols)
+    bins = torch.empty(4 * obs.n_bins, dtype=torch.float32, device="cuda")
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(g, stream=s):
+            hr2.forward_batch_dev_noalloc(ctx, T, obs, p, Tk, x, lg, sc, 3, bins, None, None, s)
+    torch.cuda.synchronize()
+    ref = torch.empty_like(bins)
+    hr2.forward_batch_dev(ctx, T, obs, p, Tk, x, lg, sc, 3, ref)
+    torch.cuda.synchronize()
+    for rep in range(3):
+        bins.zero_()
+        junk = torch.randn(1 << 16, device="cuda").sum()
+        torch.cuda.synchronize()
+        say(f"noalloc graph replay {rep}")
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(bins, ref), rep
+        del junk
+    del g
+    torch.cuda.synchronize()
+    obs.close()
+    T.close()
+    ctx.close()
