@@ -151,10 +151,16 @@ typedef enum {
                               call with HIP events (0 = off)                        */
   HR2_OPT_SOURCE = 3,      /* 1 = linear source (default), 2 = parabolic; servers
                               take the value their context has at creation          */
-  HR2_OPT_ROW_POLICY = 4   /* table-row loads of one-set calls: 0 = auto (non-temporal
+  HR2_OPT_ROW_POLICY = 4,  /* table-row loads of one-set calls: 0 = auto (non-temporal
                               when the call's rows would overflow the last-level
                               cache), 1 = always non-temporal, 2 = always cached.
                               Batches always load cached.  Results do not change. */
+  HR2_OPT_TILE_PAIRS = 5   /* one-set calls whose tiles spill past one round of
+                              resident workgroups: 0 = auto (the first round's
+                              workgroups take two tiles each, the tiles left
+                              over twice the layer chunks), 1 = off.  The
+                              leftover tiles' F+ changes by the rounding of a
+                              different chunk split (below 1e-6 relative).      */
 } hr2_option;
 hr2_status hr2_ctx_set_option(hr2_ctx *ctx, hr2_option opt, int value);
 

@@ -41,6 +41,7 @@ struct hr2_ctx {
   int opt_chunks = 0;
   int opt_source = 1;              // 1 linear, 2 parabolic short characteristics
   int opt_row_policy = 0;          // one-set calls: 0 auto, 1 non-temporal, 2 cached
+  int opt_tile_pairs = 0;          // one-set calls: 0 auto, 1 off
   int opt_nu_per_lane = 0;         // per-set launches: 0 auto, 1 or 2 wavenumbers per lane
   int timing_every = 0;            // time every n-th forward call (0 = off)
   int64_t timing_calls = 0;

@@ -124,7 +124,14 @@ struct ColSeg {
   int64_t chi_offset;      // stage call only: chi + chi_offset + l * nu_count
   int32_t n_sets, n_levels, tiles_per_set, n_mu;
   int32_t chunks;          // layer chunks per 64-point tile, 1..8 (= waves per workgroup)
-  int32_t pad;
+  // Tile groups (one set, the launch's only segment): workgroup blockIdx
+  // = x + 8 k runs on XCD x (round-robin dispatch) and covers XCD x's
+  // contiguous share of the tiles; its first wg_multi workgroups take
+  // tiles_per_wg tiles of chunks / tiles_per_wg layer chunks each, the rest
+  // one tile of `chunks`, so the tiles left for the last round of waves
+  // finish in a fraction of the levels.  wg_multi = 0: one tile per
+  // workgroup (segment lists, batches).
+  int32_t wg_multi, tiles_per_wg;
 };
 
 // One segment of a convolve/bin launch: n_sets spectra against one layout.

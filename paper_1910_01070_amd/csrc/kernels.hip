@@ -778,12 +778,18 @@ constexpr int kMuTierSmall = 3;
 // Occupancy floor per instantiation: the FP32 parabolic sweep with an exact
 // species count and the small angle tier fits in 72 VGPRs (7 waves per SIMD)
 // without spilling when asked to, where the compiler otherwise takes 73-74
-// (6 waves).  Everything else keeps the compiler's choice.
+// (6 waves).  The linear sweep over exactly 8 species in the small angle tier
+// takes 62-63 VGPRs but 102 SGPRs, which holds it to 7 waves per SIMD (SGPRs
+// are allocated in blocks of 16 from 800 per SIMD); asked for 8 it fits in
+// 78 SGPRs without spilling, so that four 8-wave workgroups of tile pairs fit
+// on a CU.  Everything else keeps the compiler's choice.
 template <typename Real, int NSS, int MAXMU, bool PARA>
 constexpr int column_min_waves() {
-  return (PARA && !std::is_same<Real, double>::value && NSS < 0 && MAXMU <= kMuTierSmall) ? 7
-                                                                                          : 1;
+  if (std::is_same<Real, double>::value || NSS >= 0 || MAXMU > kMuTierSmall) return 1;
+  if (PARA) return 7;
+  return NSS == -8 ? 8 : 1;
 }
+
 
 // Workgroup = C waves over one 64-point tile of one set; wave c sweeps layer
 // chunk c: stage 1 (opacity, Sect. 2.3) from the slot registers, dtau
@@ -835,14 +841,36 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(
   }
   const ColSeg d = n_segs == 0 ? seg0 : segs[sg];
   const int n_sets = d.n_sets;
-  const int C = blockDim.x >> 6;   // one wave per layer chunk (the segment's chunks)
-  const int64_t local = g - d.wg_begin;
-  const int64_t t = local / n_sets;
-  const int s = (int)(local - t * n_sets);
-
   // the wave index is uniform across a wavefront; say so, so that everything
   // derived from it (chunk, levels, records, load masks) stays scalar
-  const int chunk = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  int C = blockDim.x >> 6;   // one wave per layer chunk (the segment's chunks)
+  int chunk = wave, grp = 0;
+  int64_t t;
+  int s;
+  if (n_segs == 0 && d.wg_multi > 0) {
+    // tile groups (one set): XCD x's tiles are [t0, t0 + q + (x < r))
+    const int x = blockIdx.x & 7;
+    const int64_t k = blockIdx.x >> 3;
+    const int64_t q = d.tiles_per_set >> 3, r = d.tiles_per_set & 7;
+    const int64_t t0 = x * q + (x < r ? x : r);
+    const int G = d.tiles_per_wg;
+    if (k < d.wg_multi) {
+      C /= G;
+      grp = wave / C;
+      chunk = wave - grp * C;
+      t = t0 + G * k + grp;
+    } else {
+      t = t0 + (int64_t)(G - 1) * d.wg_multi + k;
+    }
+    s = 0;
+  } else {
+    const int64_t local = g - d.wg_begin;
+    t = local / n_sets;
+    s = (int)(local - t * n_sets);
+  }
+  // this wave's tile group in the combine area
+  sh += grp * C * (MAXMU + 1) * 64;
   const int lane = threadIdx.x & 63;
   const int L = d.n_levels, nlay = L - 1;
   const int m = (nlay + C - 1) / C;
@@ -1168,7 +1196,8 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(
           F = fmaf(c_ang.cw[nmu - 1][k], I[k], F);
       }
   } else {
-    // layout: sh[(c * (MAXMU + 1) + k) * 64 + lane], k = MAXMU holds tau
+    // layout (from the tile group's base): sh[(c * (MAXMU + 1) + k) * 64 + lane],
+    // k = MAXMU holds tau
     sh[(chunk * (MAXMU + 1) + MAXMU) * 64 + lane] = tau;
 #pragma unroll
     for (int k = 0; k < MAXMU; ++k) sh[(chunk * (MAXMU + 1) + k) * 64 + lane] = I[k];

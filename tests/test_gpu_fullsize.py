@@ -183,3 +183,47 @@ def test_c4_species_offset_ablation(ctx, c2, dtype):
         T.close()
     say(f"  {dtype}: bins vs source, per species / per row: "
         f"{errs['species'][0] / errs['row'][0]:.1f}x")
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f16"])
+def test_c2_tile_pairs(ctx, c2, dtype):
+    """One-set calls whose tiles spill past one round of resident workgroups
+    run tile pairs (HR2_OPT_TILE_PAIRS): every F+ point and bin with pairs and
+    without against the oracle (FP32 on the source, FP16 on its dequantised
+    table, 1e-5), the two within 1e-6 of each other (only the leftover tiles'
+    chunk split differs), also on a window whose tile count leaves a
+    remainder over the eight XCDs and ends in a partial tile."""
+    spec = wl.c2_obs(c2)
+    col = wl.c2_column()
+    tab = c2 if dtype == "f32" else _dequantised(dtype)
+    T = hr2.Tables(ctx, c2, dtype)
+    for w in (spec.window, wl.Window(1000, 147_001, 1)):
+        if w == spec.window:
+            edges = spec.edges_cm
+        else:
+            nu_first, dnu = oracle.window_grid(c2, w)
+            edges = wl.snapped_edges(c2, w, wl.log_edges(nu_first + 0.05 * (w.count - 1) * dnu,
+                                                         nu_first + 0.95 * (w.count - 1) * dnu,
+                                                         300))
+        obs = hr2.Obs(ctx, T, w, spec.resolving_power, edges)
+        ref = oracle.forward(tab, col, w, spec.resolving_power, edges, 3)
+        got = {}
+        for opt in (0, 1):
+            ctx.set_option(hr2.OPT_TILE_PAIRS, opt)
+            bins, fplus = _bench_launch(ctx, T, obs, [col])
+            e_f, _ = tu.max_rel_err(fplus[0], ref["fplus"])
+            e_b, _ = tu.max_rel_err(bins[0], ref["bins"])
+            say(f"  {dtype} window ({w.begin}, {w.count}) pairs {'on' if opt == 0 else 'off'}: "
+                f"F+ {e_f:.2e} bins {e_b:.2e}")
+            assert e_f <= 1e-5 and e_b <= 1e-5
+            got[opt] = (bins[0], fplus[0])
+        d_f, _ = tu.max_rel_err(got[0][1], got[1][1])
+        d_b, _ = tu.max_rel_err(got[0][0], got[1][0])
+        say(f"  pairs on vs off: F+ {d_f:.2e} bins {d_b:.2e}")
+        assert d_f <= 1e-6 and d_b <= 1e-6
+        obs.close()
+    ctx.set_option(hr2.OPT_TILE_PAIRS, 0)
+    with pytest.raises(hr2.HR2Error) as ei:
+        ctx.set_option(hr2.OPT_TILE_PAIRS, 2)
+    assert ei.value.status == hr2.E_INVALID_ARG
+    T.close()
