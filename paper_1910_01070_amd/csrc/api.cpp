@@ -1087,7 +1087,6 @@ hr2_status launch_forward(hr2_ctx *ctx, const hr2_tables *t, const hr2_obs *o,
       total_wgs = seg.tiles_per_set - 8 * per_xcd;
     }
   }
-  if (timed) HIP_TRY(hipEventRecord(ev[1], s));
   // A single set reads each of its rows once.  When they cannot stay in the
   // last-level cache until the next call anyway (estimated at one new row per
   // level and species, against the 256 MB Infinity Cache), they are loaded
@@ -1101,8 +1100,12 @@ hr2_status launch_forward(hr2_ctx *ctx, const hr2_tables *t, const hr2_obs *o,
   const bool stream_rows =
       B == 1 && (ctx->opt_row_policy == 1 ||
                  (ctx->opt_row_policy == 0 && row_bytes_est > kLastLevelCacheBytes));
+  // timed calls: the column kernel's own start and end (launch timestamps),
+  // so that its interval holds no dispatch gap; the levels interval runs up
+  // to the column kernel's start and the convolution's from its end
   HIP_TRY(launch_column(t->view, nullptr, 1, &seg, total_wgs, launch_chunks, scr.recs, nullptr,
-                        fplus, n_mu, false, ctx->opt_source == 2, stream_rows, s));
+                        fplus, n_mu, false, ctx->opt_source == 2, stream_rows, s,
+                        timed ? ev[1] : nullptr, timed ? ev[2] : nullptr));
   ConvSeg cs{};
   cs.item_begin = 0;
   cs.K = o->d_K;
@@ -1122,7 +1125,6 @@ hr2_status launch_forward(hr2_ctx *ctx, const hr2_tables *t, const hr2_obs *o,
     cs.log10_eps = like->log10_eps;
     cs.terms = scr.terms;
   }
-  if (timed) HIP_TRY(hipEventRecord(ev[2], s));
   cs.items_per_wg = conv_items_per_wg(o->nnz, o->n_bins);
   HIP_TRY(launch_convolve_bin(o->fp64, nullptr, 1, &cs,
                               conv_workgroups((int64_t)B * o->n_bins, cs.items_per_wg), fplus,

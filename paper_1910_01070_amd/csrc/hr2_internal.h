@@ -224,10 +224,13 @@ hipError_t launch_levels_segs(const TableView &tv, const LevelSeg *segs_dev, int
 // seg0_host: a launch of one segment passes it by value (segs_dev unused).
 // stream_rows: load the table rows non-temporal (a launch of one set, whose
 // rows nothing reads again); ignored when the opacity comes from memory.
+// t_start / t_stop (optional): events that take the kernel's own start and
+// end times (the launch's profiling timestamps, not markers in the stream).
 hipError_t launch_column(const TableView &tv, const ColSeg *segs_dev, int n_segs,
                          const ColSeg *seg0_host, int64_t total_wgs, int chunks, const void *recs,
                          const void *chi_in, void *out, int max_mu, bool opacity_from_memory,
-                         bool para, bool stream_rows, hipStream_t stream);
+                         bool para, bool stream_rows, hipStream_t stream,
+                         hipEvent_t t_start = nullptr, hipEvent_t t_stop = nullptr);
 int column_nu_per_wg(int chunks);
 // Waves of the column kernel (with this chunk count) the device holds at once.
 // Largest angle count of the column kernel variant a request of n_mu angles

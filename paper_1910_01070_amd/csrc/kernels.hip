@@ -10,6 +10,7 @@
 // layer recurrence may be split into up to eight chunks whose affine maps
 // I_out = exp(-tau_c / mu) I_in + B_c are combined through LDS.
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 
 #include <algorithm>
 #include <cmath>
@@ -1298,13 +1299,21 @@ static size_t column_shmem(const ColumnKernel &k, int chunks) {
 hipError_t launch_column(const TableView &tv, const ColSeg *segs_dev, int n_segs,
                          const ColSeg *seg0_host, int64_t total_wgs, int chunks, const void *recs,
                          const void *chi_in, void *out, int max_mu, bool opacity_from_memory,
-                         bool para, bool stream_rows, hipStream_t stream) {
+                         bool para, bool stream_rows, hipStream_t stream, hipEvent_t t_start,
+                         hipEvent_t t_stop) {
   if (total_wgs <= 0) return hipSuccess;
   const ColumnKernel k = pick_column(tv, max_mu, opacity_from_memory, para, stream_rows);
   const ColSeg seg0 = seg0_host ? *seg0_host : ColSeg{};
-  hipLaunchKernelGGL(k.fn, dim3((unsigned)total_wgs), dim3(64 * chunks),
-                     column_shmem(k, chunks), stream, tv, segs_dev, seg0_host ? 0 : n_segs, seg0,
-                     total_wgs, recs, chi_in, out);
+  const int ns = seg0_host ? 0 : n_segs;
+  if (t_start || t_stop) {
+    hipExtLaunchKernelGGL(k.fn, dim3((unsigned)total_wgs), dim3(64 * chunks),
+                          (uint32_t)column_shmem(k, chunks), stream, t_start, t_stop, 0u, tv,
+                          segs_dev, ns, seg0, total_wgs, recs, chi_in, out);
+  } else {
+    hipLaunchKernelGGL(k.fn, dim3((unsigned)total_wgs), dim3(64 * chunks),
+                       column_shmem(k, chunks), stream, tv, segs_dev, ns, seg0, total_wgs, recs,
+                       chi_in, out);
+  }
   return hipGetLastError();
 }
 

@@ -577,3 +577,31 @@ def test_whole_forward_per_set(ctx, dtype):
     assert ei.value.status == hr2.E_UNSUPPORTED
     obs.close()
     T.close()
+
+
+def test_kernel_timing_leaves_results_unchanged(ctx):
+    """HR2_OPT_TIMING brackets every n-th call's kernels with HIP events (the
+    column kernel through its own launch timestamps): the call count, three
+    positive intervals whose column part is the smallest bracket of the
+    kernel alone, and results bit-identical to untimed calls."""
+    tab = tu.c1_table()
+    T = hr2.Tables(ctx, tab, "f32")
+    spec = wl.c1_obs(tab)
+    obs = hr2.Obs(ctx, T, spec.window, spec.resolving_power, spec.edges_cm)
+    col = wl.c1_columns()[:1]
+    ref = run_forward(ctx, T, obs, col, 3)
+    ctx.set_option(hr2.OPT_TIMING, 2)
+    ctx.collect_timing()
+    outs = [run_forward(ctx, T, obs, col, 3) for _ in range(5)]
+    ctx.set_option(hr2.OPT_TIMING, 0)
+    (ms_lev, ms_col, ms_conv), n = ctx.collect_timing()
+    say(f"  timed calls {n}: levels {ms_lev / n * 1e3:.1f} us, column {ms_col / n * 1e3:.1f} us, "
+        f"convolution {ms_conv / n * 1e3:.1f} us per call")
+    assert n == 3
+    assert ms_lev > 0 and ms_col > 0 and ms_conv > 0
+    for b, f in outs:
+        assert np.array_equal(b, ref[0]) and np.array_equal(f, ref[1])
+    (z0, z1, z2), n0 = ctx.collect_timing()
+    assert n0 == 0 and z0 == z1 == z2 == 0.0
+    obs.close()
+    T.close()
