@@ -147,8 +147,9 @@ typedef enum {
                               batches that fill the device): 0 = auto (2), 1 or 2;
                               the column kernel keeps 1 (2 costs it half its
                               resident waves)                                        */
-  HR2_OPT_TIMING = 2,      /* n > 0: bracket the kernels of every n-th forward-batch
-                              call with HIP events (0 = off)                        */
+  HR2_OPT_TIMING = 2,      /* n > 0: time the kernels of every n-th forward-batch
+                              call through HIP events attached to their launches
+                              (0 = off)                                            */
   HR2_OPT_SOURCE = 3,      /* 1 = linear source (default), 2 = parabolic; servers
                               take the value their context has at creation          */
   HR2_OPT_ROW_POLICY = 4,  /* table-row loads of one-set calls: 0 = auto (non-temporal
@@ -165,11 +166,14 @@ typedef enum {
 hr2_status hr2_ctx_set_option(hr2_ctx *ctx, hr2_option opt, int value);
 
 /* Kernel timing of the forward-batch calls made while HR2_OPT_TIMING was on
- * (measured with HIP events on the caller's stream, bracketing each launch):
- * waits for those calls, writes the summed milliseconds of the level kernel,
- * the opacity+RT column kernel and the convolve/bin kernel to ms[0..2] and
- * the number of calls to *n_calls, then resets.  At most 65536 calls are
- * recorded between collections (later ones are not timed). */
+ * (each kernel's own start and end, from HIP events attached to its launch on
+ * the caller's stream, so the gaps between kernels are not counted): waits
+ * for those calls, writes the summed milliseconds of the level kernel, the
+ * opacity+RT column kernel and the convolve/bin kernel to ms[0..2] and the
+ * number of calls to *n_calls, then resets.  A call that runs the whole
+ * forward model in one launch (small windows in large batches) counts that
+ * launch as its column kernel and nothing for the other two.  At most 65536
+ * calls are recorded between collections (later ones are not timed). */
 hr2_status hr2_ctx_collect_timing(hr2_ctx *ctx, double ms[3], int64_t *n_calls);
 
 /* Cross-section and CIA tables (Sect. 2.3).  All arrays are host FP64.

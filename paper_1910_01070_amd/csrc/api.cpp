@@ -964,9 +964,13 @@ namespace hr2 {
 
 constexpr size_t kMaxTimedCalls = 65536;
 
-// Event slot k of the current timed call (nullptr when not timing).
+// Event slot k of the current timed call (nullptr when not timing): the
+// start and end of its level kernel, column kernel (or whole-forward-model
+// kernel) and convolution, each taken from the launch itself.
+constexpr int kTimedEvents = 6;
 static hipEvent_t timing_event(hr2_ctx *ctx, int k) {
-  if (ctx->timing_every <= 0 || ctx->tev_used + 4 > 4 * kMaxTimedCalls) return nullptr;
+  if (ctx->timing_every <= 0 || ctx->tev_used + kTimedEvents > kTimedEvents * kMaxTimedCalls)
+    return nullptr;
   const size_t at = ctx->tev_used + k;
   while (ctx->tev.size() <= at) {
     hipEvent_t ev;
@@ -1012,11 +1016,11 @@ hr2_status launch_forward(hr2_ctx *ctx, const hr2_tables *t, const hr2_obs *o,
   if (fplus == nullptr) fplus = scr.fplus;
   const bool this_call = scr.timing && ctx->timing_every > 0 && !capturing(s) &&
                          (ctx->timing_calls++ % ctx->timing_every) == 0;
-  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+  hipEvent_t ev[kTimedEvents] = {};
+  bool timed = this_call;
   if (this_call)
-    for (int k = 0; k < 4; ++k) ev[k] = timing_event(ctx, k);
-  const bool timed = ev[0] && ev[1] && ev[2] && ev[3];
-  if (timed) HIP_TRY(hipEventRecord(ev[0], s));
+    for (int k = 0; k < kTimedEvents; ++k) timed = (ev[k] = timing_event(ctx, k)) && timed;
+  auto tev = [&](int k) { return timed ? ev[k] : nullptr; };
   const int64_t base_waves = (int64_t)B * ((w.nu_count + 63) / 64);
   // Small windows in a batch that fills the device on its own: the whole
   // forward model in one launch, one workgroup per set (records and F+ in
@@ -1037,17 +1041,15 @@ hr2_status launch_forward(hr2_ctx *ctx, const hr2_tables *t, const hr2_obs *o,
     a.kstart = o->d_kstart;
     a.mlo = o->d_mlo;
     a.mlen = o->d_mlen;
-    if (timed) HIP_TRY(hipEventRecord(ev[1], s));
-    HIP_TRY(launch_set_forward(t->view, cv, a, n_mu, ctx->opt_nu_per_lane, s));
+    HIP_TRY(launch_set_forward(t->view, cv, a, n_mu, ctx->opt_nu_per_lane, s, tev(2), tev(3)));
     if (timed) {
-      HIP_TRY(hipEventRecord(ev[2], s));
-      HIP_TRY(hipEventRecord(ev[3], s));
-      ctx->tev_used += 4;
+      ctx->tmask.push_back(2);   // one kernel: the column interval
+      ctx->tev_used += kTimedEvents;
     }
     return HR2_OK;
   }
   HIP_TRY(launch_levels(t->view, cv, scr.recs, status, t->view.dtype == HR2_TABLE_F64, s,
-                        theta));
+                        theta, tev(0), tev(1)));
   const int chunks = ctx->opt_chunks ? std::min(ctx->opt_chunks, std::max(1, L - 1))
                                      : auto_chunks(t->view, base_waves, L, n_mu, false,
                                                    ctx->opt_source == 2);
@@ -1100,12 +1102,9 @@ hr2_status launch_forward(hr2_ctx *ctx, const hr2_tables *t, const hr2_obs *o,
   const bool stream_rows =
       B == 1 && (ctx->opt_row_policy == 1 ||
                  (ctx->opt_row_policy == 0 && row_bytes_est > kLastLevelCacheBytes));
-  // timed calls: the column kernel's own start and end (launch timestamps),
-  // so that its interval holds no dispatch gap; the levels interval runs up
-  // to the column kernel's start and the convolution's from its end
   HIP_TRY(launch_column(t->view, nullptr, 1, &seg, total_wgs, launch_chunks, scr.recs, nullptr,
-                        fplus, n_mu, false, ctx->opt_source == 2, stream_rows, s,
-                        timed ? ev[1] : nullptr, timed ? ev[2] : nullptr));
+                        fplus, n_mu, false, ctx->opt_source == 2, stream_rows, s, tev(2),
+                        tev(3)));
   ConvSeg cs{};
   cs.item_begin = 0;
   cs.K = o->d_K;
@@ -1128,11 +1127,11 @@ hr2_status launch_forward(hr2_ctx *ctx, const hr2_tables *t, const hr2_obs *o,
   cs.items_per_wg = conv_items_per_wg(o->nnz, o->n_bins);
   HIP_TRY(launch_convolve_bin(o->fp64, nullptr, 1, &cs,
                               conv_workgroups((int64_t)B * o->n_bins, cs.items_per_wg), fplus,
-                              bins, s));
+                              bins, s, tev(4), tev(5)));
   if (like) HIP_TRY(launch_lnl_reduce(cs.terms, B, o->n_bins, like->lnl, s));
   if (timed) {
-    HIP_TRY(hipEventRecord(ev[3], s));
-    ctx->tev_used += 4;
+    ctx->tmask.push_back(7);   // levels, column, convolution
+    ctx->tev_used += kTimedEvents;
   }
   return HR2_OK;
 }
@@ -1407,15 +1406,19 @@ extern "C" hr2_status hr2_forward_params_dev(hr2_ctx *ctx, const hr2_tables *t, 
 extern "C" hr2_status hr2_ctx_collect_timing(hr2_ctx *ctx, double ms[3], int64_t *n_calls) {
   if (!ctx || !ms || !n_calls) return set_error(HR2_E_INVALID_ARG, "NULL argument");
   ms[0] = ms[1] = ms[2] = 0.0;
-  *n_calls = (int64_t)(ctx->tev_used / 4);
-  for (size_t c = 0; c + 4 <= ctx->tev_used; c += 4) {
-    HIP_TRY(hipEventSynchronize(ctx->tev[c + 3]));
+  *n_calls = (int64_t)ctx->tmask.size();
+  for (size_t c = 0; c < ctx->tmask.size(); ++c) {
+    const size_t base = c * kTimedEvents;
+    const int mask = ctx->tmask[c];
+    HIP_TRY(hipEventSynchronize(ctx->tev[base + ((mask & 4) ? 5 : 3)]));
     for (int k = 0; k < 3; ++k) {
+      if (!(mask & (1 << k))) continue;
       float t = 0.0f;
-      HIP_TRY(hipEventElapsedTime(&t, ctx->tev[c + k], ctx->tev[c + k + 1]));
+      HIP_TRY(hipEventElapsedTime(&t, ctx->tev[base + 2 * k], ctx->tev[base + 2 * k + 1]));
       ms[k] += t;
     }
   }
   ctx->tev_used = 0;
+  ctx->tmask.clear();
   return HR2_OK;
 }

@@ -45,7 +45,8 @@ struct hr2_ctx {
   int opt_nu_per_lane = 0;         // per-set launches: 0 auto, 1 or 2 wavenumbers per lane
   int timing_every = 0;            // time every n-th forward call (0 = off)
   int64_t timing_calls = 0;
-  std::vector<hipEvent_t> tev;     // 4 events per timed call
+  std::vector<hipEvent_t> tev;     // 6 events per timed call (start, end of 3 kernels)
+  std::vector<uint8_t> tmask;      // per timed call: which of the 3 intervals it has
   size_t tev_used = 0;             // events recorded since the last collection
   bool captured = false;           // a call on this context ran under stream capture: a
                                    // graph may hold its scratch, so superseded scratch

@@ -209,7 +209,8 @@ struct ThetaArgs {
 
 hipError_t launch_levels(const TableView &tv, const ColumnsView &cv, void *recs,
                          int *status, bool fp64, hipStream_t stream,
-                         const ThetaArgs *theta = nullptr);
+                         const ThetaArgs *theta = nullptr, hipEvent_t t_start = nullptr,
+                         hipEvent_t t_stop = nullptr);
 // Workgroups per set of the segmented level launch for columns of L levels.
 int level_blocks_per_set(const TableView &tv, int L);
 // Several batches in one launch: segs_dev[n_segs] in device memory (ascending
@@ -224,8 +225,9 @@ hipError_t launch_levels_segs(const TableView &tv, const LevelSeg *segs_dev, int
 // seg0_host: a launch of one segment passes it by value (segs_dev unused).
 // stream_rows: load the table rows non-temporal (a launch of one set, whose
 // rows nothing reads again); ignored when the opacity comes from memory.
-// t_start / t_stop (optional): events that take the kernel's own start and
-// end times (the launch's profiling timestamps, not markers in the stream).
+// t_start / t_stop (optional, here and on the other launch helpers): events
+// that take the kernel's own start and end times (the launch's profiling
+// timestamps, not markers in the stream).
 hipError_t launch_column(const TableView &tv, const ColSeg *segs_dev, int n_segs,
                          const ColSeg *seg0_host, int64_t total_wgs, int chunks, const void *recs,
                          const void *chi_in, void *out, int max_mu, bool opacity_from_memory,
@@ -249,7 +251,8 @@ int column_wave_capacity(const TableView &tv, int max_mu, bool opacity_from_memo
 bool set_forward_fits(const TableView &tv, int n_levels, int64_t nu_count);
 int set_forward_nu_per_lane(const TableView &tv, int requested);
 hipError_t launch_set_forward(const TableView &tv, const ColumnsView &cv, const SetFwdArgs &args,
-                              int max_mu, int nu_per_lane, hipStream_t stream);
+                              int max_mu, int nu_per_lane, hipStream_t stream,
+                              hipEvent_t t_start = nullptr, hipEvent_t t_stop = nullptr);
 
 hipError_t launch_opacity_only(const TableView &tv, const void *recs, int n_levels,
                                int64_t nu_begin, int64_t nu_count, int64_t nu_stride,
@@ -264,7 +267,8 @@ int64_t conv_workgroups(int64_t n_items, int items_per_wg);
 // total_wgs: the workgroups of all segments.
 hipError_t launch_convolve_bin(bool fp64, const ConvSeg *segs_dev, int n_segs,
                                const ConvSeg *seg0_host, int64_t total_wgs, const void *in,
-                               void *out, hipStream_t stream);
+                               void *out, hipStream_t stream, hipEvent_t t_start = nullptr,
+                               hipEvent_t t_stop = nullptr);
 // ln L per set: the sum over bins of the terms k_convolve_bin wrote.
 hipError_t launch_lnl_reduce(const double *terms, int n_sets, int n_bins, double *lnl,
                              hipStream_t stream);

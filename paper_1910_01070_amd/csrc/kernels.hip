@@ -90,6 +90,18 @@ __device__ __forceinline__ TT buf_load(rsrc_t r, uint32_t off, uint32_t soff) {
 __device__ __forceinline__ float fexp2(float x) { return __builtin_amdgcn_exp2f(x); }
 __device__ __forceinline__ float frcp(float x) { return __builtin_amdgcn_rcpf(x); }
 
+// A launch with start/stop events takes the kernel's own timestamps
+// (hipExtLaunchKernel); without events it is a plain launch (which stream
+// capture records).
+template <typename F, typename... Args>
+static void launch_timed(F kernel, dim3 grid, dim3 block, uint32_t shmem, hipStream_t stream,
+                         hipEvent_t t_start, hipEvent_t t_stop, Args... args) {
+  if (t_start || t_stop)
+    hipExtLaunchKernelGGL(kernel, grid, block, shmem, stream, t_start, t_stop, 0u, args...);
+  else
+    hipLaunchKernelGGL(kernel, grid, block, shmem, stream, args...);
+}
+
 // ------------------------------------------------------------ level records
 // Each workgroup stages one set (inputs and axes in LDS, every level's cell)
 // and runs independent items: per level, one for the cell, rows, weights and
@@ -453,7 +465,8 @@ __global__ __launch_bounds__(kLevelThreads) void k_levels(TableView tv, const Le
 }
 
 hipError_t launch_levels(const TableView &tv, const ColumnsView &cv, void *recs, int *status,
-                         bool fp64, hipStream_t stream, const ThetaArgs *theta) {
+                         bool fp64, hipStream_t stream, const ThetaArgs *theta,
+                         hipEvent_t t_start, hipEvent_t t_stop) {
   ThetaArgs ta{};
   if (theta) ta = *theta;
   // one workgroup per kLevelThreads items of a set: every item runs at once
@@ -467,11 +480,11 @@ hipError_t launch_levels(const TableView &tv, const ColumnsView &cv, void *recs,
   seg0.cv = cv;
   seg0.blocks_per_set = per_set;
   if (fp64)
-    hipLaunchKernelGGL(k_levels<double>, grid, dim3(threads), 0, stream, tv, nullptr, 0, seg0,
-                       (LevelRecD *)recs, status, ta);
+    launch_timed(k_levels<double>, grid, dim3(threads), 0u, stream, t_start, t_stop, tv,
+                 (const LevelSeg *)nullptr, 0, seg0, (LevelRecD *)recs, status, ta);
   else
-    hipLaunchKernelGGL(k_levels<float>, grid, dim3(threads), 0, stream, tv, nullptr, 0, seg0,
-                       (LevelRecF *)recs, status, ta);
+    launch_timed(k_levels<float>, grid, dim3(threads), 0u, stream, t_start, t_stop, tv,
+                 (const LevelSeg *)nullptr, 0, seg0, (LevelRecF *)recs, status, ta);
   return hipGetLastError();
 }
 
@@ -1305,15 +1318,9 @@ hipError_t launch_column(const TableView &tv, const ColSeg *segs_dev, int n_segs
   const ColumnKernel k = pick_column(tv, max_mu, opacity_from_memory, para, stream_rows);
   const ColSeg seg0 = seg0_host ? *seg0_host : ColSeg{};
   const int ns = seg0_host ? 0 : n_segs;
-  if (t_start || t_stop) {
-    hipExtLaunchKernelGGL(k.fn, dim3((unsigned)total_wgs), dim3(64 * chunks),
-                          (uint32_t)column_shmem(k, chunks), stream, t_start, t_stop, 0u, tv,
-                          segs_dev, ns, seg0, total_wgs, recs, chi_in, out);
-  } else {
-    hipLaunchKernelGGL(k.fn, dim3((unsigned)total_wgs), dim3(64 * chunks),
-                       column_shmem(k, chunks), stream, tv, segs_dev, ns, seg0, total_wgs, recs,
-                       chi_in, out);
-  }
+  launch_timed(k.fn, dim3((unsigned)total_wgs), dim3(64 * chunks),
+               (uint32_t)column_shmem(k, chunks), stream, t_start, t_stop, tv, segs_dev, ns, seg0,
+               total_wgs, recs, chi_in, out);
   return hipGetLastError();
 }
 
@@ -1509,17 +1516,18 @@ __global__ __launch_bounds__(256) void k_convolve_bin(const ConvSeg *__restrict_
 
 hipError_t launch_convolve_bin(bool fp64, const ConvSeg *segs_dev, int n_segs,
                                const ConvSeg *seg0_host, int64_t total_wgs, const void *in,
-                               void *out, hipStream_t stream) {
+                               void *out, hipStream_t stream, hipEvent_t t_start,
+                               hipEvent_t t_stop) {
   if (total_wgs <= 0) return hipSuccess;
   const dim3 grid((unsigned)total_wgs);
   const ConvSeg seg0 = seg0_host ? *seg0_host : ConvSeg{};
   const int ns = seg0_host ? 0 : n_segs;
   if (fp64)
-    hipLaunchKernelGGL(k_convolve_bin<double>, grid, dim3(256), 0, stream, segs_dev, ns, seg0,
-                       total_wgs, (const double *)in, (double *)out);
+    launch_timed(k_convolve_bin<double>, grid, dim3(256), 0u, stream, t_start, t_stop, segs_dev,
+                 ns, seg0, total_wgs, (const double *)in, (double *)out);
   else
-    hipLaunchKernelGGL(k_convolve_bin<float>, grid, dim3(256), 0, stream, segs_dev, ns, seg0,
-                       total_wgs, (const float *)in, (float *)out);
+    launch_timed(k_convolve_bin<float>, grid, dim3(256), 0u, stream, t_start, t_stop, segs_dev,
+                 ns, seg0, total_wgs, (const float *)in, (float *)out);
   return hipGetLastError();
 }
 
@@ -1733,7 +1741,8 @@ bool set_forward_fits(const TableView &tv, int n_levels, int64_t nu_count) {
 }
 
 hipError_t launch_set_forward(const TableView &tv, const ColumnsView &cv, const SetFwdArgs &args,
-                              int max_mu, int nu_per_lane, hipStream_t stream) {
+                              int max_mu, int nu_per_lane, hipStream_t stream, hipEvent_t t_start,
+                              hipEvent_t t_stop) {
   if (cv.B <= 0) return hipSuccess;
   void (*fn)(TableView, ColumnsView, SetFwdArgs) = nullptr;
   bool ok;
@@ -1756,7 +1765,8 @@ hipError_t launch_set_forward(const TableView &tv, const ColumnsView &cv, const 
       ok = false;
   }
   if (!ok) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(fn, dim3((unsigned)cv.B), dim3(kSetThreads), 0, stream, tv, cv, args);
+  launch_timed(fn, dim3((unsigned)cv.B), dim3(kSetThreads), 0u, stream, t_start, t_stop, tv, cv,
+               args);
   return hipGetLastError();
 }
 
