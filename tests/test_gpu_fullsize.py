@@ -65,16 +65,18 @@ def _dev(a):
 
 def _bench_launch(ctx, T, obs, cols):
     """The bench's step: hr2_forward_batch_dev with the columns in HBM, the
-    caller's F+ buffer, default chunking and row policy."""
+    caller's F+ buffer, default chunking and row policy (and the columns'
+    gray clouds, when they carry one)."""
     B = len(cols)
     p, Tk, x = (_dev(np.stack([getattr(c, k) for c in cols])) for k in ("p_bar", "T_K", "x"))
     lg, sc = _dev([c.log_g for c in cols]), _dev([c.scale for c in cols])
+    cl = _dev([c.cloud for c in cols]) if cols[0].cloud is not None else None
     bins = torch.empty(B * obs.n_bins, dtype=torch.float32, device="cuda")
     fplus = torch.empty(B * obs.window.count, dtype=torch.float32, device="cuda")
     status = torch.full((B,), 7, dtype=torch.int32, device="cuda")
     ctx.set_option(hr2.OPT_CHUNKS, 0)
     ctx.set_option(hr2.OPT_ROW_POLICY, 0)
-    hr2.forward_batch_dev(ctx, T, obs, p, Tk, x, lg, sc, 3, bins, fplus, status)
+    hr2.forward_batch_dev(ctx, T, obs, p, Tk, x, lg, sc, 3, bins, fplus, status, cloud=cl)
     torch.cuda.synchronize()
     assert int(status.abs().sum()) == 0
     return (bins.cpu().numpy().reshape(B, obs.n_bins).astype(np.float64),
@@ -226,4 +228,38 @@ def test_c2_tile_pairs(ctx, c2, dtype):
     with pytest.raises(hr2.HR2Error) as ei:
         ctx.set_option(hr2.OPT_TILE_PAIRS, 2)
     assert ei.value.status == hr2.E_INVALID_ARG
+    T.close()
+
+
+def test_c2_cloudy_tile_pairs(ctx, c2):
+    """C2 with a gray cloud (optical depth 5 spread over 0.3-3 bar, App. B),
+    the one-set launch with tile pairs and without: every F+ point and bin
+    against the oracle (1e-5), and the two within 5e-6 of each other: two
+    FP32 evaluations that differ only in the leftover tiles' chunk split, each
+    about 2e-6 from the oracle here, so their difference is bounded by the
+    sum (1.3e-6 measured, against 6e-7 for the clear sky: the cloud's optical
+    depth enters every layer's sum)."""
+    spec = wl.c2_obs(c2)
+    c = wl.c2_column()
+    col = wl.Column(c.p_bar, c.T_K, c.x, c.log_g, c.scale, (5.0, 0.3, 10.0))
+    T = hr2.Tables(ctx, c2, "f32")
+    obs = hr2.Obs(ctx, T, spec.window, spec.resolving_power, spec.edges_cm)
+    ref = oracle.forward(c2, col, spec.window, spec.resolving_power, spec.edges_cm, 3)
+    clear = oracle.forward(c2, c, spec.window, spec.resolving_power, spec.edges_cm, 3)
+    got = {}
+    for opt in (0, 1):
+        ctx.set_option(hr2.OPT_TILE_PAIRS, opt)
+        bins, fplus = _bench_launch(ctx, T, obs, [col])
+        e_f, _ = tu.max_rel_err(fplus[0], ref["fplus"])
+        e_b, _ = tu.max_rel_err(bins[0], ref["bins"])
+        say(f"  C2 cloudy, pairs {'on' if opt == 0 else 'off'}: F+ {e_f:.2e} bins {e_b:.2e}")
+        assert e_f <= 1e-5 and e_b <= 1e-5
+        got[opt] = (bins[0], fplus[0])
+    ctx.set_option(hr2.OPT_TILE_PAIRS, 0)
+    d_f, _ = tu.max_rel_err(got[0][1], got[1][1])
+    say(f"  pairs on vs off: F+ {d_f:.2e}")
+    assert d_f <= 5e-6
+    # the cloud changes the spectrum (the comparison is not of two clear skies)
+    assert tu.max_rel_err(ref["bins"], clear["bins"])[0] > 1e-3
+    obs.close()
     T.close()
