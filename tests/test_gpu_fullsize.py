@@ -263,3 +263,45 @@ def test_c2_cloudy_tile_pairs(ctx, c2):
     assert tu.max_rel_err(ref["bins"], clear["bins"])[0] > 1e-3
     obs.close()
     T.close()
+
+
+def test_c2_graph_replay(ctx, c2):
+    """The bench's one-set C2 call (three launches, tile pairs, non-temporal
+    rows) captured into a HIP graph and replayed three times, with eager work
+    and synchronisations between the replays: every replay's F+ and bins equal
+    the eager call's bit for bit."""
+    spec = wl.c2_obs(c2)
+    col = wl.c2_column()
+    T = hr2.Tables(ctx, c2, "f32")
+    obs = hr2.Obs(ctx, T, spec.window, spec.resolving_power, spec.edges_cm)
+    p, Tk, x = (_dev(getattr(col, k)[None]) for k in ("p_bar", "T_K", "x"))
+    lg, sc = _dev([col.log_g]), _dev([col.scale])
+    bins = torch.empty(obs.n_bins, dtype=torch.float32, device="cuda")
+    fplus = torch.empty(spec.window.count, dtype=torch.float32, device="cuda")
+    ctx.set_option(hr2.OPT_CHUNKS, 0)
+    ctx.set_option(hr2.OPT_TILE_PAIRS, 0)
+    hr2.forward_batch_dev(ctx, T, obs, p, Tk, x, lg, sc, 3, bins, fplus)
+    torch.cuda.synchronize()
+    ref_b, ref_f = bins.clone(), fplus.clone()
+    g = torch.cuda.CUDAGraph()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(g, stream=s):
+            hr2.forward_batch_dev(ctx, T, obs, p, Tk, x, lg, sc, 3, bins, fplus, None, s)
+    torch.cuda.synchronize()
+    for rep in range(3):
+        bins.zero_()
+        fplus.zero_()
+        junk = torch.randn(1 << 16, device="cuda").sum()
+        hr2.forward_batch_dev(ctx, T, obs, p, Tk, x, lg, sc, 3, torch.empty_like(bins))
+        torch.cuda.synchronize()
+        say(f"C2 replay {rep}")
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(bins, ref_b) and torch.equal(fplus, ref_f), rep
+        del junk
+    del g
+    torch.cuda.synchronize()
+    obs.close()
+    T.close()
