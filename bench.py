@@ -85,9 +85,10 @@ def traffic_from_profile(kernel_hash):
 
 def valu_from_profile(kernel_hash, col_ms):
     """The column kernel's VALU issue time per launch from a committed
-    rocprofv3 SQ_INSTS_VALU run on the current kernel source: wave
-    instructions x 4 cycles (64 lanes on a 16-wide SIMD) over the chip's
-    1024 SIMDs at 2.4 GHz, next to the measured kernel time."""
+    rocprofv3 SQ counter run on the current kernel source: wave instructions
+    x 4 cycles (64 lanes on a 16-wide SIMD), transcendental ones (exp2, rcp)
+    x 8 (half rate, measured on the box), over the chip's 1024 SIMDs at
+    2.4 GHz, next to the measured kernel time."""
     path = os.path.join(ROOT, "profiles", "column_kernel_c2_f32_valu.json")
     if not os.path.exists(path):
         return None
@@ -95,8 +96,10 @@ def valu_from_profile(kernel_hash, col_ms):
         d = json.load(f)
     if d.get("kernel_source_sha256_16") != kernel_hash:
         return None
-    t_us = d["sq_insts_valu_per_launch"] * 4.0 / (1024 * 2.4e9) * 1e6
-    return {"sq_insts_valu_per_launch": d["sq_insts_valu_per_launch"],
+    valu, trans = d["sq_insts_valu_per_launch"], d.get("sq_insts_valu_trans_f32", 0.0)
+    t_us = (valu + trans) * 4.0 / (1024 * 2.4e9) * 1e6
+    return {"sq_insts_valu_per_launch": valu, "sq_insts_valu_trans_f32": trans,
+            "cycles_per_wave_instruction": {"valu": 4, "transcendental": 8},
             "valu_issue_us": t_us, "kernel_us": col_ms * 1e3,
             "issue_frac": t_us / (col_ms * 1e3), "source": "profiles/column_kernel_c2_f32_valu.json"}
 
