@@ -156,12 +156,17 @@ typedef enum {
                               when the call's rows would overflow the last-level
                               cache), 1 = always non-temporal, 2 = always cached.
                               Batches always load cached.  Results do not change. */
-  HR2_OPT_TILE_PAIRS = 5   /* one-set calls whose tiles spill past one round of
+  HR2_OPT_TILE_PAIRS = 5,  /* one-set calls whose tiles spill past one round of
                               resident workgroups: 0 = auto (the first round's
                               workgroups take two tiles each, the tiles left
                               over twice the layer chunks), 1 = off.  The
                               leftover tiles' F+ changes by the rounding of a
                               different chunk split (below 1e-6 relative).      */
+  HR2_OPT_TIMING_KERNELS = 6 /* which kernels a timed call times, a bit mask: 1 the
+                              level kernel, 2 the column kernel (or the whole-
+                              forward-model kernel), 4 the convolution; 1..7,
+                              default 7.  Each timed launch costs a few
+                              microseconds of GPU time.                          */
 } hr2_option;
 hr2_status hr2_ctx_set_option(hr2_ctx *ctx, hr2_option opt, int value);
 

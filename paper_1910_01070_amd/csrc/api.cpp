@@ -278,6 +278,12 @@ extern "C" hr2_status hr2_ctx_set_option(hr2_ctx *ctx, hr2_option opt, int value
         return set_error(HR2_E_INVALID_ARG, "row policy must be 0 (auto), 1 or 2");
       ctx->opt_row_policy = value;
       return HR2_OK;
+    case HR2_OPT_TIMING_KERNELS:
+      if (value < 1 || value > 7)
+        return set_error(HR2_E_INVALID_ARG, "timed kernels: a mask of 1 (levels), 2 (column), "
+                                            "4 (convolution), 1 .. 7");
+      ctx->timing_kernels = value;
+      return HR2_OK;
     case HR2_OPT_TILE_PAIRS:
       if (value < 0 || value > 1)
         return set_error(HR2_E_INVALID_ARG, "tile pairs must be 0 (auto) or 1 (off)");
@@ -1020,7 +1026,8 @@ hr2_status launch_forward(hr2_ctx *ctx, const hr2_tables *t, const hr2_obs *o,
   bool timed = this_call;
   if (this_call)
     for (int k = 0; k < kTimedEvents; ++k) timed = (ev[k] = timing_event(ctx, k)) && timed;
-  auto tev = [&](int k) { return timed ? ev[k] : nullptr; };
+  const int tk = ctx->timing_kernels;
+  auto tev = [&](int k) { return timed && ((tk >> (k / 2)) & 1) ? ev[k] : nullptr; };
   const int64_t base_waves = (int64_t)B * ((w.nu_count + 63) / 64);
   // Small windows in a batch that fills the device on its own: the whole
   // forward model in one launch, one workgroup per set (records and F+ in
@@ -1043,7 +1050,7 @@ hr2_status launch_forward(hr2_ctx *ctx, const hr2_tables *t, const hr2_obs *o,
     a.mlen = o->d_mlen;
     HIP_TRY(launch_set_forward(t->view, cv, a, n_mu, ctx->opt_nu_per_lane, s, tev(2), tev(3)));
     if (timed) {
-      ctx->tmask.push_back(2);   // one kernel: the column interval
+      ctx->tmask.push_back((uint8_t)(tk & 2));   // one kernel: the column interval
       ctx->tev_used += kTimedEvents;
     }
     return HR2_OK;
@@ -1130,7 +1137,7 @@ hr2_status launch_forward(hr2_ctx *ctx, const hr2_tables *t, const hr2_obs *o,
                               bins, s, tev(4), tev(5)));
   if (like) HIP_TRY(launch_lnl_reduce(cs.terms, B, o->n_bins, like->lnl, s));
   if (timed) {
-    ctx->tmask.push_back(7);   // levels, column, convolution
+    ctx->tmask.push_back((uint8_t)tk);   // levels, column, convolution as asked
     ctx->tev_used += kTimedEvents;
   }
   return HR2_OK;
@@ -1410,9 +1417,9 @@ extern "C" hr2_status hr2_ctx_collect_timing(hr2_ctx *ctx, double ms[3], int64_t
   for (size_t c = 0; c < ctx->tmask.size(); ++c) {
     const size_t base = c * kTimedEvents;
     const int mask = ctx->tmask[c];
-    HIP_TRY(hipEventSynchronize(ctx->tev[base + ((mask & 4) ? 5 : 3)]));
     for (int k = 0; k < 3; ++k) {
       if (!(mask & (1 << k))) continue;
+      HIP_TRY(hipEventSynchronize(ctx->tev[base + 2 * k + 1]));
       float t = 0.0f;
       HIP_TRY(hipEventElapsedTime(&t, ctx->tev[base + 2 * k], ctx->tev[base + 2 * k + 1]));
       ms[k] += t;

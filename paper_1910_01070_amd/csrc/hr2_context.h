@@ -44,6 +44,7 @@ struct hr2_ctx {
   int opt_tile_pairs = 0;          // one-set calls: 0 auto, 1 off
   int opt_nu_per_lane = 0;         // per-set launches: 0 auto, 1 or 2 wavenumbers per lane
   int timing_every = 0;            // time every n-th forward call (0 = off)
+  int timing_kernels = 7;          // of those calls: 1 levels, 2 column, 4 convolution
   int64_t timing_calls = 0;
   std::vector<hipEvent_t> tev;     // 6 events per timed call (start, end of 3 kernels)
   std::vector<uint8_t> tmask;      // per timed call: which of the 3 intervals it has

@@ -27,7 +27,8 @@ STATUS_NAMES = {0: "HR2_OK", 1: "HR2_NOT_READY", -1: "HR2_E_INVALID_ARG",
 DTYPES = {"f32": 0, "f16": 1, "bf16": 2, "f64": 3}
 OFFSET_MODES = {"row": 0, "species": 1}
 REQ_PENDING, REQ_RUNNING, REQ_DONE, REQ_ERROR, REQ_CANCELLED = range(5)
-OPT_CHUNKS, OPT_NU_PER_LANE, OPT_TIMING, OPT_SOURCE, OPT_ROW_POLICY, OPT_TILE_PAIRS = range(6)
+(OPT_CHUNKS, OPT_NU_PER_LANE, OPT_TIMING, OPT_SOURCE, OPT_ROW_POLICY, OPT_TILE_PAIRS,
+ OPT_TIMING_KERNELS) = range(7)
 
 _DP = POINTER(c_double)
 

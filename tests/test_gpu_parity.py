@@ -580,10 +580,10 @@ def test_whole_forward_per_set(ctx, dtype):
 
 
 def test_kernel_timing_leaves_results_unchanged(ctx):
-    """HR2_OPT_TIMING brackets every n-th call's kernels with HIP events (the
-    column kernel through its own launch timestamps): the call count, three
-    positive intervals whose column part is the smallest bracket of the
-    kernel alone, and results bit-identical to untimed calls."""
+    """HR2_OPT_TIMING times every n-th call's kernels through HIP events
+    attached to their launches: the call count, three positive intervals, the
+    column kernel alone with HR2_OPT_TIMING_KERNELS = 2, bad masks refused,
+    and results bit-identical to untimed calls."""
     tab = tu.c1_table()
     T = hr2.Tables(ctx, tab, "f32")
     spec = wl.c1_obs(tab)
@@ -603,5 +603,19 @@ def test_kernel_timing_leaves_results_unchanged(ctx):
         assert np.array_equal(b, ref[0]) and np.array_equal(f, ref[1])
     (z0, z1, z2), n0 = ctx.collect_timing()
     assert n0 == 0 and z0 == z1 == z2 == 0.0
+    # the column kernel alone (HR2_OPT_TIMING_KERNELS = 2), then a bad mask
+    ctx.set_option(hr2.OPT_TIMING, 1)
+    ctx.set_option(hr2.OPT_TIMING_KERNELS, 2)
+    outs = [run_forward(ctx, T, obs, col, 3) for _ in range(2)]
+    ctx.set_option(hr2.OPT_TIMING, 0)
+    (c0, c1, c2), n = ctx.collect_timing()
+    assert n == 2 and c0 == 0.0 and c1 > 0 and c2 == 0.0
+    for b, f in outs:
+        assert np.array_equal(b, ref[0]) and np.array_equal(f, ref[1])
+    for bad in (0, 8):
+        with pytest.raises(hr2.HR2Error) as ei:
+            ctx.set_option(hr2.OPT_TIMING_KERNELS, bad)
+        assert ei.value.status == hr2.E_INVALID_ARG
+    ctx.set_option(hr2.OPT_TIMING_KERNELS, 7)
     obs.close()
     T.close()
