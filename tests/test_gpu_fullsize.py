@@ -305,3 +305,34 @@ def test_c2_graph_replay(ctx, c2):
     torch.cuda.synchronize()
     obs.close()
     T.close()
+
+
+def test_c2_noalloc_entry_matches(ctx, c2):
+    """The allocation-free entry point on the C2 one-set call (tile pairs, its
+    records in the library's fixed array) equals the regular entry point bit
+    for bit, twice in a row, the second time on a shorter window."""
+    spec = wl.c2_obs(c2)
+    col = wl.c2_column()
+    T = hr2.Tables(ctx, c2, "f32")
+    p, Tk, x = (_dev(getattr(col, k)[None]) for k in ("p_bar", "T_K", "x"))
+    lg, sc = _dev([col.log_g]), _dev([col.scale])
+    ctx.set_option(hr2.OPT_CHUNKS, 0)
+    short = wl.Window(5000, 140_000, 1)
+    nu_first, dnu = oracle.window_grid(c2, short)
+    short_edges = wl.snapped_edges(c2, short, wl.log_edges(nu_first + 0.05 * (short.count - 1) * dnu,
+                                                           nu_first + 0.95 * (short.count - 1) * dnu,
+                                                           300))
+    for w, edges in ((spec.window, spec.edges_cm), (short, short_edges)):
+        obs = hr2.Obs(ctx, T, w, spec.resolving_power, edges)
+        out = {}
+        for name, fn in (("regular", hr2.forward_batch_dev), ("noalloc", hr2.forward_batch_dev_noalloc)):
+            bins = torch.empty(obs.n_bins, dtype=torch.float32, device="cuda")
+            fplus = torch.empty(w.count, dtype=torch.float32, device="cuda")
+            fn(ctx, T, obs, p, Tk, x, lg, sc, 3, bins, fplus)
+            torch.cuda.synchronize()
+            out[name] = (bins.cpu().numpy(), fplus.cpu().numpy())
+        say(f"  window ({w.begin}, {w.count}): noalloc == regular")
+        assert np.array_equal(out["regular"][0], out["noalloc"][0])
+        assert np.array_equal(out["regular"][1], out["noalloc"][1])
+        obs.close()
+    T.close()
