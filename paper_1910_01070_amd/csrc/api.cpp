@@ -112,6 +112,13 @@ static AngleTable make_angle_table() {
   for (int n = 1; n <= kMaxMu; ++n) {
     double mu[kMaxMu], w[kMaxMu];
     gauss_legendre_01(n, mu, w);
+    // slots past the n nodes: a valid direction (mu = 1) of weight 0, so a
+    // kernel may run them unguarded and add exactly zero to the flux
+    for (int k = n; k < kMaxMu; ++k) {
+      t.mu[n - 1][k] = t.inv_mu[n - 1][k] = 1.0f;
+      t.l2e_mu[n - 1][k] = (float)log2e;
+      t.mu_d[n - 1][k] = t.inv_mu_d[n - 1][k] = 1.0;
+    }
     for (int k = 0; k < n; ++k) {
       t.mu[n - 1][k] = (float)mu[k];
       t.inv_mu[n - 1][k] = (float)(1.0 / mu[k]);

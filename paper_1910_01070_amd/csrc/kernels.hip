@@ -836,6 +836,10 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(
   constexpr bool kF64 = std::is_same<Real, double>::value;
   constexpr int NS = NSS < 0 ? -NSS : NSS;
   constexpr bool kExact = NSS < 0;
+  // small angle tier: every one of the MAXMU slots runs (the angle table
+  // pads a row past its n_mu nodes with mu = 1 and weight 0, so the extra
+  // slots add exactly zero to F), and the loops carry no per-angle guards
+  constexpr bool kAllMu = MAXMU <= kMuTierSmall;
   const Rec *__restrict__ recs = (const Rec *)recs_v;
   const Real *__restrict__ chi_in = (const Real *)chi_in_v;
   Real *__restrict__ out = (Real *)out_v;
@@ -903,7 +907,10 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(
   const double c1nu3_d = kC1 * nu_d * nu_d * nu_d;
   const float nu_hi = (float)nu_d;
   const float nu_lo = (float)(nu_d - (double)nu_hi);
-  const float c1nu3_f = (float)c1nu3_d;
+  // FP32: the sweep carries source and intensities in units of the lane's
+  // Planck prefactor c1 nu^3 (the transfer is linear in them), which
+  // multiplies the flux once at the end: one multiply and one register fewer
+  // per level
 
   // per-species and per-pair base pointers (uniform) and this lane's byte
   // offset in a row: each load is base + (row offset + lane offset)
@@ -920,7 +927,19 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(
   }
   const rsrc_t rc = make_rsrc(cia, 2 * pair_bytes);
   const uint32_t kb = kk * (uint32_t)sizeof(TT);
-  const uint32_t kbc = kk * (uint32_t)sizeof(Real);
+  // the lane's byte offset in a CIA row (Real elements), formed from kb at
+  // each CIA fetch when the two element sizes differ: an opaque shift that
+  // the compiler cannot hoist, so no register holds it across the sweep
+  auto cia_lane_offset = [&](uint32_t kb_) -> uint32_t {
+    if constexpr (sizeof(TT) == sizeof(Real)) {
+      return kb_;
+    } else {
+      static_assert(sizeof(Real) == 2 * sizeof(TT), "FP32 sweep over 16-bit rows");
+      uint32_t r;
+      asm volatile("v_lshlrev_b32 %0, 1, %1" : "=v"(r) : "v"(kb_));
+      return r;
+    }
+  };
   const int S = kExact ? NS : tv.S;
   const bool has_cia = tv.n_cia > 0;
 
@@ -978,7 +997,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(
 #pragma unroll
       for (int k = 0; k < 2; ++k) {
         if (mask & (16 << k)) {
-          const uint32_t off = rr.cia_rowb[k] + kbc;
+          const uint32_t off = rr.cia_rowb[k] + cia_lane_offset(kb);
           cslot[0][k] = buf_load<Real>(rc, off, 0);
           cslot[1][k] = buf_load<Real>(rc, off, (uint32_t)pair_bytes);
         }
@@ -1020,7 +1039,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(
     if constexpr (kF64)
       return planck_d(nu_d, c1nu3_d, r.T);
     else
-      return planck_f(nu_hi, nu_lo, c1nu3_f, r.pl_hi, r.pl_lo);
+      return planck_f(nu_hi, nu_lo, 1.0f, r.pl_hi, r.pl_lo);
   };
 
   // Odd chunks compose their layers' maps from the top down, so that the
@@ -1053,7 +1072,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(
           if constexpr (kF64) {
 #pragma unroll
             for (int k = 0; k < MAXMU; ++k)
-              if (k < nmu) {
+              if (kAllMu || k < nmu) {
                 double e, c;
                 sc_coef_d(dtau, S_prev, Sl, a_mud[k], e, c);
                 I[k] = fma(A[k], c, I[k]);
@@ -1063,7 +1082,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(
             const float D = Sl - S_prev, rD = D * frcp(dtau);
 #pragma unroll
             for (int k = 0; k < MAXMU; ++k)
-              if (k < nmu) {
+              if (kAllMu || k < nmu) {
                 float e, uD;
                 sc_coef_f(dtau, rD, D, a_inv[k], a_l2e[k], a_mu[k], e, uD);
                 I[k] = fmaf(A[k], fmaf(-e, Sl, S_prev) + uD, I[k]);
@@ -1080,7 +1099,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(
             if constexpr (kF64) {
 #pragma unroll
               for (int k = 0; k < MAXMU; ++k)
-                if (k < nmu) {
+                if (kAllMu || k < nmu) {
                   double e, c;
                   if (has_dn && dtau_last > 0.0)
                     sc_para_coef_d(dtau, dtau_last, Sl, S_prev, S_pp, a_mud[k], e, c);
@@ -1095,7 +1114,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(
               const bool para = has_dn && dtau_last > 0.0f;
 #pragma unroll
               for (int k = 0; k < MAXMU; ++k)
-                if (k < nmu) {
+                if (kAllMu || k < nmu) {
                   float e, c;
                   if (para)
                     sc_para_coef_f(dtau, dtau_last, r_u, r_d, r_s, Sl, S_prev, S_pp, a_inv[k],
@@ -1140,12 +1159,12 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(
           if constexpr (kF64) {
 #pragma unroll
             for (int k = 0; k < MAXMU; ++k)
-              if (k < nmu) I[k] = sc_step_d(I[k], dtau, S, S_prev, a_mud[k]);
+              if (kAllMu || k < nmu) I[k] = sc_step_d(I[k], dtau, S, S_prev, a_mud[k]);
           } else {
             const float D = S_prev - S, rD = D * frcp(dtau);
 #pragma unroll
             for (int k = 0; k < MAXMU; ++k)
-              if (k < nmu)
+              if (kAllMu || k < nmu)
                 I[k] = sc_step_f(I[k], dtau, rD, S, S_prev, D, a_inv[k], a_l2e[k], a_mu[k]);
           }
         } else {
@@ -1156,14 +1175,14 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(
             if constexpr (kF64) {
 #pragma unroll
               for (int k = 0; k < MAXMU; ++k)
-                if (k < nmu)
+                if (kAllMu || k < nmu)
                   I[k] = dtau > 0.0 ? sc_para_d(I[k], dtau_last, dtau, S_pp, S_prev, S, a_mud[k])
                                     : sc_step_d(I[k], dtau_last, S_prev, S_pp, a_mud[k]);
             } else {
               const float r_u = frcp(dtau_last), r_d = frcp(dtau), r_s = frcp(dtau_last + dtau);
 #pragma unroll
               for (int k = 0; k < MAXMU; ++k)
-                if (k < nmu)
+                if (kAllMu || k < nmu)
                   I[k] = dtau > 0.0f
                              ? sc_para_f(I[k], dtau_last, dtau, r_u, r_d, r_s, S_pp, S_prev, S,
                                          a_inv[k], a_l2e[k], a_mu[k])
@@ -1186,12 +1205,12 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(
         if constexpr (kF64) {
 #pragma unroll
           for (int k = 0; k < MAXMU; ++k)
-            if (k < nmu) I[k] = sc_step_d(I[k], dtau_last, S_prev, S_pp, a_mud[k]);
+            if (kAllMu || k < nmu) I[k] = sc_step_d(I[k], dtau_last, S_prev, S_pp, a_mud[k]);
         } else {
           const float r_u = frcp(dtau_last);
 #pragma unroll
           for (int k = 0; k < MAXMU; ++k)
-            if (k < nmu)
+            if (kAllMu || k < nmu)
               I[k] = sc_step_weights_f(I[k], dtau_last, r_u, S_prev, S_pp, a_inv[k], a_l2e[k],
                                        a_mu[k]);
         }
@@ -1199,36 +1218,38 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(
     }
   }
 
+  // the lane id again (no register carries it across the sweep)
+  const int lane_e = __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
   Real F = (Real)0;
   if (C == 1) {
 #pragma unroll
     for (int k = 0; k < MAXMU; ++k)
-      if (k < nmu) {
+      if (kAllMu || k < nmu) {
         if constexpr (kF64)
           F += c_ang.cw_d[nmu - 1][k] * I[k];
         else
           F = fmaf(c_ang.cw[nmu - 1][k], I[k], F);
       }
   } else {
-    // layout (from the tile group's base): sh[(c * (MAXMU + 1) + k) * 64 + lane],
+    // layout (from the tile group's base): sh[(c * (MAXMU + 1) + k) * 64 + lane_e],
     // k = MAXMU holds tau
-    sh[(chunk * (MAXMU + 1) + MAXMU) * 64 + lane] = tau;
+    sh[(chunk * (MAXMU + 1) + MAXMU) * 64 + lane_e] = tau;
 #pragma unroll
-    for (int k = 0; k < MAXMU; ++k) sh[(chunk * (MAXMU + 1) + k) * 64 + lane] = I[k];
+    for (int k = 0; k < MAXMU; ++k) sh[(chunk * (MAXMU + 1) + k) * 64 + lane_e] = I[k];
     __syncthreads();
     if (chunk == C - 1) {
 #pragma unroll
       for (int k = 0; k < MAXMU; ++k)
-        if (k < nmu) {
-          Real acc = sh[k * 64 + lane];
+        if (kAllMu || k < nmu) {
+          Real acc = sh[k * 64 + lane_e];
           for (int c = 1; c < C; ++c) {
-            const Real tc = sh[(c * (MAXMU + 1) + MAXMU) * 64 + lane];
+            const Real tc = sh[(c * (MAXMU + 1) + MAXMU) * 64 + lane_e];
             Real tr;
             if constexpr (kF64)
               tr = exp(-tc / a_mud[k]);
             else
               tr = fexp2(-tc * a_l2e[k]);
-            acc = tr * acc + sh[(c * (MAXMU + 1) + k) * 64 + lane];
+            acc = tr * acc + sh[(c * (MAXMU + 1) + k) * 64 + lane_e];
           }
           if constexpr (kF64)
             F += c_ang.cw_d[nmu - 1][k] * acc;
@@ -1237,7 +1258,14 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(
         }
     }
   }
-  if (active && chunk == C - 1) out[d.out_offset + (int64_t)s * d.out_stride + j] = F;
+  // the lane's point again, from uniform values and the lane id
+  const int64_t je = t * 64 + lane_e;
+  if constexpr (!kF64) {
+    const int64_t jje = je < nu_count ? je : nu_count - 1;
+    const double nu_e = tv.nu0 + (double)(d.nu_begin + jje * d.nu_stride) * tv.dnu;
+    F *= (float)(kC1 * nu_e * nu_e * nu_e);
+  }
+  if (je < nu_count && chunk == C - 1) out[d.out_offset + (int64_t)s * d.out_stride + je] = F;
 }
 
 int column_nu_per_wg(int) { return 64; }
@@ -1583,7 +1611,7 @@ __global__ __launch_bounds__(kSetThreads) __attribute__((amdgpu_waves_per_eu(8))
   for (int t = wave; t < tiles; t += n_waves) {
     int64_t j[NU];
     bool active[NU];
-    float nu_hi[NU], nu_lo[NU], c1nu3_f[NU];
+    float nu_hi[NU], nu_lo[NU];
     uint32_t kb[NU], kbc[NU];
 #pragma unroll
     for (int u = 0; u < NU; ++u) {
@@ -1595,7 +1623,6 @@ __global__ __launch_bounds__(kSetThreads) __attribute__((amdgpu_waves_per_eu(8))
       const double nu_d = tv.nu0 + (double)kidx * tv.dnu;
       nu_hi[u] = (float)nu_d;
       nu_lo[u] = (float)(nu_d - (double)nu_hi[u]);
-      c1nu3_f[u] = (float)(kC1 * nu_d * nu_d * nu_d);
       kb[u] = kk * (uint32_t)sizeof(TT);
       kbc[u] = kk * (uint32_t)sizeof(float);
     }
@@ -1675,7 +1702,8 @@ __global__ __launch_bounds__(kSetThreads) __attribute__((amdgpu_waves_per_eu(8))
       }
 #pragma unroll
       for (int u = 0; u < NU; ++u) {
-        const float Sl = planck_f(nu_hi[u], nu_lo[u], c1nu3_f[u], r.pl_hi, r.pl_lo);
+        // in units of c1 nu^3, as in k_column
+        const float Sl = planck_f(nu_hi[u], nu_lo[u], 1.0f, r.pl_hi, r.pl_lo);
         if (l == 0) {
 #pragma unroll
           for (int k = 0; k < MAXMU; ++k) I[u][k] = Sl;
@@ -1700,6 +1728,11 @@ __global__ __launch_bounds__(kSetThreads) __attribute__((amdgpu_waves_per_eu(8))
 #pragma unroll
       for (int k = 0; k < MAXMU; ++k)
         if (k < nmu) F = fmaf(c_ang.cw[nmu - 1][k], I[u][k], F);
+      {
+        const int64_t jj = active[u] ? j[u] : nu_count - 1;
+        const double nu_d = tv.nu0 + (double)(a.nu_begin + jj * a.nu_stride) * tv.dnu;
+        F *= (float)(kC1 * nu_d * nu_d * nu_d);
+      }
       if (active[u]) {
         s_fp[j[u]] = F;
         a.fplus[(int64_t)s * nu_count + j[u]] = F;
