@@ -246,10 +246,10 @@ int column_wave_capacity(const TableView &tv, int max_mu, bool opacity_from_memo
 // levels and windows of at most 4096 points (set_forward_fits), a linear
 // source and a layout with short supports (one wave per bin).  Same
 // arithmetic as the level, column (one chunk) and convolve/bin kernels.
-// nu_per_lane: 0 = automatic (two wavenumbers per lane), 1 or 2;
-// set_forward_nu_per_lane says which the launch uses.
+// nu_per_lane: 0 = automatic (two wavenumbers per lane up to three angles,
+// one above), 1 or 2; set_forward_nu_per_lane says which the launch uses.
 bool set_forward_fits(const TableView &tv, int n_levels, int64_t nu_count);
-int set_forward_nu_per_lane(const TableView &tv, int requested);
+int set_forward_nu_per_lane(const TableView &tv, int requested, int max_mu);
 hipError_t launch_set_forward(const TableView &tv, const ColumnsView &cv, const SetFwdArgs &args,
                               int max_mu, int nu_per_lane, hipStream_t stream,
                               hipEvent_t t_start = nullptr, hipEvent_t t_stop = nullptr);

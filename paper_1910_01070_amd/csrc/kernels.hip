@@ -87,6 +87,22 @@ __device__ __forceinline__ TT buf_load(rsrc_t r, uint32_t off, uint32_t soff) {
   }
 }
 
+// The lane's byte offset in a CIA row (FP32 or FP64 elements, like the
+// sweep) from its byte offset in a table row (TT elements): formed at each
+// CIA fetch when the two element sizes differ, by an opaque shift that the
+// compiler cannot hoist, so that no register holds it across the sweep.
+template <typename TT, typename Real = float>
+__device__ __forceinline__ uint32_t cia_offset_from_row_offset(uint32_t kb) {
+  if constexpr (sizeof(TT) == sizeof(Real)) {
+    return kb;
+  } else {
+    static_assert(sizeof(Real) == 2 * sizeof(TT), "FP32 sweep over 16-bit rows");
+    uint32_t r;
+    asm volatile("v_lshlrev_b32 %0, 1, %1" : "=v"(r) : "v"(kb));
+    return r;
+  }
+}
+
 __device__ __forceinline__ float fexp2(float x) { return __builtin_amdgcn_exp2f(x); }
 __device__ __forceinline__ float frcp(float x) { return __builtin_amdgcn_rcpf(x); }
 
@@ -229,6 +245,16 @@ __device__ const double *theta_tail(const ParamView &pv, const double *th) {
 // 128 threads 7.0-7.3 us; 64 threads 8.3-8.4 us)
 constexpr int kLevelThreads = 128;
 
+// A double that every lane of the wave holds (loaded from one address, or
+// formed from the same LDS values): moved to scalar registers, so that it
+// costs no vector registers while the level items run.
+__device__ __forceinline__ double wave_uniform(double v) {
+  const uint64_t u = __builtin_bit_cast(uint64_t, v);
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)u);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(u >> 32));
+  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
 // The level records of set s, written to recs_set[0 .. L-1] (global or LDS
 // memory): the items of that set that fall to this workgroup, which is
 // workgroup `part` of the blocks_per_set ones sharing the set.  Every thread
@@ -299,6 +325,13 @@ __device__ void level_records(const TableView &tv, const ColumnsView &cv, int s,
     xs += s_x[q];
     mm += s_x[q] * s_m[q];
   }
+  logg = wave_uniform(logg);
+  scale = wave_uniform(scale);
+  tau_c = wave_uniform(tau_c);
+  c_top = wave_uniform(c_top);
+  c_frac = wave_uniform(c_frac);
+  xs = wave_uniform(xs);
+  mm = wave_uniform(mm);
   bad |= !(xs < 1.0) || !isfinite(logg) || !isfinite(scale);
   bad |= !(tau_c >= 0.0) || !isfinite(tau_c);
   if (tau_c > 0.0)
@@ -333,7 +366,12 @@ __device__ void level_records(const TableView &tv, const ColumnsView &cv, int s,
   // disjoint fields of the records.
   const int per_level = S + tv.n_cia;
   const int n_items = L * (2 + per_level);
-  for (int t = part * blockDim.x + threadIdx.x; t < n_items; t += blocks_per_set * blockDim.x) {
+  // every launch gives each item a thread of its own (blocks_per_set
+  // workgroups of blockDim.x threads cover n_items), so a thread runs at most
+  // one item: a branch, not a loop, whose invariant FP64 polynomial constants
+  // the compiler would keep in (and spill from) vector registers
+  const int t = part * blockDim.x + threadIdx.x;
+  if (t < n_items) {
     if (t >= L && t < 2 * L) {
       // the layer above level l: half thickness and cloud optical depth
       const int l = t - L;
@@ -927,19 +965,6 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(
   }
   const rsrc_t rc = make_rsrc(cia, 2 * pair_bytes);
   const uint32_t kb = kk * (uint32_t)sizeof(TT);
-  // the lane's byte offset in a CIA row (Real elements), formed from kb at
-  // each CIA fetch when the two element sizes differ: an opaque shift that
-  // the compiler cannot hoist, so no register holds it across the sweep
-  auto cia_lane_offset = [&](uint32_t kb_) -> uint32_t {
-    if constexpr (sizeof(TT) == sizeof(Real)) {
-      return kb_;
-    } else {
-      static_assert(sizeof(Real) == 2 * sizeof(TT), "FP32 sweep over 16-bit rows");
-      uint32_t r;
-      asm volatile("v_lshlrev_b32 %0, 1, %1" : "=v"(r) : "v"(kb_));
-      return r;
-    }
-  };
   const int S = kExact ? NS : tv.S;
   const bool has_cia = tv.n_cia > 0;
 
@@ -997,7 +1022,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(
 #pragma unroll
       for (int k = 0; k < 2; ++k) {
         if (mask & (16 << k)) {
-          const uint32_t off = rr.cia_rowb[k] + cia_lane_offset(kb);
+          const uint32_t off = rr.cia_rowb[k] + cia_offset_from_row_offset<TT, Real>(kb);
           cslot[0][k] = buf_load<Real>(rc, off, 0);
           cslot[1][k] = buf_load<Real>(rc, off, (uint32_t)pair_bytes);
         }
@@ -1570,6 +1595,8 @@ hipError_t launch_convolve_bin(bool fp64, const ConvSeg *segs_dev, int n_segs,
 // one chunk and of k_convolve_bin's one-wave-per-bin scheme, step for step.
 constexpr int kSetThreads = 1024;
 constexpr int kSetMaxLevels = 64;
+// one thread per level item (one species, up to two CIA pairs)
+static_assert(kSetMaxLevels * (2 + 1 + HR2_MAX_CIA) <= kSetThreads, "level items per thread");
 constexpr int kSetMaxNu = 4096;
 
 // NU wavenumbers per lane (1 or 2): a wave's tile is 64 NU points, lane j
@@ -1583,8 +1610,10 @@ __global__ __launch_bounds__(kSetThreads) __attribute__((amdgpu_waves_per_eu(8))
   constexpr bool kExact = NSS < 0;
   __shared__ Rec s_rec[kSetMaxLevels];
   __shared__ float s_fp[kSetMaxNu];
+  __shared__ float s_scale;   // the set's scale, for the bins (kept out of registers)
   const int s = blockIdx.x;
   const int L = cv.L;
+  if (threadIdx.x == 0) s_scale = (float)cv.scale[s];
   level_records<float>(tv, cv, s, 0, 1, s_rec, a.status, ThetaArgs{});
   __syncthreads();
 
@@ -1609,22 +1638,18 @@ __global__ __launch_bounds__(kSetThreads) __attribute__((amdgpu_waves_per_eu(8))
   }
 
   for (int t = wave; t < tiles; t += n_waves) {
-    int64_t j[NU];
-    bool active[NU];
     float nu_hi[NU], nu_lo[NU];
-    uint32_t kb[NU], kbc[NU];
+    uint32_t kb[NU];
 #pragma unroll
     for (int u = 0; u < NU; ++u) {
-      j[u] = (int64_t)t * (64 * NU) + u * 64 + lane;
-      active[u] = j[u] < nu_count;
-      const int64_t jj = active[u] ? j[u] : nu_count - 1;
+      const int64_t j = (int64_t)t * (64 * NU) + u * 64 + lane;
+      const int64_t jj = j < nu_count ? j : nu_count - 1;
       const int64_t kidx = a.nu_begin + jj * a.nu_stride;
       const uint32_t kk = (uint32_t)kidx;
       const double nu_d = tv.nu0 + (double)kidx * tv.dnu;
       nu_hi[u] = (float)nu_d;
       nu_lo[u] = (float)(nu_d - (double)nu_hi[u]);
       kb[u] = kk * (uint32_t)sizeof(TT);
-      kbc[u] = kk * (uint32_t)sizeof(float);
     }
     float slot[NU][NS][4];
     float cslot[NU][2][2];
@@ -1657,7 +1682,7 @@ __global__ __launch_bounds__(kSetThreads) __attribute__((amdgpu_waves_per_eu(8))
           if (mask & (16 << k)) {
 #pragma unroll
             for (int u = 0; u < NU; ++u) {
-              const uint32_t off = rr.cia_rowb[k] + kbc[u];
+              const uint32_t off = rr.cia_rowb[k] + cia_offset_from_row_offset<TT>(kb[u]);
               cslot[u][0][k] = buf_load<float>(rc, off, 0);
               cslot[u][1][k] = buf_load<float>(rc, off, (uint32_t)pair_bytes);
             }
@@ -1722,20 +1747,24 @@ __global__ __launch_bounds__(kSetThreads) __attribute__((amdgpu_waves_per_eu(8))
       hdz_prev = r.hdz;
       dtc_prev = r.dtc;
     }
+    // the lane's points again, from the tile and the lane id (no register
+    // carries them across the sweep)
+    const int lane_e = __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
 #pragma unroll
     for (int u = 0; u < NU; ++u) {
       float F = 0.0f;
 #pragma unroll
       for (int k = 0; k < MAXMU; ++k)
         if (k < nmu) F = fmaf(c_ang.cw[nmu - 1][k], I[u][k], F);
+      const int64_t j = (int64_t)t * (64 * NU) + u * 64 + lane_e;
       {
-        const int64_t jj = active[u] ? j[u] : nu_count - 1;
+        const int64_t jj = j < nu_count ? j : nu_count - 1;
         const double nu_d = tv.nu0 + (double)(a.nu_begin + jj * a.nu_stride) * tv.dnu;
         F *= (float)(kC1 * nu_d * nu_d * nu_d);
       }
-      if (active[u]) {
-        s_fp[j[u]] = F;
-        a.fplus[(int64_t)s * nu_count + j[u]] = F;
+      if (j < nu_count) {
+        s_fp[j] = F;
+        a.fplus[(int64_t)s * nu_count + j] = F;
       }
     }
   }
@@ -1743,7 +1772,7 @@ __global__ __launch_bounds__(kSetThreads) __attribute__((amdgpu_waves_per_eu(8))
 
   // Eq. 17 and the binning: one wave per bin, as k_convolve_bin's short-
   // support scheme, from the F+ in LDS
-  const float sc = (float)cv.scale[s];
+  const float sc = s_scale;
   for (int jb = wave; jb < a.n_bins; jb += n_waves) {
     float acc = conv_partial<float, 64>(a.K + a.kstart[jb], s_fp + a.mlo[jb], a.mlen[jb], lane);
 #pragma unroll
@@ -1765,7 +1794,12 @@ static bool set_forward_kernel(int S, int nu_per_lane,
   return true;
 }
 
-int set_forward_nu_per_lane(const TableView &, int requested) { return requested == 1 ? 1 : 2; }
+// Automatic: two per lane in the small angle tier; one in the large tier,
+// where two would not fit the registers without spilling.
+int set_forward_nu_per_lane(const TableView &, int requested, int max_mu) {
+  if (requested == 1 || requested == 2) return requested;
+  return max_mu <= kMuTierSmall ? 2 : 1;
+}
 
 bool set_forward_fits(const TableView &tv, int n_levels, int64_t nu_count) {
   return tv.dtype != HR2_TABLE_F64 && tv.S == 1 && n_levels <= kSetMaxLevels &&
@@ -1780,7 +1814,7 @@ hipError_t launch_set_forward(const TableView &tv, const ColumnsView &cv, const 
   void (*fn)(TableView, ColumnsView, SetFwdArgs) = nullptr;
   bool ok;
   const bool small = max_mu <= kMuTierSmall;
-  const int nl = set_forward_nu_per_lane(tv, nu_per_lane);
+  const int nl = set_forward_nu_per_lane(tv, nu_per_lane, max_mu);
   switch (tv.dtype) {
     case HR2_TABLE_F16:
       ok = small ? set_forward_kernel<_Float16, kMuTierSmall>(tv.S, nl, &fn)
