@@ -135,8 +135,9 @@ def main():
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy 5 times (counter scale)")
     ap.add_argument("--workload", default="c2",
-                    choices=["c2", "c3", "c4", "c5", "params", "oracle"],
-                    help="c2 (default): one realistic spectrum per step; c3: 512-set C1 batch "
+                    choices=["c1", "c2", "c3", "c4", "c5", "params", "oracle"],
+                    help="c2 (default): one realistic spectrum per step; c1: one small FP64 "
+                         "spectrum per synchronous call (latency); c3: 512-set C1 batch "
                          "as a HIP graph vs 512 sequential calls; c4: reduced-precision "
                          "batches; c5: Poisson serving trace; params: parameter vectors "
                          "to ln L; oracle: the FP64 oracle timed on the host")
@@ -178,6 +179,8 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"calibrate_copy_bytes_read": n * 4, "bytes_written": n * 4, "repeats": 5}))
         return
+    if args.workload == "c1":
+        return run_c1(args)
     if args.workload == "c3":
         return run_c3(args)
     if args.workload == "c4":
@@ -404,6 +407,55 @@ def _dev_columns(cols):
     return (dev(np.stack([c.p_bar for c in cols])), dev(np.stack([c.T_K for c in cols])),
             dev(np.stack([c.x for c in cols])), dev([c.log_g for c in cols]),
             dev([c.scale for c in cols]))
+
+
+def run_c1(args):
+    """C1: one plain FP64 forward model (1 absorber, 5 x 5 table, 2000 points,
+    20 layers, 3 angles, 50 bins) per call, each call synchronised: the
+    latency of one small spectrum, launches included.  Device columns (the
+    device entry) and host columns (the host entry, the column upload
+    included); bins stay on the device."""
+    import torch
+    import workloads as wl
+    from paper_1910_01070_amd import hr2
+    tab = wl.c1_table()
+    spec = wl.c1_obs(tab)
+    cols = wl.c1_columns()
+    ctx = hr2.Context(0)
+    T = hr2.Tables(ctx, tab, "f64")
+    obs = hr2.Obs(ctx, T, spec.window, spec.resolving_power, spec.edges_cm)
+    res = {}
+    for c in cols[-1:]:
+        p, Tk, x, lg, sc = _dev_columns([c])
+        bins = torch.empty(obs.n_bins, dtype=torch.float64, device="cuda")
+        for name, call in (
+                ("device_entry", lambda: hr2.forward_batch_dev(ctx, T, obs, p, Tk, x, lg, sc, 3, bins)),
+                ("host_entry", lambda: hr2.forward_batch(ctx, T, obs, [c], 3, bins))):
+            for _ in range(args.warmup):
+                call()
+                torch.cuda.synchronize()
+            dt = []
+            for _ in range(args.steps):
+                t0 = time.perf_counter()
+                call()
+                torch.cuda.synchronize()
+                dt.append(time.perf_counter() - t0)
+            dt = np.array(dt)
+            res[name] = {"p50_ms": float(np.median(dt) * 1e3),
+                         "p99_ms": float(np.percentile(dt, 99) * 1e3),
+                         "spectra_per_s": float(1.0 / np.mean(dt))}
+    layer_nu = (cols[-1].n_levels - 1) * spec.window.count
+    print(json.dumps({
+        "metric": METRIC, "value": res["device_entry"]["spectra_per_s"], "unit": "spectra/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": 1e3 / res["device_entry"]["spectra_per_s"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "C1 plain FP64 forward model: 1 absorber, 5 T x 5 log p table, "
+                               "2000 points at 1 cm^-1, 20 layers, 3 angles, R=300, 50 bins; "
+                               "one synchronous call per spectrum"},
+        "layer_nu_points_per_s": layer_nu * res["device_entry"]["spectra_per_s"],
+        "latency": res,
+    }))
 
 
 def run_c3(args):
