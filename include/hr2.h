@@ -144,7 +144,8 @@ typedef enum {
   HR2_OPT_CHUNKS = 0,      /* layer chunks per wavenumber tile: 0 = auto, 1 .. 8 */
   HR2_OPT_NU_PER_LANE = 1, /* wavenumbers per lane of the one-launch-per-set path
                               (one-species tables, windows of at most 4096 points,
-                              batches that fill the device): 0 = auto (2), 1 or 2;
+                              batches that fill the device): 0 = auto (2 up to
+                              three angles, 1 above), 1 or 2;
                               the column kernel keeps 1 (2 costs it half its
                               resident waves)                                        */
   HR2_OPT_TIMING = 2,      /* n > 0: time the kernels of every n-th forward-batch
