@@ -150,14 +150,14 @@ def main():
     ap.add_argument("--rates", default="", help="c5: comma-separated arrival rates to sweep")
     ap.add_argument("--strided-frac", type=float, default=0.5,
                     help="c5: share of requests on 1 cm^-1 windows (stride 10)")
-    ap.add_argument("--no-north-star", action="store_true",
+    ap.add_argument("--no-comparison", action="store_true",
                     help="c2: skip the serving / plain FP32 / batch comparison legs")
-    ap.add_argument("--ns-rate", type=float, default=2000.0,
-                    help="c2 north-star leg: arrival rate of the short serving trace")
-    ap.add_argument("--ns-duration", type=float, default=2.0,
-                    help="c2 north-star leg: length of the short serving trace, s")
-    ap.add_argument("--ns-plain", type=int, default=200,
-                    help="c2 north-star leg: requests timed on the plain FP32 path")
+    ap.add_argument("--cmp-rate", type=float, default=2000.0,
+                    help="c2 comparison leg: arrival rate of the short serving trace")
+    ap.add_argument("--cmp-duration", type=float, default=2.0,
+                    help="c2 comparison leg: length of the short serving trace, s")
+    ap.add_argument("--cmp-plain", type=int, default=200,
+                    help="c2 comparison leg: requests timed on the plain FP32 path")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
@@ -223,14 +223,14 @@ def main():
     default_launch = (args.source == 1 and not args.cloud and args.dtype == "f32" and B == 1
                       and args.n_nu == 150_000)
     default_c2 = default_launch and args.chunks == 0
-    north_star, T16 = None, None
-    if default_c2 and not args.no_north_star:
+    comparison, T16 = None, None
+    if default_c2 and not args.no_comparison:
         # the comparison legs run first: besides their own figures, they leave
         # the device in the steady state of a loaded server (clocks up, the
         # FP32 table recently read by the batch leg) before the headline's
         # warmup and timed steps; from a cold start the column kernel needs
         # 100-200 steps to settle
-        T16, north_star = north_star_legs(ctx, T, tab, args)
+        T16, comparison = comparison_legs(ctx, T, tab, args)
 
     # latency: one step at a time, host launch to device completion
     lat = []
@@ -338,8 +338,8 @@ def main():
         res["binding_roof"] = {"hbm_us": hbm_us, "valu_issue_us": valu_us,
                                "bound": "valu" if valu_us >= hbm_us else "hbm",
                                "kernel_us": col_ms * 1e3, "frac": roof_us / (col_ms * 1e3)}
-    if north_star is not None:
-        res["north_star"] = north_star
+    if comparison is not None:
+        res["comparison"] = comparison
     if not args.no_cpu_baseline:
         log("timing the oracle on the host")
         res["cpu_baseline"] = cpu_baseline(tab, cols[0], spec, n_mu, args.cpu_budget_s)
@@ -788,21 +788,21 @@ def batch_leg(ctx, tables_by_dtype, tab, B, steps):
     return out
 
 
-def north_star_legs(ctx, T32, tab, args):
+def comparison_legs(ctx, T32, tab, args):
     """What the target compares, on the same box as the headline: the
     batched reduced-precision serving path (a short C5 trace on FP16 tables)
     against the plain FP32 path one request at a time on the same requests,
     and 64-set batches with FP32 vs FP16 tables."""
     from paper_1910_01070_amd import hr2
     T16 = hr2.Tables(ctx, tab, "f16")
-    log(f"north star: C5 trace at {args.ns_rate:g} req/s for {args.ns_duration:g} s, FP16 tables")
-    serving, trace = serve_leg(ctx, T16, tab, args.ns_rate, args.ns_duration)
+    log(f"comparison: C5 trace at {args.cmp_rate:g} req/s for {args.cmp_duration:g} s, FP16 tables")
+    serving, trace = serve_leg(ctx, T16, tab, args.cmp_rate, args.cmp_duration)
     log(serving)
-    sample = trace[: min(len(trace), args.ns_plain)]
-    log(f"north star: plain FP32 path on {len(sample)} of the same requests")
+    sample = trace[: min(len(trace), args.cmp_plain)]
+    log(f"comparison: plain FP32 path on {len(sample)} of the same requests")
     plain = plain_leg(ctx, T32, sample)
     log(plain)
-    log("north star: 64-set batches, FP16 vs FP32 tables")
+    log("comparison: 64-set batches, FP16 vs FP32 tables")
     batches = batch_leg(ctx, {"f16": T16, "f32": T32}, tab, 64, 10)
     log(batches)
     return T16, {
