@@ -87,7 +87,8 @@ def valu_from_profile(kernel_hash, col_ms):
     """The column kernel's VALU issue time per launch from a committed
     rocprofv3 SQ counter run on the current kernel source: wave instructions
     x 4 cycles (64 lanes on a 16-wide SIMD), transcendental ones (exp2, rcp)
-    x 8 (half rate, measured on the box), over the chip's 1024 SIMDs at
+    x 8 (half rate, measured by a microbenchmark on an MI355X), over the
+    chip's 1024 SIMDs at
     2.4 GHz, next to the measured kernel time."""
     path = os.path.join(ROOT, "profiles", "column_kernel_c2_f32_valu.json")
     if not os.path.exists(path):
@@ -789,8 +790,8 @@ def batch_leg(ctx, tables_by_dtype, tab, B, steps):
 
 
 def comparison_legs(ctx, T32, tab, args):
-    """What the target compares, on the same box as the headline: the
-    batched reduced-precision serving path (a short C5 trace on FP16 tables)
+    """The comparison, on the same GPU and in the same run as the headline:
+    the batched reduced-precision serving path (a short C5 trace on FP16 tables)
     against the plain FP32 path one request at a time on the same requests,
     and 64-set batches with FP32 vs FP16 tables."""
     from paper_1910_01070_amd import hr2
