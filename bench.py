@@ -88,8 +88,7 @@ def valu_from_profile(kernel_hash, col_ms):
     rocprofv3 SQ counter run on the current kernel source: wave instructions
     x 4 cycles (64 lanes on a 16-wide SIMD), transcendental ones (exp2, rcp)
     x 8 (half rate, measured by a microbenchmark on an MI355X), over the
-    chip's 1024 SIMDs at
-    2.4 GHz, next to the measured kernel time."""
+    chip's 1024 SIMDs at 2.4 GHz, next to the measured kernel time."""
     path = os.path.join(ROOT, "profiles", "column_kernel_c2_f32_valu.json")
     if not os.path.exists(path):
         return None
