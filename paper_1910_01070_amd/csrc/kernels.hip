@@ -988,6 +988,12 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(
     a_l2e[k] = c_ang.l2e_mu[nmu - 1][k];
     a_mud[k] = kF64 ? c_ang.mu_d[nmu - 1][k] : 0.0;
   }
+  // a chunk's first level is the boundary it shares with the chunk that
+  // starts there too (odd chunks sweep down, even ones up): its rows load
+  // with the default policy, so the second wave's read finds them in the
+  // cache; the sweep's own rows follow the launch's policy
+  using kLoopPol = std::integral_constant<int, STREAM ? kCpolStream : 0>;
+  using kFirstPol = std::integral_constant<int, 0>;
   Real tau = (Real)0, chi_prev = (Real)0, S_prev = (Real)0, hdz_prev = (Real)0,
        dtc_prev = (Real)0;
   Real S_pp = (Real)0, dtau_last = (Real)0;   // parabolic: level l-2, layer l-2 -> l-1
@@ -999,7 +1005,8 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(
   // of level l+1 are requested right after level l's opacity is formed (its
   // slot values are no longer needed), so the loads are in flight while
   // level l's Planck function and RT update run.
-  auto fetch = [&](const Rec &rr, int mask) {
+  auto fetch = [&](const Rec &rr, int mask, auto pol) {
+    constexpr int kPol = decltype(pol)::value;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
       if (mask & (1 << k)) {
@@ -1007,7 +1014,6 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(
 #pragma unroll
         for (int q = 0; q < NS; ++q) {
           if (q < S) {
-            constexpr int kPol = STREAM ? kCpolStream : 0;
             const TT v = BIG ? buf_load<TT, kPol>(rs[BIG ? q : 0], off, 0)
                              : buf_load<TT, kPol>(rs[0], off, (uint32_t)(q * sp_bytes));
             if constexpr (kF64)
@@ -1074,7 +1080,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(
   // at l_end, the downwind level of the chunk's top layer.
   const bool down = (chunk & 1) != 0;
   if (down && l0 < nlay) {
-    if constexpr (!FROM_CHI) fetch(rec[l_end], rec[l_end].mask >> 8);
+    if constexpr (!FROM_CHI) fetch(rec[l_end], rec[l_end].mask >> 8, kFirstPol{});
     Real A[MAXMU];   // transmission of the layers composed so far
 #pragma unroll
     for (int k = 0; k < MAXMU; ++k) A[k] = (Real)1;
@@ -1085,7 +1091,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(
         if (l > l0) {
           const Rec &rn = rec[l - 1];
           asm volatile("" ::: "memory");
-          fetch(rn, rn.mask >> 16);
+          fetch(rn, rn.mask >> 16, kLoopPol{});
         }
       }
       const Real Sl = source(r);
@@ -1159,7 +1165,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(
       S_prev = Sl;
     }
   } else if (l0 < nlay) {
-    if constexpr (!FROM_CHI) fetch(rec[l0], rec[l0].mask >> 8);
+    if constexpr (!FROM_CHI) fetch(rec[l0], rec[l0].mask >> 8, kFirstPol{});
     for (int l = l0; l <= l_end; ++l) {
       const Rec r = rec[l];
       const Real chi = opacity(r, l);
@@ -1169,7 +1175,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(
           // keeps this fetch here, after the opacity, instead of being merged
           // with the chunk's first fetch at the top of the loop
           asm volatile("" ::: "memory");
-          fetch(rn, rn.mask);
+          fetch(rn, rn.mask, kLoopPol{});
         }
       }
       const Real S = source(r);
