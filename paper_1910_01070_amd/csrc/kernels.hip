@@ -1084,14 +1084,17 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(
     Real A[MAXMU];   // transmission of the layers composed so far
 #pragma unroll
     for (int k = 0; k < MAXMU; ++k) A[k] = (Real)1;
-    for (int l = l_end; l >= l0; --l) {
+    // the last two levels run in a loop of their own, whose prefetch (the
+    // chunk's last level, a boundary the neighbouring chunk reaches at the
+    // end of its sweep too) loads with the default policy
+    auto down_level = [&](int l, auto pol) {
       const Rec r = rec[l];
       const Real chi = opacity(r, l);
       if constexpr (!FROM_CHI) {
         if (l > l0) {
           const Rec &rn = rec[l - 1];
           asm volatile("" ::: "memory");
-          fetch(rn, rn.mask >> 16, kLoopPol{});
+          fetch(rn, rn.mask >> 16, pol);
         }
       }
       const Real Sl = source(r);
@@ -1163,10 +1166,13 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(
       }
       chi_prev = chi;
       S_prev = Sl;
-    }
+    };
+    int l = l_end;
+    for (; l - 1 > l0; --l) down_level(l, kLoopPol{});
+    for (; l >= l0; --l) down_level(l, kFirstPol{});
   } else if (l0 < nlay) {
     if constexpr (!FROM_CHI) fetch(rec[l0], rec[l0].mask >> 8, kFirstPol{});
-    for (int l = l0; l <= l_end; ++l) {
+    auto up_level = [&](int l, auto pol) {
       const Rec r = rec[l];
       const Real chi = opacity(r, l);
       if constexpr (!FROM_CHI) {
@@ -1175,7 +1181,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(
           // keeps this fetch here, after the opacity, instead of being merged
           // with the chunk's first fetch at the top of the loop
           asm volatile("" ::: "memory");
-          fetch(rn, rn.mask, kLoopPol{});
+          fetch(rn, rn.mask, pol);
         }
       }
       const Real S = source(r);
@@ -1229,7 +1235,10 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(
       S_prev = S;
       hdz_prev = r.hdz;
       dtc_prev = r.dtc;
-    }
+    };
+    int l = l0;
+    for (; l + 1 < l_end; ++l) up_level(l, kLoopPol{});
+    for (; l <= l_end; ++l) up_level(l, kFirstPol{});
     if constexpr (PARA) {
       // the topmost chunk's last step has no downwind level: linear
       if (l_end == l1 && l1 > l0) {
