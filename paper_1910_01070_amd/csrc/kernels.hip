@@ -991,9 +991,14 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(
   // a chunk's first level is the boundary it shares with the chunk that
   // starts there too (odd chunks sweep down, even ones up): its rows load
   // with the default policy, so the second wave's read finds them in the
-  // cache; the sweep's own rows follow the launch's policy
+  // cache.  So do the rows of the sweep's last kCachedTail levels: the
+  // chunk that ends at the same boundary from the other side reaches rows
+  // of the same (T, p) grid points at about the same time.  The levels
+  // before follow the launch's policy (non-temporal for one-set launches
+  // whose rows overflow the cache); caching every level was slower.
   using kLoopPol = std::integral_constant<int, STREAM ? kCpolStream : 0>;
   using kFirstPol = std::integral_constant<int, 0>;
+  constexpr int kCachedTail = 16;
   Real tau = (Real)0, chi_prev = (Real)0, S_prev = (Real)0, hdz_prev = (Real)0,
        dtc_prev = (Real)0;
   Real S_pp = (Real)0, dtau_last = (Real)0;   // parabolic: level l-2, layer l-2 -> l-1
@@ -1084,9 +1089,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(
     Real A[MAXMU];   // transmission of the layers composed so far
 #pragma unroll
     for (int k = 0; k < MAXMU; ++k) A[k] = (Real)1;
-    // the last two levels run in a loop of their own, whose prefetch (the
-    // chunk's last level, a boundary the neighbouring chunk reaches at the
-    // end of its sweep too) loads with the default policy
+    // the sweep's cached tail runs in a loop of its own
     auto down_level = [&](int l, auto pol) {
       const Rec r = rec[l];
       const Real chi = opacity(r, l);
@@ -1168,7 +1171,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(
       S_prev = Sl;
     };
     int l = l_end;
-    for (; l - 1 > l0; --l) down_level(l, kLoopPol{});
+    for (; l >= l0 + kCachedTail; --l) down_level(l, kLoopPol{});
     for (; l >= l0; --l) down_level(l, kFirstPol{});
   } else if (l0 < nlay) {
     if constexpr (!FROM_CHI) fetch(rec[l0], rec[l0].mask >> 8, kFirstPol{});
@@ -1237,7 +1240,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(
       dtc_prev = r.dtc;
     };
     int l = l0;
-    for (; l + 1 < l_end; ++l) up_level(l, kLoopPol{});
+    for (; l + kCachedTail <= l_end; ++l) up_level(l, kLoopPol{});
     for (; l <= l_end; ++l) up_level(l, kFirstPol{});
     if constexpr (PARA) {
       // the topmost chunk's last step has no downwind level: linear
