@@ -995,7 +995,10 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(
   // chunk that ends at the same boundary from the other side reaches rows
   // of the same (T, p) grid points at about the same time.  The levels
   // before follow the launch's policy (non-temporal for one-set launches
-  // whose rows overflow the cache); caching every level was slower.
+  // whose rows overflow the cache); caching every level was slower.  Only
+  // such launches split the sweep in two loops: where both policies are the
+  // default one the split only cost time (the compiler laid out the second
+  // loop's copy worse, 2-byte rows lost 20-30 %).
   using kLoopPol = std::integral_constant<int, STREAM ? kCpolStream : 0>;
   using kFirstPol = std::integral_constant<int, 0>;
   constexpr int kCachedTail = 16;
@@ -1171,7 +1174,8 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(
       S_prev = Sl;
     };
     int l = l_end;
-    for (; l >= l0 + kCachedTail; --l) down_level(l, kLoopPol{});
+    if constexpr (STREAM)
+      for (; l >= l0 + kCachedTail; --l) down_level(l, kLoopPol{});
     for (; l >= l0; --l) down_level(l, kFirstPol{});
   } else if (l0 < nlay) {
     if constexpr (!FROM_CHI) fetch(rec[l0], rec[l0].mask >> 8, kFirstPol{});
@@ -1240,7 +1244,8 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(
       dtc_prev = r.dtc;
     };
     int l = l0;
-    for (; l + kCachedTail <= l_end; ++l) up_level(l, kLoopPol{});
+    if constexpr (STREAM)
+      for (; l + kCachedTail <= l_end; ++l) up_level(l, kLoopPol{});
     for (; l <= l_end; ++l) up_level(l, kFirstPol{});
     if constexpr (PARA) {
       // the topmost chunk's last step has no downwind level: linear
