@@ -160,7 +160,7 @@ def main():
                     help="c2 comparison leg: requests timed on the plain FP32 path")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
+        print(json.dumps({"error": "this benchmark runs on one GPU; --gpus must be 1"}))
         sys.exit(2)
     if args.workload == "oracle":
         return run_oracle_timing(args)   # host only

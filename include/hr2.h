@@ -89,7 +89,7 @@ typedef enum {
   HR2_E_NO_MEMORY = -3,     /* device or host allocation failed; request > budget     */
   HR2_E_DEVICE = -4,        /* a HIP call failed                                       */
   HR2_E_NOT_FOUND = -5,     /* unknown or already consumed ticket                      */
-  HR2_E_UNSUPPORTED = -6,   /* valid request this build does not implement            */
+  HR2_E_UNSUPPORTED = -6,   /* valid request the library does not implement          */
   HR2_E_CANCELLED = -7      /* request cancelled by hr2_serve_destroy                  */
 } hr2_status;
 
